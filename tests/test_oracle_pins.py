@@ -1,0 +1,451 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by
+mathematics, independent of the oracle's own code: closed forms, hand-computed
+values, an independently written energy, invariances, exactness on grid
+nodes, agreement of two formulations, brute force on small inputs."""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize_scalar
+
+from oracle import metrics as om
+from oracle import tfdp as ot
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def path_csr(n):
+    rows, cols = [], []
+    for i in range(n):
+        for j in (i - 1, i + 1):
+            if 0 <= j < n:
+                rows.append(i)
+                cols.append(j)
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    return rp, np.array(cols, dtype=np.int32)
+
+
+def csr_of(n, edges):
+    adj = [[] for _ in range(n)]
+    for u, v in edges:
+        adj[u].append(v)
+        adj[v].append(u)
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(a) for a in adj])
+    ci = np.array([v for a in adj for v in sorted(a)], dtype=np.int32)
+    return rp, ci
+
+
+# --------------------------------------------------------------- t-force (Sec. 3.2)
+
+@pytest.mark.parametrize("phi", [1.5, 2.0, 3.0, 8.0])
+def test_tforce_peak_closed_form(phi):
+    # d/dd [d (1+d^2)^-phi] = (1+d^2)^(-phi-1) (1 + d^2 - 2 phi d^2) = 0  =>  d* = 1/sqrt(2 phi - 1)
+    d = np.linspace(1e-4, 3.0, 300001)
+    f = ot.t_force(d, phi)
+    dstar = 1.0 / math.sqrt(2 * phi - 1)
+    assert abs(d[np.argmax(f)] - dstar) < 2e-5
+    assert f.max() < 1.0  # the maximum stays below 1 (Sec. 3.2)
+
+
+def test_tforce_peak_value_gamma2():
+    # f(1/sqrt(3)) = (1/sqrt 3)(3/4)^2 = 9/(16 sqrt 3) = 0.3247595...
+    assert abs(float(ot.t_force(1 / math.sqrt(3), 2.0)) - 9 / (16 * math.sqrt(3))) < 1e-15
+    assert abs(9 / (16 * math.sqrt(3)) - 0.324760) < 1e-6
+
+
+@pytest.mark.parametrize("phi", [1.0, 2.0, 4.0])
+def test_tforce_requirements_r1_r3(phi):
+    # R3: f ~ d as d -> 0; R2: f ~ d^(1 - 2 phi) as d -> inf; R1: bounded, positive
+    small = np.array([1e-6, 1e-7])
+    assert np.allclose(ot.t_force(small, phi) / small, 1.0, rtol=1e-10)
+    big = np.array([1e6, 2e6])
+    slope = math.log(ot.t_force(big[1], phi) / ot.t_force(big[0], phi)) / math.log(2.0)
+    assert abs(slope - (1 - 2 * phi)) < 1e-6
+    d = np.linspace(1e-3, 100, 10001)
+    f = ot.t_force(d, phi)
+    assert np.all(f > 0) and f.max() <= 1.0
+
+
+def test_general_tforce_is_negative_derivative():
+    # Eq.3 is minus the derivative of (1 + tau d^2)^-phi; with tau = 1 it is 2 (phi) * Eq.4 at exponent phi+1
+    tau, phi = 0.7, 1.3
+    d = np.linspace(0.1, 5, 50)
+    e = lambda x: (1 + tau * x * x) ** (-phi)
+    h = 1e-6
+    fd = -(e(d + h) - e(d - h)) / (2 * h)
+    assert np.allclose(ot.t_force_general(d, tau, phi), fd, rtol=1e-7)
+    assert np.allclose(ot.t_force_general(d, 1.0, 1.0), 2 * ot.t_force(d, 2.0), rtol=1e-14)
+
+
+def test_contact_ratio_limit_eq9():
+    # lim_{d->0} F^a / F^r = alpha (1 + beta)  (Eq.8 -> Eq.9)
+    a, b, g = 0.1, 8.0, 2.0
+    d = 1e-7
+    ratio = a * ot.attractive_magnitude(d, b) / ot.repulsive_magnitude(d, g)
+    assert abs(ratio - a * (1 + b)) < 1e-9
+
+
+def test_pair_equilibrium_closed_form():
+    # two connected nodes, defaults: (1+d^2)^-2 = 0.1 (1 + 8/(1+d^2))
+    # with u = 1+d^2: 0.1 u^2 + 0.8 u - 1 = 0  =>  u = 2 (-0.4 + sqrt(0.26)) / 0.2 ... d*^2 = sqrt(26) - 5
+    dstar = math.sqrt(math.sqrt(26.0) - 5.0)
+    assert abs(dstar - 0.3146737) < 1e-7
+    rp, ci = csr_of(2, [(0, 1)])
+    p = ot.Params(k_mode=0)
+    pos = np.array([[0.0, 0.0], [dstar, 0.0]])
+    _, _, disp = ot.forces(pos, rp, ci, p, 0)
+    assert np.abs(disp).max() < 1e-14
+    # slightly stretched -> net attraction; compressed -> net repulsion
+    _, _, dl = ot.forces(np.array([[0.0, 0.0], [dstar * 1.1, 0.0]]), rp, ci, p, 0)
+    _, _, ds = ot.forces(np.array([[0.0, 0.0], [dstar * 0.9, 0.0]]), rp, ci, p, 0)
+    assert dl[0, 0] > 0 and ds[0, 0] < 0
+
+
+def test_pair_layout_converges_to_equilibrium():
+    dstar = math.sqrt(math.sqrt(26.0) - 5.0)
+    rp, ci = csr_of(2, [(0, 1)])
+    p = ot.Params(k_mode=0, total_iters=200, t0=1.0)
+    x = ot.layout(np.array([[0.0, 0.0], [1.5, 0.7]]), rp, ci, p)
+    assert abs(np.linalg.norm(x[0] - x[1]) - dstar) < 1e-6
+
+
+# --------------------------------------------------------------- exact sums
+
+def test_three_points_hand_computed():
+    rows = np.loadtxt(os.path.join(GOLDEN, "three_points.txt"))
+    pos = rows[:, 1:3]
+    rp, ci = csr_of(3, [(0, 1), (0, 2)])
+    fr = ot.repulsion_exact(pos, 2.0)
+    fa = ot.attraction(pos, rp, ci, 0.1, 8.0)
+    assert np.allclose(fr, rows[:, 3:5], atol=1e-15, rtol=0)
+    assert np.allclose(fa, rows[:, 5:7], atol=1e-15, rtol=0)
+    # sampled-row variants give the same numbers
+    assert np.allclose(ot.repulsion_exact(pos, 2.0, rows=[2, 0]), rows[[2, 0], 3:5], atol=1e-15)
+    assert np.allclose(ot.attraction(pos, rp, ci, 0.1, 8.0, rows=[1, 2]), rows[[1, 2], 5:7], atol=1e-15)
+
+
+def energy(x, edges, alpha, beta, gamma):
+    """Potential whose negative gradient is the t-FDP displacement:
+    sum_{i<j} (1+d^2)^(1-gamma) / (2 (gamma-1)) + alpha sum_edges [d^2/2 + beta/2 ln(1+d^2)]."""
+    n = x.shape[0]
+    e = 0.0
+    for i in range(n):
+        for j in range(i + 1, n):
+            d2 = float(((x[i] - x[j]) ** 2).sum())
+            e += (1 + d2) ** (1 - gamma) / (2 * (gamma - 1))
+    for u, v in edges:
+        d2 = float(((x[u] - x[v]) ** 2).sum())
+        e += alpha * (d2 / 2 + beta / 2 * math.log1p(d2))
+    return e
+
+
+@pytest.mark.parametrize("gamma", [2.0, 1.5, 3.7])
+def test_forces_are_minus_energy_gradient(gamma):
+    rng = np.random.default_rng(5)
+    n = 7
+    x = rng.normal(size=(n, 2)) * 1.3
+    edges = [(0, 1), (1, 2), (2, 3), (0, 4), (4, 5), (5, 6), (6, 1)]
+    rp, ci = csr_of(n, edges)
+    p = ot.Params(alpha=0.13, beta=5.0, gamma=gamma)
+    _, _, disp = ot.forces(x, rp, ci, p, 0)
+    h = 1e-6
+    grad = np.zeros_like(x)
+    for i in range(n):
+        for c in range(2):
+            xp = x.copy()
+            xm = x.copy()
+            xp[i, c] += h
+            xm[i, c] -= h
+            grad[i, c] = (energy(xp, edges, 0.13, 5.0, gamma) - energy(xm, edges, 0.13, 5.0, gamma)) / (2 * h)
+    assert np.allclose(disp, -grad, atol=1e-7, rtol=1e-6)
+
+
+def test_newton_third_law_exact():
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-3, 3, size=(300, 2))
+    fr = ot.repulsion_exact(x, 2.0)
+    rp, ci = csr_of(300, [(i, (7 * i + 3) % 300) for i in range(300) if (7 * i + 3) % 300 != i])
+    fa = ot.attraction(x, rp, ci, 0.1, 8.0)
+    assert np.abs(fr.sum(0)).max() < 1e-12 * np.abs(fr).max() * 300
+    assert np.abs(fa.sum(0)).max() < 1e-12 * np.abs(fa).max() * 300
+
+
+def test_single_node_and_coincident_nodes():
+    assert np.all(ot.repulsion_exact(np.array([[0.3, -0.2]]), 2.0) == 0.0)
+    assert np.all(ot.repulsion_exact(np.array([[0.3, -0.2], [0.3, -0.2]]), 2.0) == 0.0)
+    f = ot.repulsion_ibfft_stable(np.array([[0.3, -0.2]]), 2.0, 8, 2)
+    assert np.abs(f).max() < 1e-15
+
+
+# --------------------------------------------------------------- interpolation pieces
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_lagrange_partition_reproduction_delta(k):
+    t = np.linspace(0, 1, 101)
+    w = ot.lagrange_weights(t, k)
+    assert np.allclose(w.sum(-1), 1.0, atol=1e-14)
+    tau = ot.node_offsets(k)
+    for deg in range(k):
+        assert np.allclose((w * tau ** deg).sum(-1), t ** deg, atol=1e-13)
+    assert np.allclose(ot.lagrange_weights(tau, k), np.eye(k), atol=1e-15)
+
+
+def test_lagrange_explicit_k3():
+    # closed forms for k = 3, nodes 1/6, 1/2, 5/6
+    t = np.linspace(0, 1, 11)
+    w = ot.lagrange_weights(t, 3)
+    assert np.allclose(w[:, 0], 4.5 * (t - 0.5) * (t - 5 / 6))
+    assert np.allclose(w[:, 1], -9 * (t - 1 / 6) * (t - 5 / 6))
+    assert np.allclose(w[:, 2], 4.5 * (t - 1 / 6) * (t - 0.5))
+
+
+def test_box_and_binning():
+    rng = np.random.default_rng(2)
+    x = np.stack([rng.uniform(-3, 5, 500), rng.uniform(10, 11, 500)], 1)
+    lo_x, lo_y, w = ot.square_box(x)
+    assert w == pytest.approx(x[:, 0].max() - x[:, 0].min())
+    assert lo_x == pytest.approx(x[:, 0].min())
+    assert lo_y + w / 2 == pytest.approx((x[:, 1].min() + x[:, 1].max()) / 2)
+    c, t, h = ot.bin_points(x, (lo_x, lo_y, w), 16)
+    assert c.min() >= 0 and c.max() <= 15 and t.min() >= 0 and t.max() <= 1
+    assert np.allclose(lo_x + (c[:, 0] + t[:, 0]) * h, x[:, 0])
+    assert ot.square_box(np.ones((4, 2)))[2] == 1.0
+
+
+def test_spread_gather_adjoint():
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, (200, 2))
+    for k in (1, 2, 3):
+        it = ot.Interp(x, 8, k)
+        v = rng.normal(size=200)
+        phi = rng.normal(size=(1, it.m, it.m))
+        lhs = float((it.spread([v])[0] * phi[0]).sum())
+        rhs = float((v * it.gather(phi, lambda g, dx, dy: g[0])).sum())
+        assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + 1)
+
+
+@pytest.mark.parametrize("m", [5, 16, 24])
+def test_fft_convolution_equals_direct_sum(m):
+    rng = np.random.default_rng(m)
+    q = rng.normal(size=(3, m, m))
+    k, hx, hy = ot.kernel_tables(m, 0.37, 2.0)
+    for tab in (k, hx, hy):
+        a = ot.convolve_fft(q, tab)
+        b = ot.convolve_direct(q, tab)
+        assert np.abs(a - b).max() < 1e-12 * np.abs(b).max()
+    # a longer (non power of two) circulant gives the same linear convolution
+    assert np.allclose(ot.convolve_fft(q, hx, length=2 * m - 1), ot.convolve_direct(q, hx), atol=1e-12)
+
+
+def test_direct_sum_literal_loop_tiny():
+    # an explicit quadruple loop over grid nodes on a 3x3 grid, written with
+    # node coordinates rather than table offsets
+    m, s, g = 3, 0.5, 2.0
+    rng = np.random.default_rng(0)
+    q = rng.normal(size=(1, m, m))
+    k, hx, _ = ot.kernel_tables(m, s, g)
+    ref_k = np.zeros((m, m))
+    ref_h = np.zeros((m, m))
+    for gy in range(m):
+        for gx in range(m):
+            for py in range(m):
+                for px in range(m):
+                    dx, dy = (gx - px) * s, (gy - py) * s
+                    kk = (1 + dx * dx + dy * dy) ** -g
+                    ref_k[gy, gx] += kk * q[0, py, px]
+                    ref_h[gy, gx] += kk * dx * q[0, py, px]
+    assert np.allclose(ot.convolve_direct(q, k)[0], ref_k, atol=1e-14)
+    assert np.allclose(ot.convolve_direct(q, hx)[0], ref_h, atol=1e-14)
+
+
+def test_kernel_spectrum_real():
+    m = 16
+    k, hx, _ = ot.kernel_tables(m, 0.2, 2.0)
+    L = ot.fft_length(m)
+    emb = np.zeros((L, L))
+    off = np.arange(-(m - 1), m)
+    emb[np.ix_(off % L, off % L)] = k
+    spec = np.fft.fft2(emb)
+    assert np.abs(spec.imag).max() < 1e-12 * np.abs(spec.real).max()
+    emb[np.ix_(off % L, off % L)] = hx
+    spec = np.fft.fft2(emb)
+    assert np.abs(spec.real).max() < 1e-12 * np.abs(spec.imag).max()
+
+
+# --------------------------------------------------------------- interpolated repulsion
+
+def on_grid_points(n_int, k, lo, w, count, rng):
+    m = n_int * k
+    s = w / m
+    g = rng.choice(m * m, size=min(count, m * m), replace=False)
+    gx, gy = g % m, g // m
+    return np.stack([lo[0] + (gx + 0.5) * s, lo[1] + (gy + 0.5) * s], 1)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("form", ["paper", "stable"])
+def test_on_grid_points_are_exact(k, form):
+    # points sitting exactly on interpolation nodes: interpolation is exact,
+    # so the scheme must return the exact all-pairs repulsion
+    rng = np.random.default_rng(10 + k)
+    n_int = 6
+    lo, w = (-1.25, 0.5), 3.0
+    x = on_grid_points(n_int, k, lo, w, 60, rng)
+    fn = ot.repulsion_ibfft_paper if form == "paper" else ot.repulsion_ibfft_stable
+    for gamma in (2.0, 1.3):
+        f = fn(x, gamma, n_int, k, box=(lo[0], lo[1], w))
+        ref = ot.repulsion_exact(x, gamma)
+        assert rel_l2(f, ref) < 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_paper_form_equals_stable_form(k):
+    rng = np.random.default_rng(20 + k)
+    x = rng.uniform(-4, 7, (700, 2))
+    a = ot.repulsion_ibfft_paper(x, 2.0, 16, k)
+    b = ot.repulsion_ibfft_stable(x, 2.0, 16, k)
+    assert rel_l2(a, b) < 1e-12
+    # direct-sum grid interaction gives the same result as the FFT one
+    c = ot.repulsion_ibfft_stable(x, 2.0, 8, k, direct=True)
+    d = ot.repulsion_ibfft_stable(x, 2.0, 8, k)
+    assert rel_l2(c, d) < 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_interpolated_zero_net_force(k):
+    rng = np.random.default_rng(30 + k)
+    x = rng.normal(size=(800, 2)) * 3
+    f = ot.repulsion_ibfft_stable(x, 2.0, 32, k)
+    assert np.abs(f.sum(0)).max() < 1e-10 * np.abs(f).sum()
+
+
+def test_interpolated_invariances():
+    rng = np.random.default_rng(40)
+    x = rng.uniform(-2, 2, (500, 2))
+    for k in (1, 2, 3):
+        f = ot.repulsion_ibfft_stable(x, 2.0, 16, k)
+        # translation by a dyadic vector keeps every binning operation exact
+        ft = ot.repulsion_ibfft_stable(x + np.array([0.5, -0.25]), 2.0, 16, k)
+        assert rel_l2(ft, f) < 1e-9
+        # 90 degree rotation (x, y) -> (-y, x) rotates the forces
+        xr = np.stack([-x[:, 1], x[:, 0]], 1)
+        fr = ot.repulsion_ibfft_stable(xr, 2.0, 16, k)
+        assert rel_l2(fr, np.stack([-f[:, 1], f[:, 0]], 1)) < 1e-9
+        # reflection x -> -x
+        xm = np.stack([-x[:, 0], x[:, 1]], 1)
+        fm = ot.repulsion_ibfft_stable(xm, 2.0, 16, k)
+        assert rel_l2(fm, np.stack([-f[:, 0], f[:, 1]], 1)) < 1e-9
+
+
+def test_exact_invariances():
+    rng = np.random.default_rng(41)
+    x = rng.uniform(-2, 2, (200, 2))
+    f = ot.repulsion_exact(x, 2.0)
+    assert rel_l2(ot.repulsion_exact(x + 3.0, 2.0), f) < 1e-13
+    xr = np.stack([-x[:, 1], x[:, 0]], 1)
+    assert rel_l2(ot.repulsion_exact(xr, 2.0), np.stack([-f[:, 1], f[:, 0]], 1)) < 1e-13
+
+
+def test_interpolation_error_falls_with_spacing():
+    # error against the exact sum decreases as h/k shrinks; k = 3 at a fine
+    # grid is within 1e-3
+    rng = np.random.default_rng(50)
+    x = rng.uniform(-1, 1, (400, 2))
+    ref = ot.repulsion_exact(x, 2.0)
+    errs = {k: [rel_l2(ot.repulsion_ibfft_stable(x, 2.0, n, k), ref) for n in (8, 16, 32)]
+            for k in (1, 2, 3)}
+    for k in (1, 2, 3):
+        assert errs[k][0] > errs[k][1] > errs[k][2]
+    assert errs[3][2] < 1e-4 and errs[2][2] < 1e-3 and errs[1][2] < 1e-1
+    for n_i in range(3):
+        assert errs[1][n_i] > errs[2][n_i] > errs[3][n_i]
+
+
+# --------------------------------------------------------------- schedule and loop
+
+def test_k_schedule():
+    def counts(total):
+        ks = [ot.k_for_iteration(t, total) for t in range(total)]
+        return [ks.count(1), ks.count(2), ks.count(3)]
+    assert counts(300) == [270, 15, 15]
+    assert counts(500) == [450, 25, 25]
+    assert counts(200) == [180, 10, 10]
+    assert counts(50) == [45, 2, 3]
+    assert ot.k_for_iteration(269, 300) == 1 and ot.k_for_iteration(270, 300) == 2
+    assert ot.k_for_iteration(285, 300) == 3
+
+
+def test_capped_move():
+    x = np.zeros((3, 2))
+    d = np.array([[3.0, 4.0], [0.3, 0.4], [0.0, 0.0]])
+    y = ot.capped_move(x, d, 1.0)
+    assert np.allclose(y, [[0.6, 0.8], [0.3, 0.4], [0.0, 0.0]])
+    assert ot.step_cap(0, 100, 5.0) == 5.0 and ot.step_cap(50, 100, 5.0) == 2.5
+    assert ot.default_t0(100) == 1.0 and ot.default_t0(10 ** 6) == 100.0
+
+
+def test_energy_decreases_with_small_steps():
+    rng = np.random.default_rng(60)
+    n = 12
+    edges = [(i, (i + 1) % n) for i in range(n)] + [(0, 6)]
+    rp, ci = csr_of(n, edges)
+    x = rng.uniform(-1, 1, (n, 2))
+    p = ot.Params(k_mode=0, total_iters=40, t0=0.02)
+    e0 = energy(x, edges, p.alpha, p.beta, p.gamma)
+    xs = ot.layout(x, rp, ci, p, iters=20)
+    assert energy(xs, edges, p.alpha, p.beta, p.gamma) < e0
+
+
+# --------------------------------------------------------------- metrics (Sec. 4)
+
+def test_metrics_path_on_a_line():
+    n = 12
+    rp, ci = path_csr(n)
+    x = np.stack([np.arange(n) * 2.5, np.zeros(n)], 1)
+    assert om.stress_error(x, rp, ci) < 1e-25
+    assert om.neighborhood_preservation(x, rp, ci, 1) == 1.0
+    assert om.neighborhood_preservation(x, rp, ci, 2) == 1.0
+
+
+def test_optimal_scale_is_minimiser():
+    rng = np.random.default_rng(70)
+    lay = rng.uniform(0.5, 3, 50)
+    gd = rng.integers(1, 6, 50).astype(float)
+    s = om.optimal_scale(lay, gd)
+    res = minimize_scalar(lambda v: (((v * lay - gd) / gd) ** 2).sum(), bounds=(0.01, 10), method="bounded",
+                          options={"xatol": 1e-12})
+    assert abs(s - res.x) < 1e-6
+
+
+def test_stress_skips_disconnected_pairs():
+    # two separate paths of 3 nodes, laid out exactly, far apart
+    rp, ci = csr_of(6, [(0, 1), (1, 2), (3, 4), (4, 5)])
+    x = np.array([[0, 0], [1, 0], [2, 0], [100, 50], [101, 50], [102, 50]], dtype=float)
+    assert om.stress_error(x, rp, ci) < 1e-25
+    # SE with a known distortion: squeeze one path by half -> closed form via optimal scale
+    x2 = x.copy()
+    x2[3:, 0] = 100 + (x2[3:, 0] - 100) * 0.5
+    se = om.stress_error(x2, rp, ci)
+    lay = np.array([1, 2, 1, 0.5, 1, 0.5])
+    gd = np.array([1, 2, 1, 1, 2, 1.0])
+    s = om.optimal_scale(lay, gd)
+    assert abs(se - (((s * lay - gd) / gd) ** 2).mean()) < 1e-14
+
+
+def test_np_known_case():
+    # star graph: centre 0 with leaves 1..4 on a unit circle, plus a far node 5
+    # attached to leaf 1: node 5's 1-ring {1}; its nearest layout neighbour is 1
+    rp, ci = csr_of(6, [(0, 1), (0, 2), (0, 3), (0, 4), (1, 5)])
+    x = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [3, 0]], dtype=float)
+    np1 = om.neighborhood_preservation(x, rp, ci, 1)
+    # node 0: ring {1,2,3,4}, 4-NN {1,2,3,4} -> 1; node 1: ring {0,5}, 2-NN {0, 2 (tie 2/4 -> lower)} -> 1/3
+    # nodes 2,3,4: ring {0}, 1-NN {0} -> 1; node 5: ring {1}, 1-NN {1} -> 1
+    assert abs(np1 - (1 + 1 / 3 + 1 + 1 + 1 + 1) / 6) < 1e-15
+    assert om.relative_error(0.9, 1.0) == pytest.approx(-0.1)
