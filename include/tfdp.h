@@ -1,0 +1,185 @@
+/*
+ * tfdp.h - C ABI of the MI355X t-FDP layout library (libtfdp.so).
+ *
+ * t-FDP ("Force-directed graph layouts revisited: a new force based on the
+ * t-Distribution", Zhong et al., arXiv 2303.03964) lays out an undirected
+ * graph in 2D. One iteration computes, for every node i,
+ *
+ *   repulsion  F^r_i = sum_j (x_i - x_j) / (1 + |x_i - x_j|^2)^gamma
+ *              (Sec. 3.3 Eq.5, rewritten as kernel sums in Sec. 3.4 Eq.11-15),
+ *   attraction F^a_i = -alpha sum_{j in N(i)} (1 + beta/(1 + |x_i - x_j|^2)) (x_i - x_j)
+ *              (Sec. 3.3 Eq.6, weighted as in Eq.7),
+ *   motion     D_i = rep_weight * F^r_i + F^a_i  (Eq.7; rep_weight = 1 is the
+ *              paper's model, other values give the global refinement of Sec. 5),
+ *
+ * then moves every node. The repulsion is evaluated either exactly (O(n^2),
+ * the "exact method" of Sec. 3.4) or by the interpolation-based FFT scheme of
+ * Sec. 3.4: spread the nodes onto an equispaced grid of N_int x N_int
+ * intervals with k x k Lagrange nodes each, convolve with the kernel by FFT,
+ * interpolate back.
+ *
+ * Readings of points the paper leaves open (the same in the library and in
+ * its FP64 test oracle):
+ *  - box: square of side W = max(x range, y range) centred on the mid-range
+ *    of each axis (W = 1 if all nodes coincide); interval index and
+ *    in-interval coordinate computed in float64;
+ *  - interpolation nodes at (j + 1/2)/k of each interval, j = 0..k-1;
+ *  - update: x_i += D_i * min(1, T_t / |D_i|), T_t = t0 * (1 - t / T)
+ *    (the paper gives no rule; Sec. 3.1 only says the force moves the node);
+ *  - k schedule (Sec. 3.4, "Choices of k"): k = 1 for t < floor(0.9 T),
+ *    k = 2 for t < floor(0.95 T), k = 3 afterwards.
+ *
+ * Memory and ownership. Every pointer named d_* is device memory on the
+ * current HIP device. The caller owns the CSR arrays, the positions, the
+ * force outputs and the workspace; the library never allocates or frees
+ * device memory and keeps the pointers given to tfdp_layout_init, so they must
+ * outlive the handle. Positions are float32 [n][2] interleaved (x0 y0 x1 y1 ..).
+ * The CSR is symmetric: every undirected edge {u, v} appears as u->v and
+ * v->u, row_ptr int32[n+1], col_idx int32[nnz], no self-loops or duplicates.
+ *
+ * Streams. Work is enqueued on the caller's stream and is asynchronous;
+ * functions that must read device results (init, sync_status, phase_times)
+ * synchronise that stream.
+ *
+ * Errors. Functions return a tfdp_status; no exception crosses the ABI and
+ * the library never aborts. tfdp_last_error() returns a thread-local message
+ * for the last failure (or a warning after TFDP_OK). Asynchronous failures
+ * (a HIP launch error, a non-finite position) are reported by the next call
+ * that synchronises: tfdp_layout_sync_status.
+ */
+#ifndef TFDP_H
+#define TFDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tfdp_status {
+    TFDP_OK = 0,
+    TFDP_ERR_INVALID_ARG = -1,  /* bad parameter, pointer, size or CSR */
+    TFDP_ERR_WORKSPACE = -2,    /* workspace missing or smaller than tfdp_workspace_size */
+    TFDP_ERR_HIP = -3,          /* a HIP runtime call or kernel launch failed */
+    TFDP_ERR_NONFINITE = -4,    /* a position became NaN or infinite */
+    TFDP_ERR_UNSUPPORTED = -5   /* valid request outside the built limits (e.g. grid too large) */
+} tfdp_status;
+
+/* Model and schedule parameters. */
+typedef struct tfdp_params {
+    float alpha;         /* attraction weight (Eq.7), default 0.1 (Sec. 3.3) */
+    float beta;          /* weight of the attractive t-force (Eq.6), default 8 */
+    float gamma;         /* repulsive t-force exponent (Eq.5), default 2; must be > 1 (Eq.10) */
+    float rep_weight;    /* multiplier of the repulsion, default 1 (Sec. 5, global refinement) */
+    int32_t n_int;       /* intervals per box side N_int (Sec. 3.4), 1..1024 */
+    int32_t k_mode;      /* 0: exact O(n^2) repulsion; 1, 2, 3: fixed k; -1: k schedule */
+    int32_t total_iters; /* T of the k schedule and the cooling, >= 1 */
+    float t0;            /* initial step cap; <= 0 selects max(1, sqrt(n)/10) */
+} tfdp_params;
+
+typedef struct tfdp_layout tfdp_layout; /* opaque handle (host memory) */
+
+/* Fill *p with the defaults: alpha 0.1, beta 8, gamma 2 (Sec. 3.3),
+ * rep_weight 1, n_int 64, k_mode -1, total_iters 300, t0 0 (automatic). */
+void tfdp_params_default(tfdp_params* p);
+
+/* Host-only check of parameters and sizes; touches no device.
+ * TFDP_ERR_INVALID_ARG: p NULL, n < 1, nnz < 0, gamma <= 1 (Eq.10), alpha,
+ * beta or rep_weight negative or not finite, n_int < 1, k_mode outside
+ * {-1,0,1,2,3}, total_iters < 1, t0 not finite.
+ * TFDP_ERR_UNSUPPORTED: N_int * k_max > 1024 (FFT length above 2048), where
+ * k_max is k_mode for k_mode 1 or 2 and 3 otherwise.
+ * Returns TFDP_OK with a warning in tfdp_last_error() when
+ * alpha (1 + beta) >= 1, which breaks the contact condition of Eq.9 (the
+ * paper's guideline, not a hard limit). */
+tfdp_status tfdp_params_validate(const tfdp_params* p, int32_t n, int64_t nnz);
+
+/* Bytes of device workspace needed by a handle with these sizes and
+ * parameters (host-only; 0 if tfdp_params_validate fails). The workspace
+ * holds the second position buffer, the binning arrays, the grids, spectra
+ * and twiddle tables, and a few counters. */
+size_t tfdp_workspace_size(int32_t n, int64_t nnz, const tfdp_params* p);
+
+/* Create a layout handle.
+ *   out        receives the handle (set to NULL on failure)
+ *   n, nnz     node count and number of CSR entries (2 x edges)
+ *   d_row_ptr  int32[n+1], d_col_idx int32[nnz]: symmetric CSR (device)
+ *   d_pos      float32[n][2] positions (device); tfdp_layout_step updates
+ *              it in place
+ *   d_ws       device workspace of ws_bytes >= tfdp_workspace_size(...),
+ *              256-byte aligned; owned by the caller, used exclusively by
+ *              this handle
+ *   p          parameters (copied)
+ *   stream     stream for the set-up work; init synchronises it
+ * Validates p (as tfdp_params_validate), checks on the device that row_ptr
+ * is monotone with row_ptr[0] = 0 and row_ptr[n] = nnz and that every column
+ * index is in [0, n) and not i itself (TFDP_ERR_INVALID_ARG otherwise),
+ * builds the FFT twiddle tables and sets the iteration counter to 0. */
+tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz,
+                             const int32_t* d_row_ptr, const int32_t* d_col_idx,
+                             float* d_pos, void* d_ws, size_t ws_bytes,
+                             const tfdp_params* p, hipStream_t stream);
+
+/* Advance the layout by `iters` iterations from the handle's counter t
+ * (asynchronous). Each iteration picks k from k_mode (or from the schedule
+ * with T = total_iters), evaluates the forces at the current positions and
+ * moves every node with the capped step T_t = t0 (1 - t/T); the counter then
+ * increases by one. Iterations past T keep going with k = 3 and a negative
+ * cap clamped to 0, i.e. no motion. The final positions are in d_pos when
+ * the stream reaches the end of the enqueued work. iters >= 0. */
+tfdp_status tfdp_layout_step(tfdp_layout* h, int32_t iters, hipStream_t stream);
+
+/* Evaluate the forces at d_pos_in (float32 [n][2], device) without moving
+ * anything and without changing the handle's state (asynchronous).
+ *   k = 0      exact repulsion (Sec. 3.4, "exact method")
+ *   k = 1,2,3  interpolated repulsion with k x k nodes per interval
+ * d_f_rep receives F^r, d_f_att F^a and d_f_tot D = rep_weight F^r + F^a,
+ * each float32 [n][2]; any of them may be NULL. d_pos_in may be the
+ * handle's own d_pos. TFDP_ERR_WORKSPACE if k exceeds the k the workspace
+ * was sized for. */
+tfdp_status tfdp_layout_forces(tfdp_layout* h, const float* d_pos_in, int32_t k,
+                               float* d_f_rep, float* d_f_att, float* d_f_tot,
+                               hipStream_t stream);
+
+/* Replace the parameters (re-tune, Sec. 5 "Global Refinement"). alpha, beta,
+ * gamma, rep_weight, total_iters, t0 may change freely; n_int and k_mode only
+ * within what the handle's workspace was sized for (TFDP_ERR_WORKSPACE
+ * otherwise). Takes effect for work enqueued afterwards. */
+tfdp_status tfdp_layout_set_params(tfdp_layout* h, const tfdp_params* p);
+
+/* Read / set the iteration counter t (checkpoint and resume: positions plus t
+ * are the whole state). */
+tfdp_status tfdp_layout_get_iter(const tfdp_layout* h, int32_t* t);
+tfdp_status tfdp_layout_set_iter(tfdp_layout* h, int32_t t);
+
+/* Synchronise `stream` and report asynchronous failures: TFDP_ERR_HIP for a
+ * failed kernel, TFDP_ERR_NONFINITE if any position computed since the last
+ * call was NaN or infinite (the flag is then cleared). */
+tfdp_status tfdp_layout_sync_status(tfdp_layout* h, hipStream_t stream);
+
+/* Destroy the handle (host memory only; the caller's buffers stay). */
+void tfdp_layout_destroy(tfdp_layout* h);
+
+/* Thread-local text for the last failure or warning ("" if none). */
+const char* tfdp_last_error(void);
+
+/* Per-phase timing with HIP events recorded on the launch stream around the
+ * kernels of each phase. Enabling costs two event records per phase launch. */
+tfdp_status tfdp_layout_set_profiling(tfdp_layout* h, int32_t enable);
+/* Number of phases and their names ("bin_count", "gather_update", ...). */
+int32_t tfdp_phase_count(void);
+const char* tfdp_phase_name(int32_t phase);
+/* Synchronise the stream of the recorded events and write, per phase, the
+ * summed milliseconds and the number of timed launches since profiling was
+ * enabled (arrays of at least tfdp_phase_count() entries); then reset. */
+tfdp_status tfdp_layout_phase_times(tfdp_layout* h, double* total_ms, int64_t* launches,
+                                    int32_t nphases);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFDP_H */

@@ -1,0 +1,248 @@
+// Box reduction and interval-row binning of the nodes (Sec. 3.4: the layout
+// box is split into N_int x N_int intervals; each node is interpolated from
+// the k x k nodes of its own interval).
+//
+// The nodes are bucketed by interval row with a stable counting sort so that
+// the spreading pass can accumulate every row of the grid in LDS without
+// global atomics:
+//   bin_count   per block of kBinChunk nodes: LDS histogram of interval rows
+//   bin_scan    per interval row: exclusive scan of the per-block counts
+//   bin_scatter per block: stable ranks inside the block (wave ballots),
+//               positions written to their sorted slot
+#include "tfdp_internal.h"
+
+namespace tfdp {
+
+// ----------------------------------------------------------------- box
+
+__global__ void k_box_begin(DevState* st, int t) {
+    if (threadIdx.x == 0) {
+        st->mm[0] = 0xffffffffu;
+        st->mm[1] = 0xffffffffu;
+        st->mm[2] = 0u;
+        st->mm[3] = 0u;
+        st->t = t;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_box_reduce(const float2* __restrict__ pos, int n,
+                                                         DevState* st) {
+    float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        float2 p = pos[i];
+        if (isfinite(p.x) && isfinite(p.y)) {
+            xmin = fminf(xmin, p.x);
+            xmax = fmaxf(xmax, p.x);
+            ymin = fminf(ymin, p.y);
+            ymax = fmaxf(ymax, p.y);
+        }
+    }
+    block_minmax_commit(xmin, ymin, xmax, ymax, st);
+}
+
+// Square box from the reduced extremes (same float64 operations as the
+// oracle), then reset of the extremes for the next reduction; optionally
+// advances the iteration counter.
+__global__ void k_box_finalize(DevState* st, int n_int, int advance) {
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0) return;
+    Box b;
+    if (st->mm[0] == 0xffffffffu) {  // nothing finite was seen
+        b.lo_x = 0.0;
+        b.lo_y = 0.0;
+        b.w = 1.0;
+    } else {
+        double xmin = (double)dec_ord(st->mm[0]);
+        double ymin = (double)dec_ord(st->mm[1]);
+        double xmax = (double)dec_ord(st->mm[2]);
+        double ymax = (double)dec_ord(st->mm[3]);
+        double rx = xmax - xmin;
+        double ry = ymax - ymin;
+        double w = rx >= ry ? rx : ry;
+        if (!(w > 0.0)) w = 1.0;
+        double cx = (xmin + xmax) / 2.0;
+        double cy = (ymin + ymax) / 2.0;
+        b.lo_x = cx - w / 2.0;
+        b.lo_y = cy - w / 2.0;
+        b.w = w;
+    }
+    b.h = b.w / (double)n_int;
+    st->box = b;
+    st->mm[0] = 0xffffffffu;
+    st->mm[1] = 0xffffffffu;
+    st->mm[2] = 0u;
+    st->mm[3] = 0u;
+    if (advance) st->t += 1;
+}
+
+void launch_box_begin(DevState* st, int t, hipStream_t s) {
+    hipLaunchKernelGGL(k_box_begin, dim3(1), dim3(64), 0, s, st, t);
+}
+
+void launch_box_reduce(const float2* pos, int n, DevState* st, hipStream_t s) {
+    int blocks = (n + kThreads * 8 - 1) / (kThreads * 8);
+    if (blocks < 1) blocks = 1;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_box_reduce, dim3(blocks), dim3(kThreads), 0, s, pos, n, st);
+}
+
+void launch_box_finalize(DevState* st, int n_int, int advance, hipStream_t s) {
+    hipLaunchKernelGGL(k_box_finalize, dim3(1), dim3(64), 0, s, st, n_int, advance);
+}
+
+// ----------------------------------------------------------------- binning
+
+__global__ __launch_bounds__(kThreads) void k_bin_count(const float2* __restrict__ pos, Bufs b) {
+    extern __shared__ int hist[];
+    const int n_int = b.n_int;
+    for (int c = threadIdx.x; c < n_int; c += blockDim.x) hist[c] = 0;
+    __syncthreads();
+    const Box bx = b.st->box;
+    const int beg = blockIdx.x * kBinChunk;
+    const int end = min(beg + kBinChunk, b.n);
+    for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+        int cy;
+        double ty;
+        bin_axis(pos[i].y, bx.lo_y, bx.h, n_int, cy, ty);
+        atomicAdd(&hist[cy], 1);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < n_int; c += blockDim.x)
+        b.blkcnt[(size_t)c * b.nblk + blockIdx.x] = hist[c];
+}
+
+// Exclusive scan of kThreads values held one per thread; returns the
+// thread's exclusive prefix and writes the block total.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* lds /* kThreads/64 + 1 */, int& total) {
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) lds[w] = x;
+    __syncthreads();
+    int base = 0;
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < w; ++i) base += lds[i];
+    int tot = 0;
+    for (int i = 0; i < nw; ++i) tot += lds[i];
+    total = tot;
+    __syncthreads();
+    return base + x - v;
+}
+
+// One block per interval row: exclusive scan of its per-block counts in
+// place, total into bucket_cnt.
+__global__ __launch_bounds__(kThreads) void k_bin_scan(Bufs b) {
+    __shared__ int lds[kThreads / 64 + 1];
+    const int c = blockIdx.x;
+    int* row = b.blkcnt + (size_t)c * b.nblk;
+    int carry = 0;
+    for (int base = 0; base < b.nblk; base += blockDim.x) {
+        const int i = base + threadIdx.x;
+        const int v = i < b.nblk ? row[i] : 0;
+        int tot;
+        const int ex = block_exclusive_scan(v, lds, tot);
+        if (i < b.nblk) row[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) b.bucket_cnt[c] = carry;
+}
+
+// Stable scatter of the positions into interval-row buckets. Block 0 also
+// publishes the bucket starts and the spreading-chunk starts.
+__global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restrict__ pos, Bufs b) {
+    extern __shared__ int sm[];
+    const int n_int = b.n_int;
+    int* base = sm;                  // [n_int] global slot of this block's first node per row
+    int* run = base + n_int;         // [n_int] nodes of this block already placed per row
+    int* wcnt = run + n_int;         // [4][n_int] per-wave counts of the current round
+    int* scan_lds = wcnt + 4 * n_int;  // [kThreads/64 + 1]
+    // bucket starts: exclusive scan over rows (n_int <= 1024, four per thread)
+    int carry = 0;
+    int chunk_carry = 0;
+    for (int c0 = 0; c0 < n_int; c0 += blockDim.x) {
+        const int c = c0 + threadIdx.x;
+        const int cnt = c < n_int ? b.bucket_cnt[c] : 0;
+        const int chunks = c < n_int ? max(1, (cnt + kSpreadChunk - 1) / kSpreadChunk) : 0;
+        int tot, tot2;
+        const int ex = block_exclusive_scan(cnt, scan_lds, tot);
+        const int ex2 = block_exclusive_scan(chunks, scan_lds, tot2);
+        if (c < n_int) {
+            base[c] = carry + ex + b.blkcnt[(size_t)c * b.nblk + blockIdx.x];
+            run[c] = 0;
+            if (blockIdx.x == 0) {
+                b.bucket_start[c] = carry + ex;
+                b.chunk_start[c] = chunk_carry + ex2;
+            }
+        }
+        carry += tot;
+        chunk_carry += tot2;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        b.bucket_start[n_int] = carry;
+        b.chunk_start[n_int] = chunk_carry;
+    }
+    for (int i = threadIdx.x; i < 4 * n_int; i += blockDim.x) wcnt[i] = 0;
+    __syncthreads();
+
+    int nbits = 1;
+    while ((1 << nbits) < n_int) ++nbits;
+    const Box bx = b.st->box;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int beg = blockIdx.x * kBinChunk;
+    const int end = min(beg + kBinChunk, b.n);
+    for (int r0 = beg; r0 < end; r0 += blockDim.x) {
+        const int i = r0 + threadIdx.x;
+        const bool valid = i < end;
+        float2 p = make_float2(0.f, 0.f);
+        int key = 0;
+        if (valid) {
+            p = pos[i];
+            double ty;
+            bin_axis(p.y, bx.lo_y, bx.h, n_int, key, ty);
+        }
+        unsigned long long peers = __ballot(valid);
+        for (int bit = 0; bit < nbits; ++bit) {
+            const bool set = (key >> bit) & 1;
+            const unsigned long long m = __ballot(set);
+            peers &= set ? m : ~m;
+        }
+        const unsigned long long before = peers & lt_mask;
+        const int rank = __popcll(before);
+        const int cnt = __popcll(peers);
+        const bool leader = valid && before == 0ull;
+        if (leader) wcnt[w * n_int + key] = cnt;
+        __syncthreads();
+        if (valid) {
+            int off = run[key] + rank;
+            for (int ww = 0; ww < w; ++ww) off += wcnt[ww * n_int + key];
+            b.spos[base[key] + off] = p;
+        }
+        __syncthreads();
+        if (leader) {
+            atomicAdd(&run[key], cnt);
+            wcnt[w * n_int + key] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_bin_count(const float2* pos, const Bufs& b, hipStream_t s) {
+    hipLaunchKernelGGL(k_bin_count, dim3(b.nblk), dim3(kThreads), b.n_int * sizeof(int), s, pos, b);
+}
+
+void launch_bin_scan(const Bufs& b, hipStream_t s) {
+    hipLaunchKernelGGL(k_bin_scan, dim3(b.n_int), dim3(kThreads), 0, s, b);
+}
+
+void launch_bin_scatter(const float2* pos, const Bufs& b, hipStream_t s) {
+    size_t lds = (size_t)(6 * b.n_int + kThreads / 64 + 1) * sizeof(int);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(b.nblk), dim3(kThreads), lds, s, pos, b);
+}
+
+}  // namespace tfdp

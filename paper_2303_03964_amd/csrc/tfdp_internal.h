@@ -1,0 +1,178 @@
+// Internal definitions shared by the HIP translation units of libtfdp.so.
+// Not part of the public ABI (see include/tfdp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tfdp {
+
+constexpr int kThreads = 256;        // threads per block of the node and FFT kernels
+constexpr int kBinChunk = 4096;      // nodes per block of the binning passes
+constexpr int kSpreadChunk = 2048;   // nodes per block of the spreading pass
+constexpr int kMaxL = 2048;          // largest FFT length per side
+constexpr int kMaxNInt = 1024;       // largest number of intervals per side
+constexpr int kColBytes = 36 * kMaxL;  // LDS of one column-pass block
+
+// Square box of the current positions, in float64 (lo, side W, interval h = W / N_int).
+struct Box {
+    double lo_x, lo_y, w, h;
+};
+
+// Device-resident per-handle state.
+struct DevState {
+    unsigned int mm[4];   // order-preserving encodings: min x, min y, max x, max y
+    int t;                // iteration index used by the update (cooling)
+    int nonfinite;        // set when a computed position is NaN or infinite
+    int csr_bad;          // set by the CSR check at init
+    int pad;
+    Box box;              // box used by every kernel of the current iteration
+};
+
+// Geometry of the grid for one k.
+struct Geom {
+    int k;      // interpolation nodes per interval per axis
+    int m;      // grid nodes per side, N_int * k
+    int L;      // FFT length per side (power of two, >= 2M, >= 64)
+    int logL;
+    int H;      // L/2 + 1 stored spectrum columns
+    int cw;     // spectrum columns per block of the column pass
+};
+
+// Workspace views used by the kernels.
+struct Bufs {
+    int n;
+    int n_int;
+    int nblk;            // blocks of the binning passes
+    int max_chunks;      // upper bound of spreading blocks
+    float2* spos;        // positions sorted by interval row
+    int* blkcnt;         // [n_int][nblk] counts, then exclusive offsets
+    int* bucket_cnt;     // [n_int]
+    int* bucket_start;   // [n_int + 1]
+    int* chunk_start;    // [n_int + 1]
+    float* spart;        // [max_chunks][k][M][3] partial grids
+    float2* qrow;        // [3][M][H] row spectra (charges, then potentials)
+    float* krow;         // [2][L][H] kernel row spectra (real)
+    float4* pot;         // [M][M] (phi_1, G_x, G_y, 0)
+    const float2* tw;    // twiddles for this L: exp(-2 pi i j / L), j < L/2
+    DevState* st;
+};
+
+struct ModelArgs {
+    float alpha, beta, gamma, rep_weight;
+    float t0;
+    int total_iters;
+};
+
+// ---- launchers (each defined next to its kernels) ----
+void launch_box_begin(DevState* st, int t, hipStream_t s);
+void launch_box_reduce(const float2* pos, int n, DevState* st, hipStream_t s);
+void launch_box_finalize(DevState* st, int n_int, int advance, hipStream_t s);
+void launch_bin_count(const float2* pos, const Bufs& b, hipStream_t s);
+void launch_bin_scan(const Bufs& b, hipStream_t s);
+void launch_bin_scatter(const float2* pos, const Bufs& b, hipStream_t s);
+void launch_spread(const Bufs& b, const Geom& g, hipStream_t s);
+void launch_rowfft(const Bufs& b, const Geom& g, float gamma, hipStream_t s);
+void launch_colconv(const Bufs& b, const Geom& g, hipStream_t s);
+void launch_rowifft(const Bufs& b, const Geom& g, hipStream_t s);
+void launch_twiddles(float2* tw, int L, hipStream_t s);
+void launch_gather(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx,
+                   const Bufs& b, const Geom& g, const ModelArgs& a,
+                   float2* f_rep, float2* f_att, float2* f_tot, hipStream_t s);
+void launch_brute(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx,
+                  int n, DevState* st, const ModelArgs& a,
+                  float2* f_rep, float2* f_att, float2* f_tot, hipStream_t s);
+void launch_csr_check(const int* row_ptr, const int* col_idx, int n, long long nnz,
+                      DevState* st, hipStream_t s);
+
+// ---- device helpers used by several translation units ----
+
+// Order-preserving map float -> uint (min/max of floats via integer atomics).
+__device__ __forceinline__ unsigned int enc_ord(float f) {
+    unsigned int u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float dec_ord(unsigned int u) {
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// Interval index and in-interval coordinate along one axis, float64 with a
+// fixed operation order and no contraction (the same operations as the CPU
+// oracle, so both choose the same interval for every node).
+__device__ __forceinline__ void bin_axis(float x, double lo, double h, int n_int,
+                                         int& c, double& t) {
+#pragma clang fp contract(off)
+    double r = ((double)x - lo) / h;
+    double f = floor(r);
+    f = fmin(fmax(f, 0.0), (double)(n_int - 1));
+    c = (int)f;
+    t = r - f;
+}
+
+// Lagrange basis on the K nodes (j + 1/2)/K of one interval, float64.
+template <int K>
+__device__ __forceinline__ void lagrange(double t, double* w) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        double tj = ((double)j + 0.5) / (double)K;
+        double v = 1.0;
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            if (m == j) continue;
+            double tm = ((double)m + 0.5) / (double)K;
+            v = v * ((t - tm) / (tj - tm));
+        }
+        w[j] = v;
+    }
+}
+
+// Offsets delta_j = (t - tau_j) h of a point from the K nodes of its interval.
+template <int K>
+__device__ __forceinline__ void node_deltas(double t, double h, double* d) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        double tj = ((double)j + 0.5) / (double)K;
+        d[j] = (t - tj) * h;
+    }
+}
+
+// Block-wide min/max of the given extremes, committed to st->mm with one
+// set of integer atomics per block (blockDim.x a multiple of 64, <= kThreads).
+__device__ __forceinline__ void block_minmax_commit(float xmin, float ymin, float xmax, float ymax,
+                                                    DevState* st) {
+    // wave reduction, then one lane per wave commits with atomics
+    for (int off = 32; off > 0; off >>= 1) {
+        xmin = fminf(xmin, __shfl_xor(xmin, off));
+        ymin = fminf(ymin, __shfl_xor(ymin, off));
+        xmax = fmaxf(xmax, __shfl_xor(xmax, off));
+        ymax = fmaxf(ymax, __shfl_xor(ymax, off));
+    }
+    __shared__ float red[4][kThreads / 64];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = xmin;
+        red[1][w] = ymin;
+        red[2][w] = xmax;
+        red[3][w] = ymax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+        for (int i = 1; i < nw; ++i) {
+            xmin = fminf(xmin, red[0][i]);
+            ymin = fminf(ymin, red[1][i]);
+            xmax = fmaxf(xmax, red[2][i]);
+            ymax = fmaxf(ymax, red[3][i]);
+        }
+        if (xmin <= xmax) {  // at least one finite position in the block
+            atomicMin(&st->mm[0], enc_ord(xmin));
+            atomicMin(&st->mm[1], enc_ord(ymin));
+            atomicMax(&st->mm[2], enc_ord(xmax));
+            atomicMax(&st->mm[3], enc_ord(ymax));
+        }
+    }
+}
+
+}  // namespace tfdp

@@ -1,0 +1,271 @@
+"""ctypes binding of libtfdp.so (C ABI in include/tfdp.h).
+
+Argument marshalling only: torch tensors supply device memory and the
+current HIP stream; every step of the computation runs in the library's
+kernels. torch is imported before the library is loaded so that both share
+one HIP runtime.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_void_p
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libtfdp.so"
+
+TFDP_OK = 0
+STATUS_NAMES = {
+    0: "TFDP_OK",
+    -1: "TFDP_ERR_INVALID_ARG",
+    -2: "TFDP_ERR_WORKSPACE",
+    -3: "TFDP_ERR_HIP",
+    -4: "TFDP_ERR_NONFINITE",
+    -5: "TFDP_ERR_UNSUPPORTED",
+}
+
+
+class TfdpParams(ctypes.Structure):
+    """Mirror of ``tfdp_params``."""
+
+    _fields_ = [
+        ("alpha", c_float),
+        ("beta", c_float),
+        ("gamma", c_float),
+        ("rep_weight", c_float),
+        ("n_int", c_int32),
+        ("k_mode", c_int32),
+        ("total_iters", c_int32),
+        ("t0", c_float),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class TfdpError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+# C signatures: name -> (restype, argtypes)
+_SIGS = {
+    "tfdp_params_default": (None, [POINTER(TfdpParams)]),
+    "tfdp_params_validate": (c_int32, [POINTER(TfdpParams), c_int32, c_int64]),
+    "tfdp_workspace_size": (c_size_t, [c_int32, c_int64, POINTER(TfdpParams)]),
+    "tfdp_layout_init": (c_int32, [POINTER(c_void_p), c_int32, c_int64, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_size_t, POINTER(TfdpParams), c_void_p]),
+    "tfdp_layout_step": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "tfdp_layout_forces": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "tfdp_layout_set_params": (c_int32, [c_void_p, POINTER(TfdpParams)]),
+    "tfdp_layout_get_iter": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "tfdp_layout_set_iter": (c_int32, [c_void_p, c_int32]),
+    "tfdp_layout_sync_status": (c_int32, [c_void_p, c_void_p]),
+    "tfdp_layout_destroy": (None, [c_void_p]),
+    "tfdp_last_error": (c_char_p, []),
+    "tfdp_layout_set_profiling": (c_int32, [c_void_p, c_int32]),
+    "tfdp_phase_count": (c_int32, []),
+    "tfdp_phase_name": (c_char_p, [c_int32]),
+    "tfdp_layout_phase_times": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64), c_int32]),
+}
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.environ.get("TFDP_LIBRARY", os.path.join(_HERE, _LIB_NAME))
+
+
+def load_library():
+    """Load libtfdp.so once; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise ImportError(f"{path} not found: build it first (python -m paper_2303_03964_amd.build)")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status):
+    if status != TFDP_OK:
+        raise TfdpError(status, tfdp_last_error())
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        return c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return c_void_p(stream.cuda_stream)
+    return c_void_p(int(stream))
+
+
+def _ptr(t):
+    return c_void_p(0 if t is None else t.data_ptr())
+
+
+# ------------------------------------------------------------------ same names as the C ABI
+
+def tfdp_last_error() -> str:
+    msg = load_library().tfdp_last_error()
+    return msg.decode() if msg else ""
+
+
+def tfdp_params_default(**overrides) -> TfdpParams:
+    p = TfdpParams()
+    load_library().tfdp_params_default(ctypes.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def tfdp_params_validate(p: TfdpParams, n: int, nnz: int) -> int:
+    return load_library().tfdp_params_validate(ctypes.byref(p), n, nnz)
+
+
+def tfdp_workspace_size(n: int, nnz: int, p: TfdpParams) -> int:
+    return int(load_library().tfdp_workspace_size(n, nnz, ctypes.byref(p)))
+
+
+def tfdp_layout_init(n, nnz, row_ptr, col_idx, pos, workspace, params, stream=None):
+    h = c_void_p()
+    _check(load_library().tfdp_layout_init(ctypes.byref(h), n, nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(pos),
+                                           _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                           ctypes.byref(params), _stream(stream)))
+    return h
+
+
+def tfdp_layout_step(h, iters, stream=None):
+    return _check(load_library().tfdp_layout_step(h, iters, _stream(stream)))
+
+
+def tfdp_layout_forces(h, pos_in, k, f_rep=None, f_att=None, f_tot=None, stream=None):
+    return _check(load_library().tfdp_layout_forces(h, _ptr(pos_in), k, _ptr(f_rep), _ptr(f_att), _ptr(f_tot),
+                                                     _stream(stream)))
+
+
+def tfdp_layout_set_params(h, params):
+    return _check(load_library().tfdp_layout_set_params(h, ctypes.byref(params)))
+
+
+def tfdp_layout_get_iter(h) -> int:
+    t = c_int32()
+    _check(load_library().tfdp_layout_get_iter(h, ctypes.byref(t)))
+    return t.value
+
+
+def tfdp_layout_set_iter(h, t):
+    return _check(load_library().tfdp_layout_set_iter(h, t))
+
+
+def tfdp_layout_sync_status(h, stream=None) -> int:
+    """Returns the raw status (TFDP_ERR_NONFINITE is reported, not raised)."""
+    st = load_library().tfdp_layout_sync_status(h, _stream(stream))
+    if st not in (TFDP_OK, -4):
+        raise TfdpError(st, tfdp_last_error())
+    return st
+
+
+def tfdp_layout_destroy(h):
+    load_library().tfdp_layout_destroy(h)
+
+
+def tfdp_layout_set_profiling(h, enable):
+    return _check(load_library().tfdp_layout_set_profiling(h, int(bool(enable))))
+
+
+def tfdp_phase_count() -> int:
+    return load_library().tfdp_phase_count()
+
+
+def tfdp_phase_name(i) -> str:
+    return load_library().tfdp_phase_name(i).decode()
+
+
+def tfdp_layout_phase_times(h):
+    n = tfdp_phase_count()
+    ms = (c_double * n)()
+    cnt = (c_int64 * n)()
+    _check(load_library().tfdp_layout_phase_times(h, ms, cnt, n))
+    return {tfdp_phase_name(i): (ms[i], cnt[i]) for i in range(n)}
+
+
+# ------------------------------------------------------------------ convenience owner of the buffers
+
+class Layout:
+    """Owns the device CSR, positions and workspace of one layout handle.
+
+    row_ptr / col_idx: int32 arrays (numpy or torch); pos: float32 [n, 2].
+    Host arrays are copied to ``device``; a device float32 ``pos`` tensor is
+    used in place.
+    """
+
+    def __init__(self, row_ptr, col_idx, pos, params: TfdpParams | None = None, device="cuda", stream=None):
+        dev = torch.device(device)
+        self.row_ptr = torch.as_tensor(row_ptr, dtype=torch.int32).to(dev).contiguous()
+        self.col_idx = torch.as_tensor(col_idx, dtype=torch.int32).to(dev).contiguous()
+        pos_t = torch.as_tensor(pos)
+        if pos_t.device == dev and pos_t.dtype == torch.float32 and pos_t.is_contiguous():
+            self.pos = pos_t
+        else:
+            self.pos = pos_t.to(dtype=torch.float32).to(dev).contiguous()
+        if self.pos.dim() != 2 or self.pos.shape[1] != 2:
+            raise ValueError("pos must have shape [n, 2]")
+        self.n = int(self.pos.shape[0])
+        self.nnz = int(self.col_idx.numel())
+        if self.row_ptr.numel() != self.n + 1:
+            raise ValueError("row_ptr must have n + 1 entries")
+        self.params = params if params is not None else tfdp_params_default()
+        size = tfdp_workspace_size(self.n, self.nnz, self.params)
+        if size == 0:
+            raise TfdpError(tfdp_params_validate(self.params, self.n, self.nnz), tfdp_last_error())
+        self.workspace = torch.empty(size + 256, dtype=torch.uint8, device=dev)
+        off = (-self.workspace.data_ptr()) % 256
+        self.workspace = self.workspace[off:off + size]
+        col = self.col_idx if self.nnz > 0 else None
+        self.handle = tfdp_layout_init(self.n, self.nnz, self.row_ptr, col, self.pos, self.workspace,
+                                       self.params, stream)
+
+    def step(self, iters, stream=None):
+        tfdp_layout_step(self.handle, iters, stream)
+
+    def forces(self, pos_in=None, k=0, stream=None):
+        pos_in = self.pos if pos_in is None else pos_in
+        out = [torch.empty((self.n, 2), dtype=torch.float32, device=self.pos.device) for _ in range(3)]
+        tfdp_layout_forces(self.handle, pos_in, k, out[0], out[1], out[2], stream)
+        return tuple(out)
+
+    def set_params(self, params: TfdpParams):
+        tfdp_layout_set_params(self.handle, params)
+        self.params = params
+
+    @property
+    def iteration(self):
+        return tfdp_layout_get_iter(self.handle)
+
+    @iteration.setter
+    def iteration(self, t):
+        tfdp_layout_set_iter(self.handle, t)
+
+    def sync_status(self, stream=None):
+        return tfdp_layout_sync_status(self.handle, stream)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            tfdp_layout_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,115 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+of include/tfdp.h, and its host-side validation returns the documented
+status codes without touching a device."""
+import ctypes
+
+import pytest
+
+from tests._lib import ensure_built, header_functions
+
+ensure_built()
+import paper_2303_03964_amd as T  # noqa: E402
+from paper_2303_03964_amd.tfdp import TfdpParams  # noqa: E402
+
+OK, INVALID, WORKSPACE, HIPERR, NONFINITE, UNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+
+def test_exports_every_header_function():
+    lib = ctypes.CDLL(T.library_path())
+    names = header_functions()
+    assert len(names) >= 16
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_defaults_match_paper():
+    p = T.tfdp_params_default()
+    assert p.alpha == pytest.approx(0.1) and p.beta == 8.0 and p.gamma == 2.0
+    assert p.rep_weight == 1.0 and p.k_mode == -1 and p.t0 == 0.0
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("gamma", 1.0, INVALID), ("gamma", 0.5, INVALID), ("gamma", float("nan"), INVALID),
+    ("alpha", -0.1, INVALID), ("alpha", float("inf"), INVALID), ("beta", -1.0, INVALID),
+    ("rep_weight", -2.0, INVALID), ("n_int", 0, INVALID), ("n_int", 1025, INVALID),
+    ("k_mode", 4, INVALID), ("k_mode", -2, INVALID), ("total_iters", 0, INVALID),
+    ("t0", float("inf"), INVALID), ("n_int", 400, UNSUPPORTED),
+])
+def test_validate_rejects(field, value, code):
+    p = T.tfdp_params_default(**{field: value})
+    assert T.tfdp_params_validate(p, 100, 10) == code
+    assert T.tfdp_last_error() != ""
+    assert T.tfdp_workspace_size(100, 10, p) == 0
+
+
+def test_validate_sizes_and_limits():
+    p = T.tfdp_params_default()
+    assert T.tfdp_params_validate(p, 0, 0) == INVALID
+    assert T.tfdp_params_validate(p, 10, -1) == INVALID
+    assert T.tfdp_params_validate(p, 10, 2 ** 31) == INVALID
+    assert T.tfdp_params_validate(p, 1, 0) == OK
+    # k_mode 1 allows a 1024-interval grid, the schedule does not
+    assert T.tfdp_params_validate(T.tfdp_params_default(n_int=1024, k_mode=1), 10, 0) == OK
+    assert T.tfdp_params_validate(T.tfdp_params_default(n_int=341), 10, 0) == OK
+    assert T.tfdp_params_validate(T.tfdp_params_default(n_int=342), 10, 0) == UNSUPPORTED
+
+
+def test_contact_condition_is_a_warning():
+    p = T.tfdp_params_default(alpha=0.2, beta=8.0)
+    assert T.tfdp_params_validate(p, 10, 0) == OK
+    assert "Eq.9" in T.tfdp_last_error()
+    assert T.tfdp_params_validate(T.tfdp_params_default(), 10, 0) == OK
+    assert T.tfdp_last_error() == ""
+
+
+def test_workspace_size_monotone():
+    p = T.tfdp_params_default(n_int=256, total_iters=500)
+    a = T.tfdp_workspace_size(1000, 0, p)
+    b = T.tfdp_workspace_size(1_000_000, 10_000_000, p)
+    assert 0 < a < b and a % 256 == 0
+    # 1M nodes, 256 intervals, k up to 3: well under 1 GB
+    assert b < 200 * 2 ** 20
+
+
+def test_init_rejects_before_device_work():
+    lib = T.load_library()
+    p = T.tfdp_params_default()
+    h = ctypes.c_void_p(1)
+    fake = ctypes.c_void_p(0x100000)
+    # NULL handle slot
+    assert lib.tfdp_layout_init(None, 10, 0, fake, fake, fake, fake, 1 << 20, ctypes.byref(p), None) == INVALID
+    # NULL device pointers
+    assert lib.tfdp_layout_init(ctypes.byref(h), 10, 4, None, fake, fake, fake, 1 << 20, ctypes.byref(p), None) == INVALID
+    assert h.value is None
+    # invalid parameters
+    bad = T.tfdp_params_default(gamma=0.9)
+    assert lib.tfdp_layout_init(ctypes.byref(h), 10, 4, fake, fake, fake, fake, 1 << 20, ctypes.byref(bad), None) == INVALID
+    # workspace missing, too small, misaligned
+    need = T.tfdp_workspace_size(10, 4, p)
+    assert lib.tfdp_layout_init(ctypes.byref(h), 10, 4, fake, fake, fake, None, need, ctypes.byref(p), None) == WORKSPACE
+    assert lib.tfdp_layout_init(ctypes.byref(h), 10, 4, fake, fake, fake, fake, need - 1, ctypes.byref(p), None) == WORKSPACE
+    odd = ctypes.c_void_p(0x100010)
+    assert lib.tfdp_layout_init(ctypes.byref(h), 10, 4, fake, fake, fake, odd, need, ctypes.byref(p), None) == WORKSPACE
+    assert "workspace" in T.tfdp_last_error()
+
+
+def test_null_handle_calls():
+    lib = T.load_library()
+    assert lib.tfdp_layout_step(None, 1, None) == INVALID
+    assert lib.tfdp_layout_forces(None, None, 1, None, None, None, None) == INVALID
+    assert lib.tfdp_layout_set_params(None, None) == INVALID
+    assert lib.tfdp_layout_get_iter(None, None) == INVALID
+    assert lib.tfdp_layout_set_iter(None, 3) == INVALID
+    assert lib.tfdp_layout_sync_status(None, None) == INVALID
+    assert lib.tfdp_layout_set_profiling(None, 1) == INVALID
+    lib.tfdp_layout_destroy(None)
+
+
+def test_phase_names():
+    names = [T.tfdp_phase_name(i) for i in range(T.tfdp_phase_count())]
+    assert "gather_update" in names and "spread" in names and "colconv" in names
+    assert T.tfdp_phase_name(-1) == "" and T.tfdp_phase_name(999) == ""
+
+
+def test_params_struct_layout():
+    assert ctypes.sizeof(TfdpParams) == 32

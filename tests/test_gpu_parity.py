@@ -1,0 +1,315 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Forces from identical FP32 positions: relative L2 <= 1e-5 against the
+oracle's exact sums (k = 0) and against the oracle's interpolated repulsion
+at the same k (k = 1, 2, 3). Sizes span many grid rows, several spreading
+chunks per row and ragged block tails; edge cases cover a single node,
+coincident nodes, an empty edge set and the largest supported grid.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synthgraphs as sg
+from oracle import tfdp as ot
+from tests._lib import ensure_built, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ensure_built()
+    import paper_2303_03964_amd as lib
+    lib.load_library()
+    return lib
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make_layout(T, g, pos, **params):
+    p = T.tfdp_params_default(**params)
+    return T.Layout(g.row_ptr, g.col_idx, pos, p)
+
+
+def gpu_forces(lay, pos, k):
+    import torch
+    pt = torch.as_tensor(pos, dtype=torch.float32).cuda().contiguous()
+    fr, fa, ft = lay.forces(pt, k)
+    torch.cuda.synchronize()
+    return fr.cpu().numpy(), fa.cpu().numpy(), ft.cpu().numpy()
+
+
+def oracle_forces(g, pos, k, n_int, alpha=0.1, beta=8.0, gamma=2.0, rep_weight=1.0):
+    x = pos.astype(np.float64)
+    fr = ot.repulsion_exact(x, gamma) if k == 0 else ot.repulsion_ibfft_stable(x, gamma, n_int, k)
+    fa = ot.attraction(x, g.row_ptr, g.col_idx, alpha, beta)
+    return fr, fa, rep_weight * fr + fa
+
+
+def check(T, g, pos, k, n_int, tol=TOL, **params):
+    say(f"case n={g.n} nnz={g.nnz} k={k} n_int={n_int} {params}")
+    lay = make_layout(T, g, pos, n_int=n_int, **params)
+    got = gpu_forces(lay, pos, k)
+    want = oracle_forces(g, pos, k, n_int, **{kk: v for kk, v in params.items()
+                                              if kk in ("alpha", "beta", "gamma", "rep_weight")})
+    errs = [rel_l2(a, b) for a, b in zip(got, want)]
+    say(f"  rel L2 rep/att/tot = {errs}")
+    if np.linalg.norm(want[0]) > 0:
+        assert errs[0] <= tol
+    if np.linalg.norm(want[1]) > 0:
+        assert errs[1] <= tol
+    assert errs[2] <= tol or np.linalg.norm(want[2]) == 0
+    lay.close()
+    return got, want
+
+
+# ------------------------------------------------------------------ 1,000-node SBM
+
+def test_sbm1k_exact(T):
+    w = sg.sbm_1k()
+    check(T, w.graph, w.pos0, 0, w.n_int)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_sbm1k_interpolated(T, k):
+    w = sg.sbm_1k()
+    got, _ = check(T, w.graph, w.pos0, k, w.n_int)
+    if k == 3:
+        # at this spacing (h/k = 0.01) the scheme itself is within 1e-3 of the exact sum
+        exact = ot.repulsion_exact(w.pos0.astype(np.float64), 2.0)
+        assert rel_l2(got[0], exact) <= 1e-3
+
+
+def test_sbm1k_spread_out_positions(T):
+    # positions of a partly converged layout: extent ~30, mixed densities
+    w = sg.sbm_1k()
+    rng = np.random.default_rng(5)
+    blocks = np.arange(1000) // 100
+    centres = rng.uniform(-12, 12, (10, 2))
+    pos = (centres[blocks] + rng.normal(size=(1000, 2)) * 1.5).astype(np.float32)
+    for k in (0, 1, 2, 3):
+        check(T, w.graph, pos, k, 64)
+
+
+# ------------------------------------------------------------------ many rows, chunks, ragged tails
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_uniform_20k_ragged(T, k):
+    n = 20011
+    g = sg.chung_lu(n, 2.5, 10.0, 11)
+    pos = sg.uniform_positions(n, 12, -30.0, 30.0)
+    check(T, g, pos, k, 128)
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_clustered_many_chunks(T, k):
+    # 70% of the nodes in one tight cluster: interval rows with many
+    # spreading chunks, most rows nearly empty
+    n = 60000
+    rng = np.random.default_rng(21)
+    g = sg.chung_lu(n, 2.5, 8.0, 22)
+    pos = rng.normal(size=(n, 2)) * 40.0
+    pos[: int(0.7 * n)] = rng.normal(size=(int(0.7 * n), 2)) * 0.8 + 5.0
+    pos = pos.astype(np.float32)
+    check(T, g, pos, k, 200 if k == 1 else 100)
+
+
+def test_params_other_than_defaults(T):
+    n = 3001
+    g = sg.chung_lu(n, 2.2, 6.0, 31)
+    pos = sg.uniform_positions(n, 32, -8, 8)
+    for k in (0, 2):
+        check(T, g, pos, k, 48, alpha=0.05, beta=20.0, gamma=3.5, rep_weight=2.0)
+        check(T, g, pos, k, 48, gamma=1.5)
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_single_node(T):
+    g = sg.csr_from_edges(1, np.zeros((0, 2), dtype=np.int64))
+    pos = np.array([[0.25, -3.0]], dtype=np.float32)
+    for k in (0, 1, 3):
+        lay = make_layout(T, g, pos, n_int=8)
+        fr, fa, ft = gpu_forces(lay, pos, k)
+        assert np.abs(fr).max() < 1e-6 and np.all(fa == 0)
+        lay.close()
+
+
+def test_coincident_nodes_and_empty_graph(T):
+    n = 500
+    g = sg.csr_from_edges(n, np.zeros((0, 2), dtype=np.int64))
+    pos = np.zeros((n, 2), dtype=np.float32) + np.float32(1.5)
+    lay = make_layout(T, g, pos, n_int=16)
+    for k in (0, 1, 2, 3):
+        fr, fa, ft = gpu_forces(lay, pos, k)
+        # the offset form adds two terms of size ~ n h K(0) that cancel; float32
+        # leaves a residue of a few ulp of that size
+        assert np.abs(fr).max() < 1e-6 * n and np.all(fa == 0)
+    lay.close()
+
+
+def test_two_nodes_pair(T):
+    g = sg.csr_from_edges(2, np.array([[0, 1]]))
+    pos = np.array([[0.0, 0.0], [0.7, -0.2]], dtype=np.float32)
+    for k in (0, 1, 2, 3):
+        check(T, g, pos, k, 4)
+
+
+def test_one_interval(T):
+    n = 777
+    g = sg.chung_lu(n, 2.5, 5.0, 41)
+    pos = sg.uniform_positions(n, 42)
+    for k in (1, 2, 3):
+        check(T, g, pos, k, 1)
+
+
+def test_largest_grid(T):
+    # N_int = 341 with k = 3: M = 1023 grid nodes per side, FFT length 2048
+    n = 30000
+    g = sg.chung_lu(n, 2.5, 10.0, 51)
+    pos = sg.uniform_positions(n, 52, -50, 50)
+    check(T, g, pos, 3, 341)
+    check(T, g, pos, 1, 341)
+
+
+# ------------------------------------------------------------------ one update step
+
+@pytest.mark.parametrize("t,k_mode", [(0, 0), (0, -1), (275, -1), (290, -1), (150, 2)])
+def test_single_step_matches_oracle(T, t, k_mode):
+    import torch
+    w = sg.sbm_1k()
+    rng = np.random.default_rng(7 + t)
+    pos = (w.pos0 * 6 + rng.normal(size=(1000, 2)) * 0.1).astype(np.float32)
+    p = T.tfdp_params_default(n_int=64, k_mode=k_mode, total_iters=300)
+    lay = T.Layout(w.graph.row_ptr, w.graph.col_idx, pos, p)
+    lay.iteration = t
+    lay.step(1)
+    torch.cuda.synchronize()
+    got = lay.pos.cpu().numpy().astype(np.float64)
+    assert lay.iteration == t + 1
+    op = ot.Params(n_int=64, k_mode=k_mode, total_iters=300)
+    k = k_mode if k_mode >= 0 else ot.k_for_iteration(t, 300)
+    _, _, disp = ot.forces(pos.astype(np.float64), w.graph.row_ptr, w.graph.col_idx, op, k)
+    want = ot.capped_move(pos.astype(np.float64), disp, ot.step_cap(t, 300, ot.default_t0(1000)))
+    move_err = rel_l2(got - pos, want - pos)
+    say(f"t={t} k={k}: relative error of the move {move_err}")
+    assert move_err <= 1e-5
+    assert lay.sync_status() == 0
+    lay.close()
+
+
+def test_step_is_deterministic_and_resumable(T):
+    import torch
+    w = sg.sbm_1k()
+    p = T.tfdp_params_default(n_int=64, total_iters=300)
+    a = T.Layout(w.graph.row_ptr, w.graph.col_idx, w.pos0, p)
+    b = T.Layout(w.graph.row_ptr, w.graph.col_idx, w.pos0, p)
+    a.step(300)
+    b.step(137)
+    b.step(1)
+    b.step(162)
+    torch.cuda.synchronize()
+    assert a.iteration == 300 and b.iteration == 300
+    assert torch.equal(a.pos, b.pos)
+    # restart from a checkpoint (positions + t) reproduces the rest bit for bit
+    c = T.Layout(w.graph.row_ptr, w.graph.col_idx, w.pos0, p)
+    c.step(200)
+    torch.cuda.synchronize()
+    ck = c.pos.clone()
+    d = T.Layout(w.graph.row_ptr, w.graph.col_idx, ck, p)
+    d.iteration = 200
+    c.step(100)
+    d.step(100)
+    torch.cuda.synchronize()
+    assert torch.equal(c.pos, d.pos) and torch.equal(c.pos, a.pos)
+    for x in (a, b, c, d):
+        assert x.sync_status() == 0
+        x.close()
+
+
+def test_forces_do_not_change_state(T):
+    import torch
+    w = sg.sbm_1k()
+    p = T.tfdp_params_default(n_int=64)
+    a = T.Layout(w.graph.row_ptr, w.graph.col_idx, w.pos0, p)
+    b = T.Layout(w.graph.row_ptr, w.graph.col_idx, w.pos0, p)
+    a.step(5)
+    b.step(2)
+    other = torch.as_tensor(sg.uniform_positions(1000, 99, -4, 4)).cuda()
+    f1 = b.forces(other, 3)
+    f2 = b.forces(other, 3)
+    b.step(3)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(f1, f2))
+    assert torch.equal(a.pos, b.pos)
+    a.close()
+    b.close()
+
+
+def test_nonfinite_is_reported(T):
+    import torch
+    w = sg.sbm_1k()
+    pos = w.pos0.copy()
+    pos[17] = np.nan
+    lay = make_layout(T, w.graph, pos, n_int=64, k_mode=1)
+    lay.step(1)
+    assert lay.sync_status() == -4
+    assert lay.sync_status() == 0  # flag cleared
+    lay.close()
+
+
+def test_invalid_csr_rejected(T):
+    import torch
+    rp = np.array([0, 1, 2, 3], dtype=np.int32)
+    ci = np.array([1, 0, 5], dtype=np.int32)  # column 5 out of range
+    with pytest.raises(T.TfdpError) as e:
+        T.Layout(rp, ci, np.zeros((3, 2), np.float32), T.tfdp_params_default(n_int=4))
+    assert e.value.status == -1
+    rp = np.array([0, 2, 1, 3], dtype=np.int32)  # not monotone
+    ci = np.array([1, 2, 0], dtype=np.int32)
+    with pytest.raises(T.TfdpError):
+        T.Layout(rp, ci, np.zeros((3, 2), np.float32), T.tfdp_params_default(n_int=4))
+    rp = np.array([0, 1, 2, 3], dtype=np.int32)
+    ci = np.array([0, 0, 1], dtype=np.int32)  # self-loop in row 0
+    with pytest.raises(T.TfdpError):
+        T.Layout(rp, ci, np.zeros((3, 2), np.float32), T.tfdp_params_default(n_int=4))
+
+
+def test_set_params_retune(T):
+    import torch
+    w = sg.sbm_1k()
+    p = T.tfdp_params_default(n_int=64, k_mode=2)
+    lay = T.Layout(w.graph.row_ptr, w.graph.col_idx, w.pos0, p)
+    with pytest.raises(T.TfdpError):
+        lay.set_params(T.tfdp_params_default(n_int=32, k_mode=2))
+    with pytest.raises(T.TfdpError):
+        lay.set_params(T.tfdp_params_default(n_int=64, k_mode=3))
+    lay.set_params(T.tfdp_params_default(n_int=64, k_mode=1, gamma=4.0, rep_weight=2.0, alpha=0.05))
+    check_pos = sg.uniform_positions(1000, 3, -5, 5)
+    got = gpu_forces(lay, check_pos, 1)
+    want = oracle_forces(w.graph, check_pos, 1, 64, alpha=0.05, gamma=4.0, rep_weight=2.0)
+    assert rel_l2(got[2], want[2]) <= TOL
+    lay.close()
+
+
+def test_profiling_phase_times(T):
+    w = sg.sbm_1k()
+    lay = make_layout(T, w.graph, w.pos0, n_int=64, total_iters=20)
+    T.tfdp_layout_set_profiling(lay.handle, 1)
+    lay.step(20)
+    times = T.tfdp_layout_phase_times(lay.handle)
+    assert times["gather_update"][1] == 20 and times["spread"][1] == 20
+    assert all(ms >= 0 for ms, _ in times.values())
+    T.tfdp_layout_set_profiling(lay.handle, 0)
+    lay.close()
