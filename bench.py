@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark of the t-FDP layout iteration on one MI355X.
+
+One step = one iteration of the whole hot path over the graph: box, interval
+binning, spreading, FFT convolution, gather, CSR attraction and the move.
+Default workload: Chung-Lu power-law graph, 1,000,000 nodes, exponent 2.5,
+mean degree 10, int32 CSR, FP32 positions uniform in [-1, 1]^2, N_int = 256,
+T = 500 iterations of the k schedule (k = 1/2/3 for 450/25/25 iterations).
+With the default --steps 500 the timed region is the whole layout.
+
+Prints one JSON line. ``value`` = n * steps / seconds (node-iterations/s)
+with the inputs resident in HBM. ``roofline`` prices the dominant kernel
+(gather + attraction + update) by its algorithmic bytes per launch over its
+average launch time, measured with HIP events on the launch stream in a
+second pass over the same iterations. ``cpu_baseline`` times the FP64 CPU
+oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="chung_lu_1m", choices=["chung_lu_1m", "mesh_100k", "sbm_1k"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations (0: about 15 s of work)")
+    ap.add_argument("--repeats", type=int, default=1, help="timed repeats; value is the median")
+    return ap.parse_args()
+
+
+def workload(name):
+    import synthgraphs as sg
+    if name == "chung_lu_1m":
+        return sg.chung_lu_1m()
+    if name == "mesh_100k":
+        return sg.mesh_100k()
+    return sg.sbm_1k()
+
+
+def gather_bytes(n, nnz, m):
+    """Algorithmic HBM bytes of one gather + attraction + update launch:
+    read own position (8 B), write new position (8 B), row_ptr (4 B) per
+    node; column index (4 B) and neighbour position (8 B) per CSR entry; the
+    M x M grid of potentials (16 B per grid node) once."""
+    return 20.0 * n + 12.0 * nnz + 16.0 * m * m
+
+
+def source_digest(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_file):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "gather_update_chung_lu_1m_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256_16") != source_digest([kernel_file, "paper_2303_03964_amd/csrc/tfdp_internal.h"]):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, iters):
+    """The FP64 oracle (as it stands) on the same graph: `iters` iterations of
+    forces + move at k = 1 from the initial positions."""
+    from oracle import tfdp as ot
+    p = ot.Params(n_int=w.n_int, total_iters=w.iters, k_mode=-1)
+    x = w.pos0.astype(np.float64)
+    g = w.graph
+    t0 = ot.default_t0(g.n)
+    c0 = time.process_time()
+    s0 = time.perf_counter()
+    done = 0
+    budget = 15.0
+    target = iters if iters > 0 else 10 ** 9
+    while done < target:
+        k = ot.k_for_iteration(done, w.iters)
+        _, _, d = ot.forces(x, g.row_ptr, g.col_idx, p, k)
+        x = ot.capped_move(x, d, ot.step_cap(done, w.iters, t0))
+        done += 1
+        if iters <= 0 and time.perf_counter() - s0 > budget:
+            break
+    wall = time.perf_counter() - s0
+    cpu = time.process_time() - c0
+    return {
+        "value": g.n * done / wall,
+        "unit": "node-iterations/s",
+        "cores": max(1, int(round(cpu / wall))),
+        "kind": "oracle",
+        "sample": f"{done} iterations (k=1) of the FP64 NumPy oracle on the same {g.n}-node graph; "
+                  f"{wall:.1f} s wall, {cpu:.1f} s CPU; host os.cpu_count()={os.cpu_count()}",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2303_03964_amd as T
+
+    t_gen = time.perf_counter()
+    w = workload(args.workload)
+    g = w.graph
+    print(f"# workload {w.name}: n={g.n} nnz={g.nnz} n_int={w.n_int} T={w.iters} "
+          f"(generated in {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    pos0 = torch.as_tensor(w.pos0).to(dev)
+    params = T.tfdp_params_default(n_int=w.n_int, total_iters=w.iters, k_mode=-1)
+    lay = T.Layout(g.row_ptr, g.col_idx, pos0.clone(), params, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def reset():
+        lay.pos.copy_(pos0)
+        lay.iteration = 0
+        torch.cuda.synchronize()
+
+    if args.warmup > 0:
+        lay.step(args.warmup)
+        torch.cuda.synchronize()
+        if lay.sync_status() != 0:
+            raise RuntimeError("non-finite positions during warm-up")
+    times = []
+    for _ in range(max(1, args.repeats)):
+        reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lay.step(args.steps)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    st = lay.sync_status()
+    if st != 0:
+        raise RuntimeError(f"layout status {st}")
+    secs = float(np.median(times))
+    print(f"# timed {args.steps} iterations: {secs * 1e3:.2f} ms (runs: {[round(t * 1e3, 2) for t in times]})",
+          file=sys.stderr, flush=True)
+
+    # second pass over the same iterations with HIP events around each phase
+    reset()
+    k1_iters = min(args.steps, (9 * w.iters) // 10)
+    T.tfdp_layout_set_profiling(lay.handle, 1)
+    lay.step(k1_iters)
+    ph1 = T.tfdp_layout_phase_times(lay.handle)
+    rest = args.steps - k1_iters
+    ph_rest = {}
+    if rest > 0:
+        lay.step(rest)
+        ph_rest = T.tfdp_layout_phase_times(lay.handle)
+    T.tfdp_layout_set_profiling(lay.handle, 0)
+    torch.cuda.synchronize()
+
+    gm_ms, gm_n = ph1["gather_update"]
+    avg_ms = gm_ms / max(gm_n, 1)
+    m1 = w.n_int  # k = 1
+    bytes_launch = gather_bytes(g.n, g.nnz, m1)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic("paper_2303_03964_amd/csrc/node_forces.hip")
+    phases = {name: round(ms / cnt, 4) for name, (ms, cnt) in ph1.items() if cnt}
+    phases_rest = {name: round(ms / cnt, 4) for name, (ms, cnt) in ph_rest.items() if cnt}
+    iter_ms_k1 = sum(ms for ms, _ in ph1.values()) / max(k1_iters, 1)
+
+    rec = {
+        "metric": "t-FDP node-iterations/s at 1M nodes" if w.name == "chung_lu_1m"
+        else f"t-FDP node-iterations/s ({w.name})",
+        "value": g.n * args.steps / secs,
+        "unit": "node-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "n": g.n,
+            "nnz": g.nnz,
+            "n_int": w.n_int,
+            "total_iters": w.iters,
+            "k_schedule": "1/2/3 over 90/5/5%",
+            "params": {"alpha": 0.1, "beta": 8.0, "gamma": 2.0},
+            "positions": "uniform [-1,1]^2 float32, seeded",
+        },
+        "roofline": {
+            "kernel": "k_gather<1> (gather + CSR attraction + update, k=1)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": bytes_launch,
+            "avg_launch_ms": avg_ms,
+            "launches": gm_n,
+        },
+        "phase_ms_k1": phases,
+        "phase_ms_k23": phases_rest,
+        "iteration_ms_k1_events": iter_ms_k1,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
+    lay.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()
