@@ -13,20 +13,34 @@
 
 namespace tfdp {
 
-// ----------------------------------------------------------------- box
+static_assert(kBoxSlots == 64, "the box finalize reduces one slot per lane of a wave");
 
+// ----------------------------------------------------------------- box
+//
+// Extremes of the positions are committed with integer atomics into one of
+// two slot sets: the update of iteration t fills set (t+1) & 1 while the
+// binning of iteration t reads set t & 1 and its scan resets set (t+1) & 1
+// for the next update. The box itself is derived by bin_count.
+
+__device__ __forceinline__ void reset_slot(DevState* st, int set, int i) {
+    st->mm[set][i][0] = 0xffffffffu;
+    st->mm[set][i][1] = 0xffffffffu;
+    st->mm[set][i][2] = 0u;
+    st->mm[set][i][3] = 0u;
+}
+
+// Reset of both slot sets; st->t = t - 1 (the scan of each iteration
+// advances it before the update reads it).
 __global__ void k_box_begin(DevState* st, int t) {
-    if (threadIdx.x == 0) {
-        st->mm[0] = 0xffffffffu;
-        st->mm[1] = 0xffffffffu;
-        st->mm[2] = 0u;
-        st->mm[3] = 0u;
-        st->t = t;
+    if (threadIdx.x < kBoxSlots) {
+        reset_slot(st, 0, threadIdx.x);
+        reset_slot(st, 1, threadIdx.x);
     }
+    if (threadIdx.x == 0) st->t = t - 1;
 }
 
 __global__ __launch_bounds__(kThreads) void k_box_reduce(const float2* __restrict__ pos, int n,
-                                                         DevState* st) {
+                                                         DevState* st, int set) {
     float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float2 p = pos[i];
@@ -37,74 +51,63 @@ __global__ __launch_bounds__(kThreads) void k_box_reduce(const float2* __restric
             ymax = fmaxf(ymax, p.y);
         }
     }
-    block_minmax_commit(xmin, ymin, xmax, ymax, st);
-}
-
-// Square box from the reduced extremes (same float64 operations as the
-// oracle), then reset of the extremes for the next reduction; optionally
-// advances the iteration counter.
-__global__ void k_box_finalize(DevState* st, int n_int, int advance) {
-#pragma clang fp contract(off)
-    if (threadIdx.x != 0) return;
-    Box b;
-    if (st->mm[0] == 0xffffffffu) {  // nothing finite was seen
-        b.lo_x = 0.0;
-        b.lo_y = 0.0;
-        b.w = 1.0;
-    } else {
-        double xmin = (double)dec_ord(st->mm[0]);
-        double ymin = (double)dec_ord(st->mm[1]);
-        double xmax = (double)dec_ord(st->mm[2]);
-        double ymax = (double)dec_ord(st->mm[3]);
-        double rx = xmax - xmin;
-        double ry = ymax - ymin;
-        double w = rx >= ry ? rx : ry;
-        if (!(w > 0.0)) w = 1.0;
-        double cx = (xmin + xmax) / 2.0;
-        double cy = (ymin + ymax) / 2.0;
-        b.lo_x = cx - w / 2.0;
-        b.lo_y = cy - w / 2.0;
-        b.w = w;
-    }
-    b.h = b.w / (double)n_int;
-    st->box = b;
-    st->mm[0] = 0xffffffffu;
-    st->mm[1] = 0xffffffffu;
-    st->mm[2] = 0u;
-    st->mm[3] = 0u;
-    if (advance) st->t += 1;
+    block_minmax_commit(xmin, ymin, xmax, ymax, st, set);
 }
 
 void launch_box_begin(DevState* st, int t, hipStream_t s) {
-    hipLaunchKernelGGL(k_box_begin, dim3(1), dim3(64), 0, s, st, t);
+    hipLaunchKernelGGL(k_box_begin, dim3(1), dim3(kBoxSlots), 0, s, st, t);
 }
 
-void launch_box_reduce(const float2* pos, int n, DevState* st, hipStream_t s) {
+void launch_box_reduce(const float2* pos, int n, DevState* st, int set, hipStream_t s) {
     int blocks = (n + kThreads * 8 - 1) / (kThreads * 8);
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_box_reduce, dim3(blocks), dim3(kThreads), 0, s, pos, n, st);
-}
-
-void launch_box_finalize(DevState* st, int n_int, int advance, hipStream_t s) {
-    hipLaunchKernelGGL(k_box_finalize, dim3(1), dim3(64), 0, s, st, n_int, advance);
+    hipLaunchKernelGGL(k_box_reduce, dim3(blocks), dim3(kThreads), 0, s, pos, n, st, set);
 }
 
 // ----------------------------------------------------------------- binning
 
-__global__ __launch_bounds__(kThreads) void k_bin_count(const float2* __restrict__ pos, Bufs b) {
+// Box of this iteration from slot set `set` (every block derives it; block 0
+// publishes it for the later kernels of the iteration), then the LDS
+// histogram of interval rows of this block's nodes.
+__global__ __launch_bounds__(kThreads) void k_bin_count(const float2* __restrict__ pos, Bufs b, int set) {
     extern __shared__ int hist[];
+    __shared__ Box sbox;
     const int n_int = b.n_int;
     for (int c = threadIdx.x; c < n_int; c += blockDim.x) hist[c] = 0;
+    if (threadIdx.x < 64) {
+        unsigned int a0 = b.st->mm[set][threadIdx.x][0];
+        unsigned int a1 = b.st->mm[set][threadIdx.x][1];
+        unsigned int a2 = b.st->mm[set][threadIdx.x][2];
+        unsigned int a3 = b.st->mm[set][threadIdx.x][3];
+        for (int off = 32; off > 0; off >>= 1) {
+            a0 = min(a0, (unsigned int)__shfl_xor((int)a0, off));
+            a1 = min(a1, (unsigned int)__shfl_xor((int)a1, off));
+            a2 = max(a2, (unsigned int)__shfl_xor((int)a2, off));
+            a3 = max(a3, (unsigned int)__shfl_xor((int)a3, off));
+        }
+        if (threadIdx.x == 0) {
+            sbox = box_from_extremes(a0, a1, a2, a3, n_int);
+            if (blockIdx.x == 0) b.st->box = sbox;
+        }
+    }
     __syncthreads();
-    const Box bx = b.st->box;
+    const Box bx = sbox;
     const int beg = blockIdx.x * kBinChunk;
     const int end = min(beg + kBinChunk, b.n);
-    for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
-        int cy;
-        double ty;
-        bin_axis(pos[i].y, bx.lo_y, bx.h, n_int, cy, ty);
-        atomicAdd(&hist[cy], 1);
+    for (int i0 = beg + threadIdx.x; i0 < end; i0 += 4 * blockDim.x) {
+        float yv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) yv[u] = pos[min(i0 + u * (int)blockDim.x, end - 1)].y;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (i0 + u * (int)blockDim.x < end) {
+                int cy;
+                double ty;
+                bin_axis(yv[u], bx.lo_y, bx.h, n_int, cy, ty);
+                atomicAdd(&hist[cy], 1);
+            }
+        }
     }
     __syncthreads();
     for (int c = threadIdx.x; c < n_int; c += blockDim.x)
@@ -135,9 +138,15 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* lds /* kThreads/
 
 // One block per interval row: exclusive scan of its per-block counts in
 // place, total into bucket_cnt.
-__global__ __launch_bounds__(kThreads) void k_bin_scan(Bufs b) {
+// Block 0 also resets slot set `reset_set` for the coming update and
+// advances the iteration counter.
+__global__ __launch_bounds__(kThreads) void k_bin_scan(Bufs b, int reset_set) {
     __shared__ int lds[kThreads / 64 + 1];
     const int c = blockIdx.x;
+    if (c == 0) {
+        if (threadIdx.x < kBoxSlots) reset_slot(b.st, reset_set, threadIdx.x);
+        if (threadIdx.x == 0) b.st->t += 1;
+    }
     int* row = b.blkcnt + (size_t)c * b.nblk;
     int carry = 0;
     for (int base = 0; base < b.nblk; base += blockDim.x) {
@@ -152,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_scan(Bufs b) {
 }
 
 // Stable scatter of the positions into interval-row buckets. Block 0 also
-// publishes the bucket starts and the spreading-chunk starts.
+// publishes the bucket starts.
 __global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restrict__ pos, Bufs b) {
     extern __shared__ int sm[];
     const int n_int = b.n_int;
@@ -162,29 +171,19 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restri
     int* scan_lds = wcnt + 4 * n_int;  // [kThreads/64 + 1]
     // bucket starts: exclusive scan over rows (n_int <= 1024, four per thread)
     int carry = 0;
-    int chunk_carry = 0;
     for (int c0 = 0; c0 < n_int; c0 += blockDim.x) {
         const int c = c0 + threadIdx.x;
         const int cnt = c < n_int ? b.bucket_cnt[c] : 0;
-        const int chunks = c < n_int ? max(1, (cnt + kSpreadChunk - 1) / kSpreadChunk) : 0;
-        int tot, tot2;
+        int tot;
         const int ex = block_exclusive_scan(cnt, scan_lds, tot);
-        const int ex2 = block_exclusive_scan(chunks, scan_lds, tot2);
         if (c < n_int) {
             base[c] = carry + ex + b.blkcnt[(size_t)c * b.nblk + blockIdx.x];
             run[c] = 0;
-            if (blockIdx.x == 0) {
-                b.bucket_start[c] = carry + ex;
-                b.chunk_start[c] = chunk_carry + ex2;
-            }
+            if (blockIdx.x == 0) b.bucket_start[c] = carry + ex;
         }
         carry += tot;
-        chunk_carry += tot2;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        b.bucket_start[n_int] = carry;
-        b.chunk_start[n_int] = chunk_carry;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) b.bucket_start[n_int] = carry;
     for (int i = threadIdx.x; i < 4 * n_int; i += blockDim.x) wcnt[i] = 0;
     __syncthreads();
 
@@ -232,12 +231,12 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restri
     }
 }
 
-void launch_bin_count(const float2* pos, const Bufs& b, hipStream_t s) {
-    hipLaunchKernelGGL(k_bin_count, dim3(b.nblk), dim3(kThreads), b.n_int * sizeof(int), s, pos, b);
+void launch_bin_count(const float2* pos, const Bufs& b, int set, hipStream_t s) {
+    hipLaunchKernelGGL(k_bin_count, dim3(b.nblk), dim3(kThreads), b.n_int * sizeof(int), s, pos, b, set);
 }
 
-void launch_bin_scan(const Bufs& b, hipStream_t s) {
-    hipLaunchKernelGGL(k_bin_scan, dim3(b.n_int), dim3(kThreads), 0, s, b);
+void launch_bin_scan(const Bufs& b, int reset_set, hipStream_t s) {
+    hipLaunchKernelGGL(k_bin_scan, dim3(b.n_int), dim3(kThreads), 0, s, b, reset_set);
 }
 
 void launch_bin_scatter(const float2* pos, const Bufs& b, hipStream_t s) {

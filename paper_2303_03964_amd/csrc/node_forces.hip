@@ -2,57 +2,96 @@
 // (Sec. 3.4, third step), attraction along the CSR rows (Sec. 3.3, Eq.6-7),
 // the displacement D = w_r F^r + F^a and the capped move; or, for the exact
 // method (Sec. 3.4), the all-pairs repulsion tiled through LDS.
+//
+// Edge pass schedule (built once at init from row_ptr): rows are cut into
+// wave groups of at most kGroupRows rows and kGroupEdges CSR entries, packed
+// four per block; a row with more than kGroupEdges entries gets a block of
+// its own. In a wave group, lane l walks CSR entry e0 + l (coalesced column
+// reads), finds its row by a binary search over the group's row starts held
+// one per lane, and adds its term to a wave-private LDS accumulator; lane r
+// then finishes row r0 + r. A heavy row is summed by all 256 threads and
+// reduced in a fixed order. Every wave handles at most kGroupEdges entries,
+// whatever the degree distribution.
 #include "tfdp_internal.h"
 
 namespace tfdp {
 
-// Attraction, displacement and either the force outputs (pos_out == nullptr)
-// or the capped move plus the block's share of the next box.
-__device__ __forceinline__ void finish_node(bool active, int i, float2 p, float frx, float fry,
-                                            const float2* __restrict__ pos,
-                                            const int* __restrict__ row_ptr,
-                                            const int* __restrict__ col_idx, const ModelArgs& a,
-                                            DevState* st, float2* __restrict__ pos_out,
-                                            float2* f_rep, float2* f_att, float2* f_tot) {
-    float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
-    if (active) {
-        float fax = 0.f, fay = 0.f;
-        const int e1 = row_ptr[i + 1];
-        for (int e = row_ptr[i]; e < e1; ++e) {
-            const float2 q = pos[col_idx[e]];
-            const float dx = p.x - q.x;
-            const float dy = p.y - q.y;
-            const float f = 1.f + a.beta / (1.f + (dx * dx + dy * dy));
-            fax += f * dx;
-            fay += f * dy;
-        }
-        fax *= -a.alpha;
-        fay *= -a.alpha;
-        const float dxt = a.rep_weight * frx + fax;
-        const float dyt = a.rep_weight * fry + fay;
-        if (pos_out == nullptr) {
-            if (f_rep) f_rep[i] = make_float2(frx, fry);
-            if (f_att) f_att[i] = make_float2(fax, fay);
-            if (f_tot) f_tot[i] = make_float2(dxt, dyt);
-        } else {
-            const int t = st->t;
-            double c = (double)a.t0 * (1.0 - (double)t / (double)a.total_iters);
-            const float cap = c > 0.0 ? (float)c : 0.f;
-            const float norm = sqrtf(dxt * dxt + dyt * dyt);
-            const float scale = norm > cap ? cap / norm : 1.f;
-            const float2 np = make_float2(p.x + dxt * scale, p.y + dyt * scale);
-            pos_out[i] = np;
-            if (isfinite(np.x) && isfinite(np.y)) {
-                xmin = np.x;
-                xmax = np.x;
-                ymin = np.y;
-                ymax = np.y;
-            } else {
-                st->nonfinite = 1;
+// Interpolated repulsion at p from the grid potentials (phi_1, G_x, G_y):
+// F = sum_g w_g (delta_g phi_1(g) + G(g)) over the K x K nodes of p's interval.
+template <int K>
+__device__ __forceinline__ void grid_repulsion(const Bufs& b, const Geom& g, const Box& bx, float2 p,
+                                               float& frx, float& fry) {
+    int cx, cy;
+    double tx, ty;
+    bin_axis(p.x, bx.lo_x, bx.h, b.n_int, cx, tx);
+    bin_axis(p.y, bx.lo_y, bx.h, b.n_int, cy, ty);
+    double wx[K], wy[K], dx[K], dy[K];
+    lagrange<K>(tx, wx);
+    lagrange<K>(ty, wy);
+    node_deltas<K>(tx, bx.h, dx);
+    node_deltas<K>(ty, bx.h, dy);
+    const int M = g.m;
+    frx = 0.f;
+    fry = 0.f;
+#pragma unroll
+    for (int bb = 0; bb < K; ++bb) {
+        const float4* row = b.pot + (size_t)(cy * K + bb) * M + cx * K;
+        const float ddy = (float)dy[bb];
+#pragma unroll
+        for (int aa = 0; aa < K; ++aa) {
+            double wd;
+            {
+#pragma clang fp contract(off)
+                wd = wx[aa] * wy[bb];
             }
+            const float w = (float)wd;
+            const float4 v = row[aa];
+            frx += w * ((float)dx[aa] * v.x + v.y);
+            fry += w * (ddy * v.x + v.z);
         }
     }
-    if (pos_out != nullptr) block_minmax_commit(xmin, ymin, xmax, ymax, st);
+}
+
+// Attraction term of one CSR entry: (1 + beta / (1 + d^2)) (x_i - x_j).
+__device__ __forceinline__ void edge_term(float px, float py, float2 q, float beta, float& ax, float& ay) {
+    const float dx = px - q.x;
+    const float dy = py - q.y;
+    const float f = 1.f + beta / (1.f + (dx * dx + dy * dy));
+    ax = f * dx;
+    ay = f * dy;
+}
+
+// Displacement of node i from its repulsion and summed attraction terms;
+// writes the force outputs (pos_out == nullptr) or the capped move and
+// widens the block's box extremes.
+__device__ __forceinline__ void node_output(int i, float2 p, float frx, float fry, float sax, float say,
+                                            const ModelArgs& a, int t, DevState* st, float2* __restrict__ pos_out,
+                                            float2* f_rep, float2* f_att, float2* f_tot, float& xmin,
+                                            float& ymin, float& xmax, float& ymax) {
+    const float fax = -a.alpha * sax;
+    const float fay = -a.alpha * say;
+    const float dxt = a.rep_weight * frx + fax;
+    const float dyt = a.rep_weight * fry + fay;
+    if (pos_out == nullptr) {
+        if (f_rep) f_rep[i] = make_float2(frx, fry);
+        if (f_att) f_att[i] = make_float2(fax, fay);
+        if (f_tot) f_tot[i] = make_float2(dxt, dyt);
+        return;
+    }
+    const double c = (double)a.t0 * (1.0 - (double)t / (double)a.total_iters);
+    const float cap = c > 0.0 ? (float)c : 0.f;
+    const float norm = sqrtf(dxt * dxt + dyt * dyt);
+    const float scale = norm > cap ? cap / norm : 1.f;
+    const float2 np = make_float2(p.x + dxt * scale, p.y + dyt * scale);
+    pos_out[i] = np;
+    if (isfinite(np.x) && isfinite(np.y)) {
+        xmin = fminf(xmin, np.x);
+        xmax = fmaxf(xmax, np.x);
+        ymin = fminf(ymin, np.y);
+        ymax = fmaxf(ymax, np.y);
+    } else {
+        st->nonfinite = 1;
+    }
 }
 
 template <int K>
@@ -60,73 +99,151 @@ __global__ __launch_bounds__(kThreads) void k_gather(const float2* __restrict__ 
                                                      float2* __restrict__ pos_out,
                                                      const int* __restrict__ row_ptr,
                                                      const int* __restrict__ col_idx, Bufs b, Geom g,
-                                                     ModelArgs a, float2* f_rep, float2* f_att,
+                                                     ModelArgs a, int set, float2* f_rep, float2* f_att,
                                                      float2* f_tot) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = i < b.n;
+    __shared__ float accx[kThreads];
+    __shared__ float accy[kThreads];
+    __shared__ float hred[2][kThreads / 64];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    accx[threadIdx.x] = 0.f;
+    accy[threadIdx.x] = 0.f;
+    __syncthreads();
+    const int2 s0 = b.sched[4 * blockIdx.x];
+    const Box bx = b.st->box;
+    float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
+    bool have = false;
+    int i = 0;
     float2 p = make_float2(0.f, 0.f);
-    float frx = 0.f, fry = 0.f;
-    if (active) {
-        const Box bx = b.st->box;
-        p = pos[i];
-        int cx, cy;
-        double tx, ty;
-        bin_axis(p.x, bx.lo_x, bx.h, b.n_int, cx, tx);
-        bin_axis(p.y, bx.lo_y, bx.h, b.n_int, cy, ty);
-        double wx[K], wy[K], dx[K], dy[K];
-        lagrange<K>(tx, wx);
-        lagrange<K>(ty, wy);
-        node_deltas<K>(tx, bx.h, dx);
-        node_deltas<K>(ty, bx.h, dy);
-        const int M = g.m;
+    float sax = 0.f, say = 0.f;
+    if (s0.y < 0) {
+        // one row with more than kGroupEdges entries, summed by the whole block;
+        // four independent column/neighbour loads in flight per thread
+        const int row = s0.x;
+        const int e1 = row_ptr[row + 1];
+        const float2 pr = pos[row];
+        float sx = 0.f, sy = 0.f;
+        for (int e = row_ptr[row] + threadIdx.x; e < e1; e += 4 * kThreads) {
+            // past the row's end the row itself stands in: its term is zero
+            int c[4];
 #pragma unroll
-        for (int bb = 0; bb < K; ++bb) {
-            const float4* row = b.pot + (size_t)(cy * K + bb) * M + cx * K;
-            const float ddy = (float)dy[bb];
+            for (int u = 0; u < 4; ++u) c[u] = e + u * kThreads < e1 ? col_idx[e + u * kThreads] : row;
+            float2 q[4];
 #pragma unroll
-            for (int aa = 0; aa < K; ++aa) {
-                double wd;
-                {
-#pragma clang fp contract(off)
-                    wd = wx[aa] * wy[bb];
+            for (int u = 0; u < 4; ++u) q[u] = pos[c[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                float ax, ay;
+                edge_term(pr.x, pr.y, q[u], a.beta, ax, ay);
+                sx += ax;
+                sy += ay;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            sx += __shfl_xor(sx, off);
+            sy += __shfl_xor(sy, off);
+        }
+        if (lane == 0) {
+            hred[0][w] = sx;
+            hred[1][w] = sy;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sax = (hred[0][0] + hred[0][1]) + (hred[0][2] + hred[0][3]);
+            say = (hred[1][0] + hred[1][1]) + (hred[1][2] + hred[1][3]);
+            have = true;
+            i = row;
+            p = pr;
+        }
+    } else {
+        const int2 gd = b.sched[4 * blockIdx.x + w];
+        const int r0 = gd.x, nr = gd.y;
+        if (nr > 0) {
+            const int rs = lane < nr ? row_ptr[r0 + lane] : 0x7fffffff;
+            const float2 po = lane < nr ? pos[r0 + lane] : make_float2(0.f, 0.f);
+            const int eb = row_ptr[r0];
+            const int ee = row_ptr[r0 + nr];
+            float* ax_w = accx + w * 64;
+            float* ay_w = accy + w * 64;
+            // all column reads of the group first, then all neighbour reads:
+            // up to kGroupEdges/64 independent loads in flight per lane
+            constexpr int R = kGroupEdges / 64;
+            int rowr[R];
+            int colr[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int e = eb + r * 64 + lane;
+                // row of entry e: the largest row index < nr whose start is <= e
+                int lo = 0;
+#pragma unroll
+                for (int step = 32; step > 0; step >>= 1) {
+                    const int cand = lo + step;
+                    const int v = __shfl(rs, cand & 63);
+                    if (cand < nr && v <= e) lo = cand;
                 }
-                const float w = (float)wd;
-                const float4 v = row[aa];
-                frx += w * ((float)dx[aa] * v.x + v.y);
-                fry += w * (ddy * v.x + v.z);
+                rowr[r] = lo;
+                colr[r] = e < ee ? col_idx[e] : r0;  // r0: any valid index, term skipped below
+            }
+            float2 q[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) q[r] = pos[colr[r]];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float px = __shfl(po.x, rowr[r]);
+                const float py = __shfl(po.y, rowr[r]);
+                if (eb + r * 64 + lane < ee) {
+                    float ax, ay;
+                    edge_term(px, py, q[r], a.beta, ax, ay);
+                    atomicAdd(ax_w + rowr[r], ax);
+                    atomicAdd(ay_w + rowr[r], ay);
+                }
+            }
+            if (lane < nr) {
+                sax = ax_w[lane];
+                say = ay_w[lane];
+                have = true;
+                i = r0 + lane;
+                p = po;
             }
         }
     }
-    finish_node(active, i, p, frx, fry, pos, row_ptr, col_idx, a, b.st, pos_out, f_rep, f_att, f_tot);
+    if (have) {
+        float frx, fry;
+        grid_repulsion<K>(b, g, bx, p, frx, fry);
+        node_output(i, p, frx, fry, sax, say, a, b.st->t, b.st, pos_out, f_rep, f_att, f_tot, xmin, ymin, xmax,
+                    ymax);
+    }
+    if (pos_out != nullptr) block_minmax_commit(xmin, ymin, xmax, ymax, b.st, set);
 }
 
 void launch_gather(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx,
-                   const Bufs& b, const Geom& g, const ModelArgs& a, float2* f_rep, float2* f_att,
+                   const Bufs& b, const Geom& g, const ModelArgs& a, int set, float2* f_rep, float2* f_att,
                    float2* f_tot, hipStream_t s) {
-    const int blocks = (b.n + kThreads - 1) / kThreads;
+    const int blocks = b.edge_blocks;
     switch (g.k) {
         case 1:
             hipLaunchKernelGGL(k_gather<1>, dim3(blocks), dim3(kThreads), 0, s, pos, pos_out, row_ptr,
-                               col_idx, b, g, a, f_rep, f_att, f_tot);
+                               col_idx, b, g, a, set, f_rep, f_att, f_tot);
             break;
         case 2:
             hipLaunchKernelGGL(k_gather<2>, dim3(blocks), dim3(kThreads), 0, s, pos, pos_out, row_ptr,
-                               col_idx, b, g, a, f_rep, f_att, f_tot);
+                               col_idx, b, g, a, set, f_rep, f_att, f_tot);
             break;
         default:
             hipLaunchKernelGGL(k_gather<3>, dim3(blocks), dim3(kThreads), 0, s, pos, pos_out, row_ptr,
-                               col_idx, b, g, a, f_rep, f_att, f_tot);
+                               col_idx, b, g, a, set, f_rep, f_att, f_tot);
             break;
     }
 }
 
 // Exact repulsion: F_i = sum_j K_ij (x_i - x_j), K_ij = (1 + d_ij^2)^-gamma
-// (Eq.11; the j = i term is zero), positions streamed through LDS tiles.
+// (Eq.11; the j = i term is zero), positions streamed through LDS tiles;
+// attraction by a per-thread row loop (used for small graphs).
 __global__ __launch_bounds__(kThreads) void k_brute(const float2* __restrict__ pos, int n,
                                                     float2* __restrict__ pos_out,
                                                     const int* __restrict__ row_ptr,
                                                     const int* __restrict__ col_idx, DevState* st,
-                                                    ModelArgs a, float2* f_rep, float2* f_att,
+                                                    ModelArgs a, int t, float2* f_rep, float2* f_att,
                                                     float2* f_tot) {
     __shared__ float2 tile[kThreads];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -156,15 +273,26 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float2* __restrict__ p
         }
         __syncthreads();
     }
-    finish_node(active, i, p, frx, fry, pos, row_ptr, col_idx, a, st, pos_out, f_rep, f_att, f_tot);
+    float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
+    if (active) {
+        float sax = 0.f, say = 0.f;
+        const int e1 = row_ptr[i + 1];
+        for (int e = row_ptr[i]; e < e1; ++e) {
+            float ax, ay;
+            edge_term(p.x, p.y, pos[col_idx[e]], a.beta, ax, ay);
+            sax += ax;
+            say += ay;
+        }
+        node_output(i, p, frx, fry, sax, say, a, t, st, pos_out, f_rep, f_att, f_tot, xmin, ymin, xmax, ymax);
+    }
 }
 
 void launch_brute(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx, int n,
-                  DevState* st, const ModelArgs& a, float2* f_rep, float2* f_att, float2* f_tot,
+                  DevState* st, const ModelArgs& a, int t, float2* f_rep, float2* f_att, float2* f_tot,
                   hipStream_t s) {
     const int blocks = (n + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(k_brute, dim3(blocks), dim3(kThreads), 0, s, pos, n, pos_out, row_ptr, col_idx,
-                       st, a, f_rep, f_att, f_tot);
+                       st, a, t, f_rep, f_att, f_tot);
 }
 
 // CSR sanity check: row_ptr[0] = 0, monotone, row_ptr[n] = nnz, columns in

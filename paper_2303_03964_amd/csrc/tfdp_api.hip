@@ -23,7 +23,6 @@ enum Phase {
     PH_BIN_SCAN,
     PH_BIN_SCATTER,
     PH_SPREAD,
-    PH_ROWFFT,
     PH_COLCONV,
     PH_ROWIFFT,
     PH_GATHER,
@@ -31,8 +30,8 @@ enum Phase {
     PH_COUNT
 };
 
-const char* kPhaseNames[PH_COUNT] = {"box",     "bin_count", "bin_scan", "bin_scatter",   "spread",
-                                     "rowfft",  "colconv",   "rowifft",  "gather_update", "brute"};
+const char* kPhaseNames[PH_COUNT] = {"box",     "bin_count", "bin_scan",      "bin_scatter", "spread_rows",
+                                     "colconv", "rowifft",   "gather_update", "brute"};
 
 int k_workspace(const tfdp_params* p) { return (p->k_mode == 1 || p->k_mode == 2) ? p->k_mode : 3; }
 
@@ -48,7 +47,7 @@ Geom make_geom(int n_int, int k) {
     g.L = L;
     g.logL = logL;
     g.H = L / 2 + 1;
-    g.cw = L >= 1024 ? 1 : 1024 / L;
+    g.cw = L >= 512 ? 1 : 512 / L;  // transforms per FFT task
     return g;
 }
 
@@ -71,7 +70,7 @@ struct Layout {
     float2* tw[4];  // per k
 };
 
-Layout carve(void* base, int n, const tfdp_params* p, size_t* bytes) {
+Layout carve(void* base, int n, long long nnz, const tfdp_params* p, size_t* bytes) {
     Layout l;
     std::memset(&l, 0, sizeof(l));
     Carve c{static_cast<char*>(base), 0};
@@ -80,24 +79,59 @@ Layout carve(void* base, int n, const tfdp_params* p, size_t* bytes) {
     l.b.n = n;
     l.b.n_int = p->n_int;
     l.b.nblk = (n + kBinChunk - 1) / kBinChunk;
-    l.b.max_chunks = (n + kSpreadChunk - 1) / kSpreadChunk + p->n_int;
     l.b.st = c.take<DevState>(1);
     l.pos_alt = c.take<float2>((size_t)n);
     l.b.spos = c.take<float2>((size_t)n);
     l.b.blkcnt = c.take<int>((size_t)p->n_int * l.b.nblk);
     l.b.bucket_cnt = c.take<int>((size_t)p->n_int);
     l.b.bucket_start = c.take<int>((size_t)p->n_int + 1);
-    l.b.chunk_start = c.take<int>((size_t)p->n_int + 1);
-    l.b.spart = c.take<float>((size_t)l.b.max_chunks * kw * gw.m * 3);
-    l.b.qrow = c.take<float2>((size_t)3 * gw.m * gw.H);
-    l.b.krow = c.take<float>((size_t)2 * gw.L * gw.H);
+    l.b.qcol = c.take<float2>((size_t)3 * gw.H * gw.m);
+    l.b.kcol = c.take<float>((size_t)2 * gw.H * gw.L);
+    l.b.prow = c.take<float2>((size_t)3 * gw.m * gw.H);
     l.b.pot = c.take<float4>((size_t)gw.m * gw.m);
-    for (int k = 1; k <= kw; ++k) l.tw[k] = c.take<float2>((size_t)make_geom(p->n_int, k).L / 2);
+    l.b.sched = c.take<int2>((size_t)4 * edge_blocks_bound(n, nnz));
+    for (int k = 1; k <= kw; ++k) l.tw[k] = c.take<float2>((size_t)make_geom(p->n_int, k).L);
     *bytes = (c.off + 255) & ~(size_t)255;
     return l;
 }
 
 bool finite_f(float v) { return std::isfinite(v); }
+
+// Edge-pass schedule: rows with more than kGroupEdges entries get a block
+// each (slot 0 = {row, -1}); the other rows are cut, in order, into wave
+// groups of at most kGroupRows rows and kGroupEdges entries, four groups per
+// block (slot = {first row, rows}; {0, 0} = idle wave). Heavy blocks first.
+std::vector<int2> build_edge_schedule(const std::vector<int>& rp, int n) {
+    std::vector<int2> heavy, groups;
+    int r = 0;
+    while (r < n) {
+        const int d = rp[r + 1] - rp[r];
+        if (d > kGroupEdges) {
+            heavy.push_back(make_int2(r, -1));
+            ++r;
+            continue;
+        }
+        const int r0 = r;
+        int edges = 0, cnt = 0;
+        while (r < n && cnt < kGroupRows) {
+            const int dd = rp[r + 1] - rp[r];
+            if (dd > kGroupEdges || edges + dd > kGroupEdges) break;
+            edges += dd;
+            ++cnt;
+            ++r;
+        }
+        groups.push_back(make_int2(r0, cnt));
+    }
+    std::vector<int2> out;
+    out.reserve(4 * (heavy.size() + (groups.size() + 3) / 4));
+    for (const int2& hrow : heavy) {
+        out.push_back(hrow);
+        for (int k = 0; k < 3; ++k) out.push_back(make_int2(0, 0));
+    }
+    for (size_t gi = 0; gi < groups.size(); gi += 4)
+        for (size_t k = 0; k < 4; ++k) out.push_back(gi + k < groups.size() ? groups[gi + k] : make_int2(0, 0));
+    return out;
+}
 
 tfdp_status check_hip(hipError_t e, const char* what) {
     if (e == hipSuccess) return TFDP_OK;
@@ -163,7 +197,7 @@ struct PhaseTimer {
             }
             h->ev_pool.push_back(e);
         }
-        hipEventRecord(h->ev_pool[h->ev_used++], s);
+        (void)hipEventRecord(h->ev_pool[h->ev_used++], s);
         h->ev_stream = s;
     }
 };
@@ -174,22 +208,23 @@ Bufs bufs_for(const tfdp_layout* h, int k) {
     return b;
 }
 
-// One evaluation of the interpolated repulsion up to the grid potentials.
-void enqueue_grid(tfdp_layout* h, const float2* pos, const Bufs& b, const Geom& g, hipStream_t s) {
-    { PhaseTimer pt(h, PH_BIN_COUNT, s); launch_bin_count(pos, b, s); }
-    { PhaseTimer pt(h, PH_BIN_SCAN, s); launch_bin_scan(b, s); }
+// One evaluation of the interpolated repulsion up to the grid potentials;
+// the box comes from extremes slot set `set`, set ^ 1 is reset for the
+// update that follows.
+void enqueue_grid(tfdp_layout* h, const float2* pos, const Bufs& b, const Geom& g, int set, hipStream_t s) {
+    { PhaseTimer pt(h, PH_BIN_COUNT, s); launch_bin_count(pos, b, set, s); }
+    { PhaseTimer pt(h, PH_BIN_SCAN, s); launch_bin_scan(b, set ^ 1, s); }
     { PhaseTimer pt(h, PH_BIN_SCATTER, s); launch_bin_scatter(pos, b, s); }
-    { PhaseTimer pt(h, PH_SPREAD, s); launch_spread(b, g, s); }
-    { PhaseTimer pt(h, PH_ROWFFT, s); launch_rowfft(b, g, h->p.gamma, s); }
+    { PhaseTimer pt(h, PH_SPREAD, s); launch_spread_rows(b, g, h->p.gamma, s); }
     { PhaseTimer pt(h, PH_COLCONV, s); launch_colconv(b, g, s); }
     { PhaseTimer pt(h, PH_ROWIFFT, s); launch_rowifft(b, g, s); }
 }
 
-void enqueue_box(tfdp_layout* h, const float2* pos, hipStream_t s) {
+// Extremes of `pos` into slot set `set` (both sets reset first).
+void enqueue_box(tfdp_layout* h, const float2* pos, int set, hipStream_t s) {
     PhaseTimer pt(h, PH_BOX, s);
     launch_box_begin(h->lay.b.st, h->t, s);
-    launch_box_reduce(pos, h->n, h->lay.b.st, s);
-    launch_box_finalize(h->lay.b.st, h->p.n_int, 0, s);
+    launch_box_reduce(pos, h->n, h->lay.b.st, set, s);
 }
 
 int k_at(const tfdp_params& p, int t) {
@@ -269,7 +304,7 @@ tfdp_status tfdp_params_validate(const tfdp_params* p, int32_t n, int64_t nnz) {
 size_t tfdp_workspace_size(int32_t n, int64_t nnz, const tfdp_params* p) {
     if (tfdp_params_validate(p, n, nnz) != TFDP_OK) return 0;
     size_t bytes = 0;
-    carve(nullptr, n, p, &bytes);
+    carve(nullptr, n, nnz, p, &bytes);
     return bytes;
 }
 
@@ -289,7 +324,7 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
         return TFDP_ERR_INVALID_ARG;
     }
     size_t need = 0;
-    carve(nullptr, n, p, &need);
+    carve(nullptr, n, nnz, p, &need);
     if (!d_ws || ws_bytes < need) {
         set_msg("workspace too small: need " + std::to_string(need) + " bytes");
         return TFDP_ERR_WORKSPACE;
@@ -317,7 +352,7 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
     h->ev_used = 0;
     h->ev_stream = nullptr;
     size_t bytes = 0;
-    h->lay = carve(d_ws, n, p, &bytes);
+    h->lay = carve(d_ws, n, nnz, p, &bytes);
 
     DevState* dst = h->lay.b.st;
     st = check_hip(hipMemsetAsync(dst, 0, sizeof(DevState), stream), "hipMemsetAsync");
@@ -332,6 +367,23 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
     if (st == TFDP_OK && hs.csr_bad) {
         set_msg("invalid CSR: row_ptr must start at 0, be monotone and end at nnz; columns in [0, n) without self-loops");
         st = TFDP_ERR_INVALID_ARG;
+    }
+    if (st == TFDP_OK) {
+        std::vector<int> rp((size_t)n + 1);
+        st = check_hip(hipMemcpy(rp.data(), d_row_ptr, rp.size() * sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy");
+        if (st == TFDP_OK) {
+            std::vector<int2> sched = build_edge_schedule(rp, n);
+            h->lay.b.edge_blocks = (int)(sched.size() / 4);
+            if ((long long)h->lay.b.edge_blocks > edge_blocks_bound(n, nnz)) {
+                set_msg("internal: edge schedule exceeds its bound");
+                st = TFDP_ERR_WORKSPACE;
+            } else {
+                st = check_hip(hipMemcpyAsync(const_cast<int2*>(h->lay.b.sched), sched.data(),
+                                              sched.size() * sizeof(int2), hipMemcpyHostToDevice, stream),
+                               "hipMemcpyAsync");
+                if (st == TFDP_OK) st = check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+            }
+        }
     }
     if (st != TFDP_OK) {
         delete h;
@@ -352,20 +404,21 @@ tfdp_status tfdp_layout_step(tfdp_layout* h, int32_t iters, hipStream_t s) {
     const ModelArgs a = model_args(h);
     float2* cur = reinterpret_cast<float2*>(h->pos);
     float2* alt = h->lay.pos_alt;
-    enqueue_box(h, cur, s);
+    enqueue_box(h, cur, h->t & 1, s);
     for (int it = 0; it < iters; ++it) {
         const int k = k_at(h->p, h->t);
         if (k == 0) {
             PhaseTimer pt(h, PH_BRUTE, s);
-            launch_brute(cur, alt, h->row_ptr, h->col_idx, h->n, h->lay.b.st, a, nullptr, nullptr, nullptr, s);
+            launch_brute(cur, alt, h->row_ptr, h->col_idx, h->n, h->lay.b.st, a, h->t, nullptr, nullptr,
+                         nullptr, s);
         } else {
             const Bufs b = bufs_for(h, k);
             const Geom g = make_geom(h->p.n_int, k);
-            enqueue_grid(h, cur, b, g, s);
+            const int set = h->t & 1;
+            enqueue_grid(h, cur, b, g, set, s);
             PhaseTimer pt(h, PH_GATHER, s);
-            launch_gather(cur, alt, h->row_ptr, h->col_idx, b, g, a, nullptr, nullptr, nullptr, s);
+            launch_gather(cur, alt, h->row_ptr, h->col_idx, b, g, a, set ^ 1, nullptr, nullptr, nullptr, s);
         }
-        launch_box_finalize(h->lay.b.st, h->p.n_int, 1, s);
         float2* tmp = cur;
         cur = alt;
         alt = tmp;
@@ -397,14 +450,14 @@ tfdp_status tfdp_layout_forces(tfdp_layout* h, const float* d_pos_in, int32_t k,
     float2* ft = reinterpret_cast<float2*>(d_f_tot);
     if (k == 0) {
         PhaseTimer pt(h, PH_BRUTE, s);
-        launch_brute(pos, nullptr, h->row_ptr, h->col_idx, h->n, h->lay.b.st, a, fr, fa, ft, s);
+        launch_brute(pos, nullptr, h->row_ptr, h->col_idx, h->n, h->lay.b.st, a, h->t, fr, fa, ft, s);
     } else {
-        enqueue_box(h, pos, s);
+        enqueue_box(h, pos, 0, s);
         const Bufs b = bufs_for(h, k);
         const Geom g = make_geom(h->p.n_int, k);
-        enqueue_grid(h, pos, b, g, s);
+        enqueue_grid(h, pos, b, g, 0, s);
         PhaseTimer pt(h, PH_GATHER, s);
-        launch_gather(pos, nullptr, h->row_ptr, h->col_idx, b, g, a, fr, fa, ft, s);
+        launch_gather(pos, nullptr, h->row_ptr, h->col_idx, b, g, a, 1, fr, fa, ft, s);
     }
     return check_hip(hipGetLastError(), "kernel launch");
 }
@@ -461,7 +514,7 @@ tfdp_status tfdp_layout_sync_status(tfdp_layout* h, hipStream_t s) {
     if (st != TFDP_OK) return st;
     if (flag) {
         int zero = 0;
-        hipMemcpy(&dst->nonfinite, &zero, sizeof(int), hipMemcpyHostToDevice);
+        (void)hipMemcpy(&dst->nonfinite, &zero, sizeof(int), hipMemcpyHostToDevice);
         set_msg("a position became NaN or infinite");
         return TFDP_ERR_NONFINITE;
     }
@@ -470,7 +523,7 @@ tfdp_status tfdp_layout_sync_status(tfdp_layout* h, hipStream_t s) {
 
 void tfdp_layout_destroy(tfdp_layout* h) {
     if (!h) return;
-    for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     delete h;
 }
 

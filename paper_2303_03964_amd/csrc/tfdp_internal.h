@@ -8,11 +8,12 @@
 namespace tfdp {
 
 constexpr int kThreads = 256;        // threads per block of the node and FFT kernels
-constexpr int kBinChunk = 4096;      // nodes per block of the binning passes
-constexpr int kSpreadChunk = 2048;   // nodes per block of the spreading pass
+constexpr int kBinChunk = 1024;      // nodes per block of the binning passes
+constexpr int kBoxSlots = 64;        // slots of the box extremes (one 128-byte line each)
 constexpr int kMaxL = 2048;          // largest FFT length per side
 constexpr int kMaxNInt = 1024;       // largest number of intervals per side
-constexpr int kColBytes = 36 * kMaxL;  // LDS of one column-pass block
+constexpr int kGroupEdges = 512;     // CSR entries of one wave group of the edge pass
+constexpr int kGroupRows = 64;       // rows of one wave group of the edge pass
 
 // Square box of the current positions, in float64 (lo, side W, interval h = W / N_int).
 struct Box {
@@ -21,7 +22,11 @@ struct Box {
 
 // Device-resident per-handle state.
 struct DevState {
-    unsigned int mm[4];   // order-preserving encodings: min x, min y, max x, max y
+    // order-preserving encodings of min x, min y, max x, max y; two sets used
+    // by alternate iterations (one is read while the next is reset and
+    // filled); blocks commit to slot blockIdx % kBoxSlots so that no single
+    // address sees thousands of device-scope atomics per launch
+    unsigned int mm[2][kBoxSlots][32];
     int t;                // iteration index used by the update (cooling)
     int nonfinite;        // set when a computed position is NaN or infinite
     int csr_bad;          // set by the CSR check at init
@@ -44,17 +49,17 @@ struct Bufs {
     int n;
     int n_int;
     int nblk;            // blocks of the binning passes
-    int max_chunks;      // upper bound of spreading blocks
     float2* spos;        // positions sorted by interval row
     int* blkcnt;         // [n_int][nblk] counts, then exclusive offsets
     int* bucket_cnt;     // [n_int]
     int* bucket_start;   // [n_int + 1]
-    int* chunk_start;    // [n_int + 1]
-    float* spart;        // [max_chunks][k][M][3] partial grids
-    float2* qrow;        // [3][M][H] row spectra (charges, then potentials)
-    float* krow;         // [2][L][H] kernel row spectra (real)
+    float2* qcol;        // [3][H][M] charge row spectra, column-major
+    float* kcol;         // [2][H][L] kernel row spectra (real), column-major
+    float2* prow;        // [3][M][H] potential row spectra after the column pass
     float4* pot;         // [M][M] (phi_1, G_x, G_y, 0)
-    const float2* tw;    // twiddles for this L: exp(-2 pi i j / L), j < L/2
+    const float2* tw;    // twiddles for this L: exp(-2 pi i j / L), j < L
+    const int2* sched;   // [4 * edge_blocks] edge-pass schedule (see node_forces.hip)
+    int edge_blocks;
     DevState* st;
 };
 
@@ -66,21 +71,23 @@ struct ModelArgs {
 
 // ---- launchers (each defined next to its kernels) ----
 void launch_box_begin(DevState* st, int t, hipStream_t s);
-void launch_box_reduce(const float2* pos, int n, DevState* st, hipStream_t s);
-void launch_box_finalize(DevState* st, int n_int, int advance, hipStream_t s);
-void launch_bin_count(const float2* pos, const Bufs& b, hipStream_t s);
-void launch_bin_scan(const Bufs& b, hipStream_t s);
+void launch_box_reduce(const float2* pos, int n, DevState* st, int set, hipStream_t s);
+void launch_bin_count(const float2* pos, const Bufs& b, int set, hipStream_t s);
+void launch_bin_scan(const Bufs& b, int reset_set, hipStream_t s);
 void launch_bin_scatter(const float2* pos, const Bufs& b, hipStream_t s);
-void launch_spread(const Bufs& b, const Geom& g, hipStream_t s);
-void launch_rowfft(const Bufs& b, const Geom& g, float gamma, hipStream_t s);
+void launch_spread_rows(const Bufs& b, const Geom& g, float gamma, hipStream_t s);
 void launch_colconv(const Bufs& b, const Geom& g, hipStream_t s);
 void launch_rowifft(const Bufs& b, const Geom& g, hipStream_t s);
 void launch_twiddles(float2* tw, int L, hipStream_t s);
 void launch_gather(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx,
-                   const Bufs& b, const Geom& g, const ModelArgs& a,
+                   const Bufs& b, const Geom& g, const ModelArgs& a, int set,
                    float2* f_rep, float2* f_att, float2* f_tot, hipStream_t s);
+// Upper bound of edge-pass blocks for n rows and nnz CSR entries.
+inline long long edge_blocks_bound(long long n, long long nnz) {
+    return (n + 3) / 4 + nnz / (kGroupEdges + 1) + 1;
+}
 void launch_brute(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx,
-                  int n, DevState* st, const ModelArgs& a,
+                  int n, DevState* st, const ModelArgs& a, int t,
                   float2* f_rep, float2* f_att, float2* f_tot, hipStream_t s);
 void launch_csr_check(const int* row_ptr, const int* col_idx, int n, long long nnz,
                       DevState* st, hipStream_t s);
@@ -127,6 +134,36 @@ __device__ __forceinline__ void lagrange(double t, double* w) {
     }
 }
 
+// Square box from the encoded extremes of one slot set (same float64
+// operations as the oracle): side W = max(x range, y range) centred on the
+// mid-ranges, W = 1 if nothing finite was seen or all points coincide.
+__device__ __forceinline__ Box box_from_extremes(unsigned int a0, unsigned int a1, unsigned int a2,
+                                                 unsigned int a3, int n_int) {
+#pragma clang fp contract(off)
+    Box b;
+    if (a0 == 0xffffffffu) {
+        b.lo_x = 0.0;
+        b.lo_y = 0.0;
+        b.w = 1.0;
+    } else {
+        const double xmin = (double)dec_ord(a0);
+        const double ymin = (double)dec_ord(a1);
+        const double xmax = (double)dec_ord(a2);
+        const double ymax = (double)dec_ord(a3);
+        const double rx = xmax - xmin;
+        const double ry = ymax - ymin;
+        double w = rx >= ry ? rx : ry;
+        if (!(w > 0.0)) w = 1.0;
+        const double cx = (xmin + xmax) / 2.0;
+        const double cy = (ymin + ymax) / 2.0;
+        b.lo_x = cx - w / 2.0;
+        b.lo_y = cy - w / 2.0;
+        b.w = w;
+    }
+    b.h = b.w / (double)n_int;
+    return b;
+}
+
 // Offsets delta_j = (t - tau_j) h of a point from the K nodes of its interval.
 template <int K>
 __device__ __forceinline__ void node_deltas(double t, double h, double* d) {
@@ -141,7 +178,7 @@ __device__ __forceinline__ void node_deltas(double t, double h, double* d) {
 // Block-wide min/max of the given extremes, committed to st->mm with one
 // set of integer atomics per block (blockDim.x a multiple of 64, <= kThreads).
 __device__ __forceinline__ void block_minmax_commit(float xmin, float ymin, float xmax, float ymax,
-                                                    DevState* st) {
+                                                    DevState* st, int set) {
     // wave reduction, then one lane per wave commits with atomics
     for (int off = 32; off > 0; off >>= 1) {
         xmin = fminf(xmin, __shfl_xor(xmin, off));
@@ -167,10 +204,11 @@ __device__ __forceinline__ void block_minmax_commit(float xmin, float ymin, floa
             ymax = fmaxf(ymax, red[3][i]);
         }
         if (xmin <= xmax) {  // at least one finite position in the block
-            atomicMin(&st->mm[0], enc_ord(xmin));
-            atomicMin(&st->mm[1], enc_ord(ymin));
-            atomicMax(&st->mm[2], enc_ord(xmax));
-            atomicMax(&st->mm[3], enc_ord(ymax));
+            unsigned int* slot = st->mm[set][blockIdx.x % kBoxSlots];
+            atomicMin(slot + 0, enc_ord(xmin));
+            atomicMin(slot + 1, enc_ord(ymin));
+            atomicMax(slot + 2, enc_ord(xmax));
+            atomicMax(slot + 3, enc_ord(ymax));
         }
     }
 }
