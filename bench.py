@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations (0: about 15 s of work)")
     ap.add_argument("--repeats", type=int, default=1, help="timed repeats; value is the median")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="copy this many MiB device-to-device once before the run (a plain copy kernel "
+                         "of known size for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -133,6 +136,14 @@ def main():
     params = T.tfdp_params_default(n_int=w.n_int, total_iters=w.iters, k_mode=-1)
     lay = T.Layout(g.row_ptr, g.col_idx, pos0.clone(), params, device=dev)
     stream = torch.cuda.current_stream()
+    if args.calib_copy_mb > 0:
+        nel = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def reset():
         lay.pos.copy_(pos0)

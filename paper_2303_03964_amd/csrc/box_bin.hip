@@ -161,7 +161,8 @@ __global__ __launch_bounds__(kThreads) void k_bin_scan(Bufs b, int reset_set) {
 }
 
 // Stable scatter of the positions into interval-row buckets. Block 0 also
-// publishes the bucket starts.
+// publishes the bucket starts and the first spreading chunk of each row
+// (rows split into chunks of kSpreadChunk nodes, at least one per row).
 __global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restrict__ pos, Bufs b) {
     extern __shared__ int sm[];
     const int n_int = b.n_int;
@@ -171,19 +172,30 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restri
     int* scan_lds = wcnt + 4 * n_int;  // [kThreads/64 + 1]
     // bucket starts: exclusive scan over rows (n_int <= 1024, four per thread)
     int carry = 0;
+    int chunk_carry = 0;
     for (int c0 = 0; c0 < n_int; c0 += blockDim.x) {
         const int c = c0 + threadIdx.x;
         const int cnt = c < n_int ? b.bucket_cnt[c] : 0;
-        int tot;
+        const int chunks = c < n_int ? max(1, (cnt + kSpreadChunk - 1) / kSpreadChunk) : 0;
+        int tot, tot2;
         const int ex = block_exclusive_scan(cnt, scan_lds, tot);
+        const int ex2 = block_exclusive_scan(chunks, scan_lds, tot2);
         if (c < n_int) {
             base[c] = carry + ex + b.blkcnt[(size_t)c * b.nblk + blockIdx.x];
             run[c] = 0;
-            if (blockIdx.x == 0) b.bucket_start[c] = carry + ex;
+            if (blockIdx.x == 0) {
+                b.bucket_start[c] = carry + ex;
+                b.chunk_start[c] = chunk_carry + ex2;
+                for (int k = 0; k < chunks; ++k) b.chunk_row[chunk_carry + ex2 + k] = c;
+            }
         }
         carry += tot;
+        chunk_carry += tot2;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) b.bucket_start[n_int] = carry;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        b.bucket_start[n_int] = carry;
+        b.chunk_start[n_int] = chunk_carry;
+    }
     for (int i = threadIdx.x; i < 4 * n_int; i += blockDim.x) wcnt[i] = 0;
     __syncthreads();
 

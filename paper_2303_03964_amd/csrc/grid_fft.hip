@@ -14,17 +14,19 @@
 //
 // The linear convolution is embedded in an L x L circulant (L = power of two
 // >= 2M) and computed with 2D FFTs:
-//   spread_rows  one block per interval row: the nodes of the row (sorted by
-//                the binning pass) accumulate in per-wave LDS copies of the
-//                row's k grid rows, which are summed in a fixed order and
-//                real-FFT'd (two real rows per complex FFT); further blocks
-//                FFT the kernel rows (K + i H_x packed). Spectra are stored
-//                column-major for the column pass.
-//   colconv      one block per group of spectrum columns: five forward
-//                column FFTs (kernel pair, three charges), spectral products,
-//                three inverse column FFTs; results stored row-major.
-//   rowifft      inverse real FFTs of the potential rows, (phi_1, G_x, G_y)
-//                written per grid node.
+//   spread   one block per chunk of an interval row's nodes (sorted by the
+//            binning pass): per-wave LDS copies of the row's k grid rows,
+//            summed in a fixed order, written as one partial row set
+//   rowfft   RB grid rows per block: partial rows summed straight into the
+//            FFT inputs (q1 + i qdx per row, qdy of two rows in one complex
+//            transform), row spectra stored column-major in tiles of RB
+//            consecutive rows (one cache line per column); further blocks do
+//            the same for the kernel rows (K + i H_x packed)
+//   colconv  one block per group of spectrum columns: five forward column
+//            FFTs (kernel pair, three charges), spectral products, three
+//            inverse column FFTs; contiguous column reads and writes
+//   rowifft  RB potential rows per block from column tiles: inverse real
+//            FFTs, (phi_1, G_x, G_y) written per grid node.
 //
 // Every FFT is a task of one wave: a Stockham autosort FFT with radix-8
 // passes (and one radix-4 or radix-2 pass), each lane holding its points in
@@ -198,33 +200,54 @@ __device__ __forceinline__ int signed_offset(int r, int M, int L) {
     return r < M ? r : (r > L - M ? r - L : INT_MIN);
 }
 
-// ----------------------------------------------------------------- spread + row FFTs
+// Rows per block of the row passes: RB grid rows make 1.5 RB transforms;
+// RBK kernel rows make RBK transforms. Column tiles of RB (RBK) consecutive
+// rows are stored with one RB * 8-byte write per column; pairs of logical
+// blocks share an XCD so that each 128-byte line is filled from one L2.
+template <int LOGL>
+struct RowTile {
+    static constexpr int RB = LOGL <= 10 ? 8 : 4;
+    static constexpr int RBK = 8;
+    static constexpr int THREADS = 512;
+};
 
-// Block size: nw waves (host-chosen, <= 16; <= 8 for L = 2048 so that the
-// 2048-point wave FFT keeps its points in registers).
+// Allow dynamic LDS beyond 64 KB (gfx950 has 160 KB per workgroup); once per kernel.
+template <class Kern>
+static void allow_big_lds(Kern k) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+}
+
+// ----------------------------------------------------------------- spread + kernel rows
+
+// Blocks [0, max_chunks): one chunk of <= kSpreadChunk sorted nodes of one
+// interval row each; per-wave LDS copies of the row's K grid rows (a fixed
+// subset and order of nodes per copy, hence a reproducible sum), summed in
+// wave order and written as one contiguous partial row set.
+// Blocks past max_chunks: RBK kernel rows each, FFT over a of
+// K(a, b) + i H_x(a, b); the result is real, its even part the row spectrum of
+// K, minus its odd part the row spectrum of H_x divided by i.
 template <int K, int LOGL>
-__global__ __launch_bounds__(LOGL >= 11 ? 512 : 1024) void k_spread_rows(Bufs b, Geom g, float gamma, int nw) {
+__global__ __launch_bounds__(512) void k_spread(Bufs b, Geom g, float gamma, int nw, int nkb) {
     extern __shared__ float4 smem4[];
-    float* sm = reinterpret_cast<float*>(smem4);
-    constexpr int L = 1 << LOGL;
-    constexpr int logL = LOGL;
-    constexpr int F = task_ffts<LOGL>();
-    constexpr int TL = F * L;  // points per task
-    const int M = g.m, H = g.H;
+    const int M = g.m;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int n_int = b.n_int;
-    if ((int)blockIdx.x < n_int) {
-        const int cy = blockIdx.x;
+    if ((int)blockIdx.x < b.max_chunks) {
+        float* acc = reinterpret_cast<float*>(smem4);  // [nw][K][M][3]
         const int per = K * M * 3;
-        for (int i = threadIdx.x; i < nw * per; i += blockDim.x) sm[i] = 0.f;
+        const int blk = blockIdx.x;
+        const int n_int = b.n_int;
+        const int nchunks = b.chunk_start[n_int];
+        const int cy = b.chunk_row[blk];
+        if (blk >= nchunks) return;
+        const int beg = b.bucket_start[cy] + (blk - b.chunk_start[cy]) * kSpreadChunk;
+        const int end = min(beg + kSpreadChunk, b.bucket_start[cy + 1]);
+        for (int i = threadIdx.x; i < nw * per; i += blockDim.x) acc[i] = 0.f;
         __syncthreads();
         const Box bx = b.st->box;
-        float* my = sm + w * per;
-        const int beg = b.bucket_start[cy], end = b.bucket_start[cy + 1];
-        const int stride = nw * 64;
-        // wave w takes nodes beg + w*64 + lane + it*stride: a fixed subset
-        // and order per wave accumulator, hence a reproducible sum
+        float* my = acc + w * per;
+        const int stride = blockDim.x;
         for (int j0 = beg + threadIdx.x; j0 < end; j0 += 4 * stride) {
             float2 pp[4];
 #pragma unroll
@@ -260,131 +283,178 @@ __global__ __launch_bounds__(LOGL >= 11 ? 512 : 1024) void k_spread_rows(Bufs b,
             }
         }
         __syncthreads();
+        float* out = b.spart + (size_t)blk * per;
         for (int i = threadIdx.x; i < per; i += blockDim.x) {
-            float v = sm[i];
-            for (int ww = 1; ww < nw; ++ww) v += sm[ww * per + i];
-            sm[i] = v;
+            float v = acc[i];
+            for (int ww = 1; ww < nw; ++ww) v += acc[ww * per + i];
+            out[i] = v;
         }
-        __syncthreads();
-        // 2K real rows packed into K complex pairs: Z = q1 + i qdx, Z' = qdy
-        const int nfft = 2 * K;
-        const int ntask = (nfft + F - 1) / F;
-        float2* z = reinterpret_cast<float2*>(sm + ((per + 3) & ~3));
-        for (int i = threadIdx.x; i < ntask * TL; i += blockDim.x) {
-            const int f = i >> logL, x = i & (L - 1);
-            float2 v = make_float2(0.f, 0.f);
-            if (f < nfft && x < M) {
-                const float* e = sm + ((f >> 1) * M + x) * 3;
-                v = (f & 1) ? make_float2(e[2], 0.f) : make_float2(e[0], e[1]);
-            }
-            z[i] = v;
-        }
-        __syncthreads();
-        for (int tk = w; tk < ntask; tk += nw) wave_fft<LOGL, false>(z + tk * TL, b.tw, lane);
-        __syncthreads();
-        for (int i = threadIdx.x; i < K * H; i += blockDim.x) {
-            const int bb = i / H, u = i % H;
-            const float2* z1 = z + (2 * bb) * L;
-            const float2* z2 = z1 + L;
-            const float2 a = z1[u];
-            const float2 c = z1[(L - u) & (L - 1)];
-            const int y = cy * K + bb;
-            // Z = FFT(q1 + i qdx): Q1 = (Z(u) + conj Z(L-u))/2, Qdx = (Z(u) - conj Z(L-u))/(2i)
-            b.qcol[((size_t)0 * H + u) * M + y] = make_float2(0.5f * (a.x + c.x), 0.5f * (a.y - c.y));
-            b.qcol[((size_t)1 * H + u) * M + y] = make_float2(0.5f * (a.y + c.y), -0.5f * (a.x - c.x));
-            b.qcol[((size_t)2 * H + u) * M + y] = z2[u];
-        }
-    } else {
-        // kernel rows r: FFT over a of K(a, b) + i H_x(a, b); the result is
-        // real, its even part is the row spectrum of K, minus its odd part
-        // the row spectrum of H_x divided by i
-        const int tk = (blockIdx.x - n_int) * nw + w;
-        const int r0 = tk * F;
-        if (r0 >= L) return;  // whole wave idle (uniform per wave)
-        float2* z = reinterpret_cast<float2*>(sm) + w * TL;
-        const Box bx = b.st->box;
-        const double s = bx.h / (double)K;
-        for (int i = lane; i < TL; i += 64) {
-            const int r = r0 + (i >> logL), a = i & (L - 1);
+        return;
+    }
+    constexpr int L = 1 << LOGL;
+    constexpr int F = task_ffts<LOGL>();
+    constexpr int TL = F * L;
+    constexpr int RBK = RowTile<LOGL>::RBK;
+    constexpr int NKT = (RBK + F - 1) / F;
+    const int lb = xcd_pair_block((int)blockIdx.x - b.max_chunks, nkb);
+    if (lb < 0) return;
+    float2* z = reinterpret_cast<float2*>(smem4);
+    const int H = g.H;
+    const int r0 = lb * RBK;
+    const Box bx = b.st->box;
+    const double s = bx.h / (double)K;
+    for (int i = threadIdx.x; i < NKT * TL; i += blockDim.x) {
+        const int f = i >> LOGL, a = i & (L - 1);
+        const int r = r0 + f;
+        float2 v = make_float2(0.f, 0.f);
+        if (f < RBK && r < L) {
             const int bt = signed_offset(r, M, L), at = signed_offset(a, M, L);
-            float2 v = make_float2(0.f, 0.f);
             if (bt != INT_MIN && at != INT_MIN) {
                 const double d2 = s * s * ((double)at * at + (double)bt * bt);
                 const double kk = (gamma == 2.0f) ? 1.0 / ((1.0 + d2) * (1.0 + d2)) : pow(1.0 + d2, -(double)gamma);
                 v = make_float2((float)kk, (float)(kk * s * (double)at));
             }
-            z[i] = v;
         }
-        __builtin_amdgcn_wave_barrier();
-        wave_fft<LOGL, false>(z, b.tw, lane);
-        for (int i = lane; i < F * H; i += 64) {
-            const int rr = i / H, u = i % H;
-            const float2* zr = z + rr * L;
-            const float a = zr[u].x;
-            const float c = zr[(L - u) & (L - 1)].x;
-            const int r = r0 + rr;
-            b.kcol[((size_t)0 * H + u) * L + r] = 0.5f * (a + c);
-            b.kcol[((size_t)1 * H + u) * L + r] = -0.5f * (a - c);
-        }
+        z[i] = v;
     }
-}
-
-static size_t spread_need(const Geom& g, int nw) {
-    const size_t per = (size_t)g.k * g.m * 3 * sizeof(float);
-    const int L = g.L;
-    const int F = L < 512 ? 512 / L : 1;
-    const size_t TL = (size_t)F * L * sizeof(float2);
-    const int ntask = (2 * g.k + F - 1) / F;
-    size_t need = (size_t)nw * per;
-    const size_t fft = ((per + 15) & ~(size_t)15) + ntask * TL;
-    if (fft > need) need = fft;
-    const size_t krow = (size_t)nw * TL;
-    if (krow > need) need = krow;
-    return need;
-}
-
-static int spread_waves(const Geom& g) {
-    int nw = g.L >= 2048 ? 8 : 16;
-    while (nw > 4 && spread_need(g, nw) > 150 * 1024) nw >>= 1;
-    return nw;
-}
-
-// Allow dynamic LDS beyond 64 KB (gfx950 has 160 KB per workgroup); once per kernel.
-template <class Kern>
-static void allow_big_lds(Kern k) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
+    __syncthreads();
+    for (int tk = w; tk < NKT; tk += nw) wave_fft<LOGL, false>(z + tk * TL, b.tw, lane);
+    __syncthreads();
+    for (int i = threadIdx.x; i < H * RBK; i += blockDim.x) {
+        const int f = i % RBK, u = i / RBK;
+        const int r = r0 + f;
+        if (r >= L) continue;
+        const float2* zr = z + f * L;
+        const float a = zr[u].x;
+        const float c = zr[(L - u) & (L - 1)].x;
+        b.kcol[(size_t)u * L + r] = make_float2(0.5f * (a + c), -0.5f * (a - c));
+    }
 }
 
 template <int K, int LOGL>
-static void launch_spread_rows_t(const Bufs& b, const Geom& g, float gamma, hipStream_t s) {
-    static const bool once = (allow_big_lds(k_spread_rows<K, LOGL>), true);
+static void launch_spread_t(const Bufs& b, const Geom& g, float gamma, hipStream_t s) {
+    static const bool once = (allow_big_lds(k_spread<K, LOGL>), true);
     (void)once;
-    const int nw = spread_waves(g);
-    const size_t lds = spread_need(g, nw);
+    const size_t per = (size_t)K * g.m * 3 * sizeof(float);
+    int nw = 8;
+    while (nw > 1 && nw * per > 128 * 1024) nw >>= 1;
     constexpr int F = task_ffts<LOGL>();
-    const int ktasks = g.L / F;
-    const int blocks = b.n_int + (ktasks + nw - 1) / nw;
-    hipLaunchKernelGGL((k_spread_rows<K, LOGL>), dim3(blocks), dim3(nw * 64), lds, s, b, g, gamma, nw);
+    constexpr int RBK = RowTile<LOGL>::RBK;
+    const size_t kern = (size_t)((RBK + F - 1) / F) * F * (1 << LOGL) * sizeof(float2);
+    const size_t lds = nw * per > kern ? nw * per : kern;
+    const int nkb = (g.L + RBK - 1) / RBK;
+    hipLaunchKernelGGL((k_spread<K, LOGL>), dim3(b.max_chunks + xcd_pair_grid(nkb)), dim3(nw * 64), lds, s, b, g,
+                       gamma, nw, nkb);
 }
 
 template <int K>
-static void launch_spread_rows_k(const Bufs& b, const Geom& g, float gamma, hipStream_t s) {
+static void launch_spread_k(const Bufs& b, const Geom& g, float gamma, hipStream_t s) {
     switch (g.logL) {
-        case 6: launch_spread_rows_t<K, 6>(b, g, gamma, s); break;
-        case 7: launch_spread_rows_t<K, 7>(b, g, gamma, s); break;
-        case 8: launch_spread_rows_t<K, 8>(b, g, gamma, s); break;
-        case 9: launch_spread_rows_t<K, 9>(b, g, gamma, s); break;
-        case 10: launch_spread_rows_t<K, 10>(b, g, gamma, s); break;
-        default: launch_spread_rows_t<K, 11>(b, g, gamma, s); break;
+        case 6: launch_spread_t<K, 6>(b, g, gamma, s); break;
+        case 7: launch_spread_t<K, 7>(b, g, gamma, s); break;
+        case 8: launch_spread_t<K, 8>(b, g, gamma, s); break;
+        case 9: launch_spread_t<K, 9>(b, g, gamma, s); break;
+        case 10: launch_spread_t<K, 10>(b, g, gamma, s); break;
+        default: launch_spread_t<K, 11>(b, g, gamma, s); break;
     }
 }
 
-void launch_spread_rows(const Bufs& b, const Geom& g, float gamma, hipStream_t s) {
+void launch_spread(const Bufs& b, const Geom& g, float gamma, hipStream_t s) {
     switch (g.k) {
-        case 1: launch_spread_rows_k<1>(b, g, gamma, s); break;
-        case 2: launch_spread_rows_k<2>(b, g, gamma, s); break;
-        default: launch_spread_rows_k<3>(b, g, gamma, s); break;
+        case 1: launch_spread_k<1>(b, g, gamma, s); break;
+        case 2: launch_spread_k<2>(b, g, gamma, s); break;
+        default: launch_spread_k<3>(b, g, gamma, s); break;
+    }
+}
+
+// ----------------------------------------------------------------- row FFTs of the charges
+
+// RB grid rows per (logical) block. Transforms of row pair q:
+// 3q = q1 + i qdx (row 2q), 3q+1 = qdy(2q) + i qdy(2q+1), 3q+2 = q1 + i qdx (row 2q+1).
+template <int LOGL>
+__global__ __launch_bounds__(RowTile<LOGL>::THREADS) void k_rowfft(Bufs b, Geom g, int nqb) {
+    extern __shared__ float2 z[];
+    constexpr int L = 1 << LOGL;
+    constexpr int F = task_ffts<LOGL>();
+    constexpr int TL = F * L;
+    constexpr int RB = RowTile<LOGL>::RB;
+    constexpr int NQT = (3 * RB / 2 + F - 1) / F;
+    const int lb = xcd_pair_block(blockIdx.x, nqb);
+    if (lb < 0) return;
+    const int M = g.m, H = g.H, K = g.k;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int nwav = blockDim.x >> 6;
+    const int y0 = lb * RB;
+    const int per = K * M * 3;
+    for (int i = threadIdx.x; i < NQT * TL; i += blockDim.x) z[i] = make_float2(0.f, 0.f);
+    __syncthreads();
+    for (int i = threadIdx.x; i < RB * M; i += blockDim.x) {
+        const int r = i / M, x = i % M;
+        const int y = y0 + r;
+        if (y >= M) continue;
+        const int cy = y / K, bb = y % K;
+        const int c0 = b.chunk_start[cy], c1 = b.chunk_start[cy + 1];
+        float s1 = 0.f, sx = 0.f, sy = 0.f;
+        for (int c = c0; c < c1; ++c) {
+            const float* e = b.spart + (size_t)c * per + (bb * M + x) * 3;
+            s1 += e[0];
+            sx += e[1];
+            sy += e[2];
+        }
+        const int q = r >> 1;
+        z[(3 * q + ((r & 1) ? 2 : 0)) * L + x] = make_float2(s1, sx);
+        reinterpret_cast<float*>(z + (3 * q + 1) * L + x)[r & 1] = sy;
+    }
+    __syncthreads();
+    for (int tk = w; tk < NQT; tk += nwav) wave_fft<LOGL, false>(z + tk * TL, b.tw, lane);
+    __syncthreads();
+    // unpack with Z(u) and Z(L-u); r fastest so each column gets RB consecutive rows
+    for (int i = threadIdx.x; i < 3 * H * RB; i += blockDim.x) {
+        const int r = i % RB, cu = i / RB;
+        const int ch = cu / H, u = cu % H;
+        const int y = y0 + r;
+        if (y >= M) continue;
+        const int q = r >> 1, odd = r & 1;
+        const int um = (L - u) & (L - 1);
+        float2 v;
+        if (ch < 2) {
+            const float2* zr = z + (3 * q + (odd ? 2 : 0)) * L;
+            const float2 a = zr[u], c = zr[um];
+            // Z = FFT(q1 + i qdx): Q1 = (Z(u) + conj Z(L-u))/2, Qdx = (Z(u) - conj Z(L-u))/(2i)
+            v = ch == 0 ? make_float2(0.5f * (a.x + c.x), 0.5f * (a.y - c.y))
+                        : make_float2(0.5f * (a.y + c.y), -0.5f * (a.x - c.x));
+        } else {
+            const float2* zr = z + (3 * q + 1) * L;
+            const float2 a = zr[u], c = zr[um];
+            v = odd ? make_float2(0.5f * (a.y + c.y), -0.5f * (a.x - c.x))
+                    : make_float2(0.5f * (a.x + c.x), 0.5f * (a.y - c.y));
+        }
+        b.qcol[((size_t)ch * H + u) * M + y] = v;
+    }
+}
+
+template <int LOGL>
+static void launch_rowfft_t(const Bufs& b, const Geom& g, hipStream_t s) {
+    static const bool once = (allow_big_lds(k_rowfft<LOGL>), true);
+    (void)once;
+    constexpr int F = task_ffts<LOGL>();
+    constexpr int TL = F * (1 << LOGL);
+    constexpr int RB = RowTile<LOGL>::RB;
+    constexpr int NQT = (3 * RB / 2 + F - 1) / F;
+    const size_t lds = (size_t)NQT * TL * sizeof(float2);
+    const int nqb = (g.m + RB - 1) / RB;
+    hipLaunchKernelGGL(k_rowfft<LOGL>, dim3(xcd_pair_grid(nqb)), dim3(RowTile<LOGL>::THREADS), lds, s, b, g, nqb);
+}
+
+void launch_rowfft(const Bufs& b, const Geom& g, hipStream_t s) {
+    switch (g.logL) {
+        case 6: launch_rowfft_t<6>(b, g, s); break;
+        case 7: launch_rowfft_t<7>(b, g, s); break;
+        case 8: launch_rowfft_t<8>(b, g, s); break;
+        case 9: launch_rowfft_t<9>(b, g, s); break;
+        case 10: launch_rowfft_t<10>(b, g, s); break;
+        default: launch_rowfft_t<11>(b, g, s); break;
     }
 }
 
@@ -395,7 +465,7 @@ void launch_spread_rows(const Bufs& b, const Geom& g, float gamma, hipStream_t s
 //   C2 = FFT_b(s b R1)      -> H_y^ = i Im C2                (real-odd rows)
 //   Q1, Qdx, Qdy            (charge row spectra, rows y < M)
 // then phi_1 = K^ Q1, G_x = H_x^ Q1 - K^ Qdx, G_y = H_y^ Q1 - K^ Qdy (scaled by
-// 1/L^2) and three inverse column FFTs; rows y < M stored row-major.
+// 1/L^2) and three inverse column FFTs; rows y < M stored column-major.
 template <int LOGL>
 __global__ __launch_bounds__(512) void k_colconv(Bufs b, Geom g) {
     extern __shared__ float2 sm2[];
@@ -410,20 +480,15 @@ __global__ __launch_bounds__(512) void k_colconv(Bufs b, Geom g) {
     const Box bx = b.st->box;
     const float s = (float)(bx.h / (double)g.k);
     const float inv = 1.f / ((float)L * (float)L);
-    const float* R1 = b.kcol;
-    const float* R2 = b.kcol + (size_t)H * L;
     // task c (0..4) of transform f covers column u0 + f
     for (int i = threadIdx.x; i < TL; i += blockDim.x) {
         const int f = i >> logL, r = i & (L - 1);
         const int u = u0 + f;
-        float r1 = 0.f, r2 = 0.f;
-        if (u < H) {
-            r1 = R1[(size_t)u * L + r];
-            r2 = R2[(size_t)u * L + r];
-        }
+        float2 kr = make_float2(0.f, 0.f);
+        if (u < H) kr = b.kcol[(size_t)u * L + r];
         const int bt = signed_offset(r, M, L);
-        sm2[i] = make_float2(r1, r2);
-        sm2[TL + i] = make_float2(bt != INT_MIN ? s * (float)bt * r1 : 0.f, 0.f);
+        sm2[i] = kr;
+        sm2[TL + i] = make_float2(bt != INT_MIN ? s * (float)bt * kr.x : 0.f, 0.f);
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             float2 v = make_float2(0.f, 0.f);
@@ -448,9 +513,9 @@ __global__ __launch_bounds__(512) void k_colconv(Bufs b, Geom g) {
     __syncthreads();
     for (int i = threadIdx.x; i < 3 * F * M; i += blockDim.x) {
         const int ch = i / (F * M), rem = i % (F * M);
-        const int f = rem % F, y = rem / F;
+        const int f = rem / M, y = rem % M;
         const int u = u0 + f;
-        if (u < H) b.prow[((size_t)ch * M + y) * H + u] = sm2[(2 + ch) * TL + f * L + y];
+        if (u < H) b.pcol[((size_t)ch * H + u) * M + y] = sm2[(2 + ch) * TL + f * L + y];
     }
 }
 
@@ -477,60 +542,72 @@ void launch_colconv(const Bufs& b, const Geom& g, hipStream_t s) {
 
 // ----------------------------------------------------------------- inverse rows
 
-// Grid rows y0 .. y0+2F-1: four tasks of F transforms, the first two hold
-// phi_1 + i G_x of F rows each, the last two G_y.
+// RB potential rows per block, read as column tiles. Transforms: row r holds
+// phi_1 + i G_x (task area r), row pair q holds G_y(2q) + i G_y(2q+1)
+// (area RB + q); the spectra of real rows are extended by Hermitian symmetry.
 template <int LOGL>
-__global__ __launch_bounds__(kThreads) void k_rowifft(Bufs b, Geom g) {
+__global__ __launch_bounds__(RowTile<LOGL>::THREADS) void k_rowifft(Bufs b, Geom g, int nrb) {
     extern __shared__ float2 z[];
     constexpr int L = 1 << LOGL;
-    constexpr int logL = LOGL;
     constexpr int F = task_ffts<LOGL>();
     constexpr int TL = F * L;
+    constexpr int RB = RowTile<LOGL>::RB;
+    constexpr int NT = (3 * RB / 2 + F - 1) / F;
+    const int lb = xcd_pair_block(blockIdx.x, nrb);
+    if (lb < 0) return;
     const int M = g.m, H = g.H;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int RB = 2 * F;
-    const int y0 = blockIdx.x * RB;
-    for (int i = threadIdx.x; i < RB * L; i += blockDim.x) {
-        const int rr = i >> logL, u = i & (L - 1);
-        const int y = y0 + rr;
-        float2 a = make_float2(0.f, 0.f), c = a, e = a;
-        if (y < M) {
-            const float2* p0 = b.prow + ((size_t)0 * M + y) * H;
-            const float2* p1 = b.prow + ((size_t)1 * M + y) * H;
-            const float2* p2 = b.prow + ((size_t)2 * M + y) * H;
-            if (u < H) {
-                a = p0[u];
-                c = p1[u];
-                e = p2[u];
-            } else {  // Hermitian extension of the spectra of real rows
-                const int uu = L - u;
-                a = make_float2(p0[uu].x, -p0[uu].y);
-                c = make_float2(p1[uu].x, -p1[uu].y);
-                e = make_float2(p2[uu].x, -p2[uu].y);
+    const int nwav = blockDim.x >> 6;
+    const int y0 = lb * RB;
+    for (int i = threadIdx.x; i < (NT * TL - (3 * RB / 2) * L); i += blockDim.x)
+        z[(3 * RB / 2) * L + i] = make_float2(0.f, 0.f);
+    for (int i = threadIdx.x; i < L * (RB / 2); i += blockDim.x) {
+        const int q = i % (RB / 2), u = i / (RB / 2);
+        const bool ext = u >= H;
+        const int uu = ext ? L - u : u;
+        float2 p[3][2];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+#pragma unroll
+            for (int o = 0; o < 2; ++o) {
+                const int y = y0 + 2 * q + o;
+                float2 v = make_float2(0.f, 0.f);
+                if (y < M) v = b.pcol[((size_t)ch * H + uu) * M + y];
+                if (ext) v.y = -v.y;
+                p[ch][o] = v;
             }
         }
-        z[i] = make_float2(a.x - c.y, a.y + c.x);  // phi_1 + i G_x
-        z[2 * TL + i] = e;
+#pragma unroll
+        for (int o = 0; o < 2; ++o)
+            z[(2 * q + o) * L + u] = make_float2(p[0][o].x - p[1][o].y, p[0][o].y + p[1][o].x);
+        z[(RB + q) * L + u] = make_float2(p[2][0].x - p[2][1].y, p[2][0].y + p[2][1].x);
     }
     __syncthreads();
-    wave_fft<LOGL, true>(z + w * TL, b.tw, lane);
+    for (int tk = w; tk < NT; tk += nwav) wave_fft<LOGL, true>(z + tk * TL, b.tw, lane);
     __syncthreads();
     for (int i = threadIdx.x; i < RB * M; i += blockDim.x) {
-        const int rr = i / M, x = i % M;
-        const int y = y0 + rr;
+        const int r = i / M, x = i % M;
+        const int y = y0 + r;
         if (y < M) {
-            const float2 v = z[rr * L + x];
-            b.pot[(size_t)y * M + x] = make_float4(v.x, v.y, z[2 * TL + rr * L + x].x, 0.f);
+            const float2 v = z[r * L + x];
+            const float2 e = z[(RB + (r >> 1)) * L + x];
+            b.pot[(size_t)y * M + x] = make_float4(v.x, v.y, (r & 1) ? e.y : e.x, 0.f);
         }
     }
 }
 
 template <int LOGL>
 static void launch_rowifft_t(const Bufs& b, const Geom& g, hipStream_t s) {
+    static const bool once = (allow_big_lds(k_rowifft<LOGL>), true);
+    (void)once;
     constexpr int F = task_ffts<LOGL>();
-    const int blocks = (g.m + 2 * F - 1) / (2 * F);
-    hipLaunchKernelGGL(k_rowifft<LOGL>, dim3(blocks), dim3(kThreads), (size_t)4 * F * g.L * sizeof(float2), s, b, g);
+    constexpr int TL = F * (1 << LOGL);
+    constexpr int RB = RowTile<LOGL>::RB;
+    constexpr int NT = (3 * RB / 2 + F - 1) / F;
+    const int nrb = (g.m + RB - 1) / RB;
+    hipLaunchKernelGGL(k_rowifft<LOGL>, dim3(xcd_pair_grid(nrb)), dim3(RowTile<LOGL>::THREADS),
+                       (size_t)NT * TL * sizeof(float2), s, b, g, nrb);
 }
 
 void launch_rowifft(const Bufs& b, const Geom& g, hipStream_t s) {

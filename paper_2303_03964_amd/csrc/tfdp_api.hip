@@ -23,6 +23,7 @@ enum Phase {
     PH_BIN_SCAN,
     PH_BIN_SCATTER,
     PH_SPREAD,
+    PH_ROWFFT,
     PH_COLCONV,
     PH_ROWIFFT,
     PH_GATHER,
@@ -30,8 +31,8 @@ enum Phase {
     PH_COUNT
 };
 
-const char* kPhaseNames[PH_COUNT] = {"box",     "bin_count", "bin_scan",      "bin_scatter", "spread_rows",
-                                     "colconv", "rowifft",   "gather_update", "brute"};
+const char* kPhaseNames[PH_COUNT] = {"box",     "bin_count", "bin_scan", "bin_scatter",   "spread",
+                                     "rowfft",  "colconv",   "rowifft",  "gather_update", "brute"};
 
 int k_workspace(const tfdp_params* p) { return (p->k_mode == 1 || p->k_mode == 2) ? p->k_mode : 3; }
 
@@ -79,15 +80,19 @@ Layout carve(void* base, int n, long long nnz, const tfdp_params* p, size_t* byt
     l.b.n = n;
     l.b.n_int = p->n_int;
     l.b.nblk = (n + kBinChunk - 1) / kBinChunk;
+    l.b.max_chunks = (n + kSpreadChunk - 1) / kSpreadChunk + p->n_int;
     l.b.st = c.take<DevState>(1);
     l.pos_alt = c.take<float2>((size_t)n);
     l.b.spos = c.take<float2>((size_t)n);
     l.b.blkcnt = c.take<int>((size_t)p->n_int * l.b.nblk);
     l.b.bucket_cnt = c.take<int>((size_t)p->n_int);
     l.b.bucket_start = c.take<int>((size_t)p->n_int + 1);
+    l.b.chunk_start = c.take<int>((size_t)p->n_int + 1);
+    l.b.chunk_row = c.take<int>((size_t)l.b.max_chunks);
+    l.b.spart = c.take<float>((size_t)l.b.max_chunks * kw * gw.m * 3);
     l.b.qcol = c.take<float2>((size_t)3 * gw.H * gw.m);
-    l.b.kcol = c.take<float>((size_t)2 * gw.H * gw.L);
-    l.b.prow = c.take<float2>((size_t)3 * gw.m * gw.H);
+    l.b.kcol = c.take<float2>((size_t)gw.H * gw.L);
+    l.b.pcol = c.take<float2>((size_t)3 * gw.H * gw.m);
     l.b.pot = c.take<float4>((size_t)gw.m * gw.m);
     l.b.sched = c.take<int2>((size_t)4 * edge_blocks_bound(n, nnz));
     for (int k = 1; k <= kw; ++k) l.tw[k] = c.take<float2>((size_t)make_geom(p->n_int, k).L);
@@ -215,7 +220,8 @@ void enqueue_grid(tfdp_layout* h, const float2* pos, const Bufs& b, const Geom& 
     { PhaseTimer pt(h, PH_BIN_COUNT, s); launch_bin_count(pos, b, set, s); }
     { PhaseTimer pt(h, PH_BIN_SCAN, s); launch_bin_scan(b, set ^ 1, s); }
     { PhaseTimer pt(h, PH_BIN_SCATTER, s); launch_bin_scatter(pos, b, s); }
-    { PhaseTimer pt(h, PH_SPREAD, s); launch_spread_rows(b, g, h->p.gamma, s); }
+    { PhaseTimer pt(h, PH_SPREAD, s); launch_spread(b, g, h->p.gamma, s); }
+    { PhaseTimer pt(h, PH_ROWFFT, s); launch_rowfft(b, g, s); }
     { PhaseTimer pt(h, PH_COLCONV, s); launch_colconv(b, g, s); }
     { PhaseTimer pt(h, PH_ROWIFFT, s); launch_rowifft(b, g, s); }
 }

@@ -9,6 +9,7 @@ namespace tfdp {
 
 constexpr int kThreads = 256;        // threads per block of the node and FFT kernels
 constexpr int kBinChunk = 1024;      // nodes per block of the binning passes
+constexpr int kSpreadChunk = 4096;   // sorted nodes per block of the spreading pass
 constexpr int kBoxSlots = 64;        // slots of the box extremes (one 128-byte line each)
 constexpr int kMaxL = 2048;          // largest FFT length per side
 constexpr int kMaxNInt = 1024;       // largest number of intervals per side
@@ -49,13 +50,17 @@ struct Bufs {
     int n;
     int n_int;
     int nblk;            // blocks of the binning passes
+    int max_chunks;      // upper bound of spreading blocks
     float2* spos;        // positions sorted by interval row
     int* blkcnt;         // [n_int][nblk] counts, then exclusive offsets
     int* bucket_cnt;     // [n_int]
     int* bucket_start;   // [n_int + 1]
+    int* chunk_start;    // [n_int + 1] first spreading chunk of each interval row
+    int* chunk_row;      // [max_chunks] interval row of each spreading chunk
+    float* spart;        // [max_chunks][k][M][3] partial grid rows of each chunk
     float2* qcol;        // [3][H][M] charge row spectra, column-major
-    float* kcol;         // [2][H][L] kernel row spectra (real), column-major
-    float2* prow;        // [3][M][H] potential row spectra after the column pass
+    float2* kcol;        // [H][L] kernel row spectra (K^, H_x^/i), column-major
+    float2* pcol;        // [3][H][M] potential row spectra after the column pass
     float4* pot;         // [M][M] (phi_1, G_x, G_y, 0)
     const float2* tw;    // twiddles for this L: exp(-2 pi i j / L), j < L
     const int2* sched;   // [4 * edge_blocks] edge-pass schedule (see node_forces.hip)
@@ -75,13 +80,26 @@ void launch_box_reduce(const float2* pos, int n, DevState* st, int set, hipStrea
 void launch_bin_count(const float2* pos, const Bufs& b, int set, hipStream_t s);
 void launch_bin_scan(const Bufs& b, int reset_set, hipStream_t s);
 void launch_bin_scatter(const float2* pos, const Bufs& b, hipStream_t s);
-void launch_spread_rows(const Bufs& b, const Geom& g, float gamma, hipStream_t s);
+void launch_spread(const Bufs& b, const Geom& g, float gamma, hipStream_t s);
+void launch_rowfft(const Bufs& b, const Geom& g, hipStream_t s);
 void launch_colconv(const Bufs& b, const Geom& g, hipStream_t s);
 void launch_rowifft(const Bufs& b, const Geom& g, hipStream_t s);
 void launch_twiddles(float2* tw, int L, hipStream_t s);
 void launch_gather(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx,
                    const Bufs& b, const Geom& g, const ModelArgs& a, int set,
                    float2* f_rep, float2* f_att, float2* f_tot, hipStream_t s);
+// Workgroups are dispatched to the 8 XCDs round robin. xcd_pair_block maps
+// the physical block index so that logical blocks 2j and 2j+1 run on the
+// same XCD (and so share its L2) when their stores fill one cache line
+// together; returns -1 for padding blocks. nb: logical blocks; grid size
+// xcd_pair_grid(nb).
+__host__ __device__ __forceinline__ int xcd_pair_grid(int nb) { return ((nb + 15) / 16) * 16; }
+__device__ __forceinline__ int xcd_pair_block(int phys, int nb) {
+    const int per = xcd_pair_grid(nb) / 8;  // logical blocks per XCD (even)
+    const int logical = (phys % 8) * per + phys / 8;
+    return logical < nb ? logical : -1;
+}
+
 // Upper bound of edge-pass blocks for n rows and nnz CSR entries.
 inline long long edge_blocks_bound(long long n, long long nnz) {
     return (n + 3) / 4 + nnz / (kGroupEdges + 1) + 1;
@@ -116,19 +134,20 @@ __device__ __forceinline__ void bin_axis(float x, double lo, double h, int n_int
     t = r - f;
 }
 
-// Lagrange basis on the K nodes (j + 1/2)/K of one interval, float64.
+// Lagrange basis on the K nodes (j + 1/2)/K of one interval, float64. The
+// node differences (j - m)/K have compile-time reciprocals K/(j - m), so no
+// division is needed (the weights only have to be accurate, unlike the
+// interval index, which must match the oracle bit for bit).
 template <int K>
 __device__ __forceinline__ void lagrange(double t, double* w) {
-#pragma clang fp contract(off)
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        double tj = ((double)j + 0.5) / (double)K;
         double v = 1.0;
 #pragma unroll
         for (int m = 0; m < K; ++m) {
             if (m == j) continue;
-            double tm = ((double)m + 0.5) / (double)K;
-            v = v * ((t - tm) / (tj - tm));
+            const double tm = ((double)m + 0.5) / (double)K;
+            v = v * ((t - tm) * ((double)K / (double)(j - m)));
         }
         w[j] = v;
     }

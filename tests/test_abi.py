@@ -107,7 +107,7 @@ def test_null_handle_calls():
 
 def test_phase_names():
     names = [T.tfdp_phase_name(i) for i in range(T.tfdp_phase_count())]
-    assert "gather_update" in names and "spread_rows" in names and "colconv" in names
+    assert "gather_update" in names and "spread" in names and "rowfft" in names and "colconv" in names
     assert T.tfdp_phase_name(-1) == "" and T.tfdp_phase_name(999) == ""
 
 

@@ -309,7 +309,7 @@ def test_profiling_phase_times(T):
     T.tfdp_layout_set_profiling(lay.handle, 1)
     lay.step(20)
     times = T.tfdp_layout_phase_times(lay.handle)
-    assert times["gather_update"][1] == 20 and times["spread_rows"][1] == 20
+    assert times["gather_update"][1] == 20 and times["spread"][1] == 20
     assert all(ms >= 0 for ms, _ in times.values())
     T.tfdp_layout_set_profiling(lay.handle, 0)
     lay.close()
