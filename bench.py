@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations (0: about 15 s of work)")
     ap.add_argument("--repeats", type=int, default=1, help="timed repeats; value is the median")
+    ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="copy this many MiB device-to-device once before the run (a plain copy kernel "
                          "of known size for scaling hardware byte counters)")
@@ -132,10 +133,15 @@ def main():
     print(f"# workload {w.name}: n={g.n} nnz={g.nnz} n_int={w.n_int} T={w.iters} "
           f"(generated in {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
+    # a side stream (default priority): iteration pairs are captured as HIP
+    # graphs, which the legacy default stream does not allow
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
     pos0 = torch.as_tensor(w.pos0).to(dev)
     params = T.tfdp_params_default(n_int=w.n_int, total_iters=w.iters, k_mode=-1)
     lay = T.Layout(g.row_ptr, g.col_idx, pos0.clone(), params, device=dev)
-    stream = torch.cuda.current_stream()
+    if args.no_graphs:
+        T.tfdp_layout_set_graphs(lay.handle, 0)
     if args.calib_copy_mb > 0:
         nel = args.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(nel, dtype=torch.float32, device=dev)
@@ -219,7 +225,7 @@ def main():
             "positions": "uniform [-1,1]^2 float32, seeded",
         },
         "roofline": {
-            "kernel": "k_gather<1> (gather + CSR attraction + update, k=1)",
+            "kernel": "k_edges<1,2> (edge pass + gather + update, k=1)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -233,6 +239,7 @@ def main():
         "phase_ms_k1": phases,
         "phase_ms_k23": phases_rest,
         "iteration_ms_k1_events": iter_ms_k1,
+        "hip_graphs": not args.no_graphs,
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)

@@ -166,6 +166,12 @@ void tfdp_layout_destroy(tfdp_layout* h);
 /* Thread-local text for the last failure or warning ("" if none). */
 const char* tfdp_last_error(void);
 
+/* Launch iteration pairs of one k as captured HIP graphs (default on; a
+ * graph per k, parity and buffer orientation is captured on first use on
+ * the step's stream and dropped by tfdp_layout_set_params). Off: every
+ * kernel is launched directly. Profiling (below) always launches directly. */
+tfdp_status tfdp_layout_set_graphs(tfdp_layout* h, int32_t enable);
+
 /* Per-phase timing with HIP events recorded on the launch stream around the
  * kernels of each phase. Enabling costs two event records per phase launch. */
 tfdp_status tfdp_layout_set_profiling(tfdp_layout* h, int32_t enable);

@@ -333,8 +333,6 @@ __global__ __launch_bounds__(512) void k_spread(Bufs b, Geom g, float gamma, int
 
 template <int K, int LOGL>
 static void launch_spread_t(const Bufs& b, const Geom& g, float gamma, hipStream_t s) {
-    static const bool once = (allow_big_lds(k_spread<K, LOGL>), true);
-    (void)once;
     const size_t per = (size_t)K * g.m * 3 * sizeof(float);
     int nw = 8;
     while (nw > 1 && nw * per > 128 * 1024) nw >>= 1;
@@ -436,8 +434,6 @@ __global__ __launch_bounds__(RowTile<LOGL>::THREADS) void k_rowfft(Bufs b, Geom 
 
 template <int LOGL>
 static void launch_rowfft_t(const Bufs& b, const Geom& g, hipStream_t s) {
-    static const bool once = (allow_big_lds(k_rowfft<LOGL>), true);
-    (void)once;
     constexpr int F = task_ffts<LOGL>();
     constexpr int TL = F * (1 << LOGL);
     constexpr int RB = RowTile<LOGL>::RB;
@@ -521,8 +517,6 @@ __global__ __launch_bounds__(512) void k_colconv(Bufs b, Geom g) {
 
 template <int LOGL>
 static void launch_colconv_t(const Bufs& b, const Geom& g, hipStream_t s) {
-    static const bool once = (allow_big_lds(k_colconv<LOGL>), true);
-    (void)once;
     constexpr int F = task_ffts<LOGL>();
     const int blocks = (g.H + F - 1) / F;
     const size_t lds = (size_t)5 * F * g.L * sizeof(float2);
@@ -599,8 +593,6 @@ __global__ __launch_bounds__(RowTile<LOGL>::THREADS) void k_rowifft(Bufs b, Geom
 
 template <int LOGL>
 static void launch_rowifft_t(const Bufs& b, const Geom& g, hipStream_t s) {
-    static const bool once = (allow_big_lds(k_rowifft<LOGL>), true);
-    (void)once;
     constexpr int F = task_ffts<LOGL>();
     constexpr int TL = F * (1 << LOGL);
     constexpr int RB = RowTile<LOGL>::RB;
@@ -619,6 +611,28 @@ void launch_rowifft(const Bufs& b, const Geom& g, hipStream_t s) {
         case 10: launch_rowifft_t<10>(b, g, s); break;
         default: launch_rowifft_t<11>(b, g, s); break;
     }
+}
+
+// Large-LDS attribute for every kernel instantiation that can exceed 64 KB
+// (called once at set-up, so that no attribute call happens during stream
+// capture).
+template <int LOGL>
+static void allow_big_lds_all_l() {
+    allow_big_lds(k_spread<1, LOGL>);
+    allow_big_lds(k_spread<2, LOGL>);
+    allow_big_lds(k_spread<3, LOGL>);
+    allow_big_lds(k_rowfft<LOGL>);
+    allow_big_lds(k_colconv<LOGL>);
+    allow_big_lds(k_rowifft<LOGL>);
+}
+
+void init_kernel_attributes() {
+    allow_big_lds_all_l<6>();
+    allow_big_lds_all_l<7>();
+    allow_big_lds_all_l<8>();
+    allow_big_lds_all_l<9>();
+    allow_big_lds_all_l<10>();
+    allow_big_lds_all_l<11>();
 }
 
 }  // namespace tfdp

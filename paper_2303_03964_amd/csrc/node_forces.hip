@@ -3,13 +3,13 @@
 // the displacement D = w_r F^r + F^a and the capped move; or, for the exact
 // method (Sec. 3.4), the all-pairs repulsion tiled through LDS.
 //
-// Edge pass schedule (built once at init from row_ptr): rows are cut into
+// Edge pass schedule (built once at init for each column slice): rows are cut into
 // wave groups of at most kGroupRows rows and kGroupEdges CSR entries, packed
 // four per block; a row with more than kGroupEdges entries gets a block of
-// its own. In a wave group, lane l walks CSR entry e0 + l (coalesced column
-// reads), finds its row by a binary search over the group's row starts held
-// one per lane, and adds its term to a wave-private LDS accumulator; lane r
-// then finishes row r0 + r. A heavy row is summed by all 256 threads and
+// its own. In a wave group, lane l walks CSR entry e0 + l (coalesced reads of
+// packed entries: column plus the row's index in the group), reads its row's
+// position from LDS, and adds its term to a wave-private LDS accumulator;
+// lane r then finishes row r0 + r. A heavy row is summed by all 256 threads and
 // reduced in a fixed order. Every wave handles at most kGroupEdges entries,
 // whatever the degree distribution.
 #include "tfdp_internal.h"
@@ -94,23 +94,29 @@ __device__ __forceinline__ void node_output(int i, float2 p, float frx, float fr
     }
 }
 
-template <int K>
-__global__ __launch_bounds__(kThreads) void k_gather(const float2* __restrict__ pos,
-                                                     float2* __restrict__ pos_out,
-                                                     const int* __restrict__ row_ptr,
-                                                     const int* __restrict__ col_idx, Bufs b, Geom g,
-                                                     ModelArgs a, int set, float2* f_rep, float2* f_att,
-                                                     float2* f_tot) {
+// Edge pass over one column slice. MODE 0: write the slice's attraction sums
+// of every row to fpart; MODE 1: add them to fpart; MODE 2 (last slice): add
+// fpart (use_part), gather the repulsion, and write the forces or the move.
+// Slicing bounds the neighbour positions read by one launch to one column
+// range.
+template <int K, int MODE>
+__global__ __launch_bounds__(kThreads) void k_edges(const float2* __restrict__ pos,
+                                                    float2* __restrict__ pos_out, EdgeSlice es,
+                                                    int use_part, float2* __restrict__ fpart, Bufs b,
+                                                    Geom g, ModelArgs a, int set, float2* f_rep,
+                                                    float2* f_att, float2* f_tot) {
     __shared__ float accx[kThreads];
     __shared__ float accy[kThreads];
     __shared__ float hred[2][kThreads / 64];
+    __shared__ float2 pown[kThreads];
+    const int* __restrict__ row_ptr = es.rp;
+    const int* __restrict__ col_idx = es.col;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     accx[threadIdx.x] = 0.f;
     accy[threadIdx.x] = 0.f;
     __syncthreads();
-    const int2 s0 = b.sched[4 * blockIdx.x];
-    const Box bx = b.st->box;
+    const int2 s0 = es.sched[4 * blockIdx.x];
     float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
     bool have = false;
     int i = 0;
@@ -127,7 +133,8 @@ __global__ __launch_bounds__(kThreads) void k_gather(const float2* __restrict__ 
             // past the row's end the row itself stands in: its term is zero
             int c[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) c[u] = e + u * kThreads < e1 ? col_idx[e + u * kThreads] : row;
+            for (int u = 0; u < 4; ++u)
+                c[u] = e + u * kThreads < e1 ? (col_idx[e + u * kThreads] & 0x3ffffff) : row;
             float2 q[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) q[u] = pos[c[u]];
@@ -156,46 +163,40 @@ __global__ __launch_bounds__(kThreads) void k_gather(const float2* __restrict__ 
             p = pr;
         }
     } else {
-        const int2 gd = b.sched[4 * blockIdx.x + w];
+        const int2 gd = es.sched[4 * blockIdx.x + w];
         const int r0 = gd.x, nr = gd.y;
         if (nr > 0) {
-            const int rs = lane < nr ? row_ptr[r0 + lane] : 0x7fffffff;
+            // positions of the group's rows in LDS; entry e carries its row's
+            // index in the group in bits 26..31
+            float2* pw = reinterpret_cast<float2*>(pown) + w * 64;
             const float2 po = lane < nr ? pos[r0 + lane] : make_float2(0.f, 0.f);
+            pw[lane] = po;
             const int eb = row_ptr[r0];
             const int ee = row_ptr[r0 + nr];
             float* ax_w = accx + w * 64;
             float* ay_w = accy + w * 64;
-            // all column reads of the group first, then all neighbour reads:
+            __builtin_amdgcn_wave_barrier();
+            // all entry reads of the group first, then all neighbour reads:
             // up to kGroupEdges/64 independent loads in flight per lane
             constexpr int R = kGroupEdges / 64;
-            int rowr[R];
-            int colr[R];
+            unsigned int ent[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int e = eb + r * 64 + lane;
-                // row of entry e: the largest row index < nr whose start is <= e
-                int lo = 0;
-#pragma unroll
-                for (int step = 32; step > 0; step >>= 1) {
-                    const int cand = lo + step;
-                    const int v = __shfl(rs, cand & 63);
-                    if (cand < nr && v <= e) lo = cand;
-                }
-                rowr[r] = lo;
-                colr[r] = e < ee ? col_idx[e] : r0;  // r0: any valid index, term skipped below
+                ent[r] = e < ee ? (unsigned int)col_idx[e] : (unsigned int)r0;
             }
             float2 q[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) q[r] = pos[colr[r]];
+            for (int r = 0; r < R; ++r) q[r] = pos[ent[r] & 0x3ffffffu];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const float px = __shfl(po.x, rowr[r]);
-                const float py = __shfl(po.y, rowr[r]);
                 if (eb + r * 64 + lane < ee) {
+                    const int lr = (int)(ent[r] >> 26);
+                    const float2 pr = pw[lr];
                     float ax, ay;
-                    edge_term(px, py, q[r], a.beta, ax, ay);
-                    atomicAdd(ax_w + rowr[r], ax);
-                    atomicAdd(ay_w + rowr[r], ay);
+                    edge_term(pr.x, pr.y, q[r], a.beta, ax, ay);
+                    atomicAdd(ax_w + lr, ax);
+                    atomicAdd(ay_w + lr, ay);
                 }
             }
             if (lane < nr) {
@@ -207,32 +208,57 @@ __global__ __launch_bounds__(kThreads) void k_gather(const float2* __restrict__ 
             }
         }
     }
-    if (have) {
-        float frx, fry;
-        grid_repulsion<K>(b, g, bx, p, frx, fry);
-        node_output(i, p, frx, fry, sax, say, a, b.st->t, b.st, pos_out, f_rep, f_att, f_tot, xmin, ymin, xmax,
-                    ymax);
+    if constexpr (MODE < 2) {
+        if (have) {
+            float2 v = make_float2(sax, say);
+            if (MODE == 1) {
+                const float2 old = fpart[i];
+                v = make_float2(old.x + sax, old.y + say);
+            }
+            fpart[i] = v;
+        }
+    } else {
+        if (have) {
+            if (use_part) {
+                const float2 old = fpart[i];
+                sax = old.x + sax;
+                say = old.y + say;
+            }
+            const Box bx = b.st->box;
+            float frx, fry;
+            grid_repulsion<K>(b, g, bx, p, frx, fry);
+            node_output(i, p, frx, fry, sax, say, a, b.st->t, b.st, pos_out, f_rep, f_att, f_tot, xmin, ymin,
+                        xmax, ymax);
+        }
+        if (pos_out != nullptr) block_minmax_commit(xmin, ymin, xmax, ymax, b.st, set);
     }
-    if (pos_out != nullptr) block_minmax_commit(xmin, ymin, xmax, ymax, b.st, set);
 }
 
-void launch_gather(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx,
-                   const Bufs& b, const Geom& g, const ModelArgs& a, int set, float2* f_rep, float2* f_att,
-                   float2* f_tot, hipStream_t s) {
-    const int blocks = b.edge_blocks;
-    switch (g.k) {
-        case 1:
-            hipLaunchKernelGGL(k_gather<1>, dim3(blocks), dim3(kThreads), 0, s, pos, pos_out, row_ptr,
-                               col_idx, b, g, a, set, f_rep, f_att, f_tot);
-            break;
-        case 2:
-            hipLaunchKernelGGL(k_gather<2>, dim3(blocks), dim3(kThreads), 0, s, pos, pos_out, row_ptr,
-                               col_idx, b, g, a, set, f_rep, f_att, f_tot);
-            break;
-        default:
-            hipLaunchKernelGGL(k_gather<3>, dim3(blocks), dim3(kThreads), 0, s, pos, pos_out, row_ptr,
-                               col_idx, b, g, a, set, f_rep, f_att, f_tot);
-            break;
+template <int K>
+static void launch_edges_k(const float2* pos, float2* pos_out, const EdgeSlice& es, int mode, int use_part,
+                           float2* fpart, const Bufs& b, const Geom& g, const ModelArgs& a, int set,
+                           float2* f_rep, float2* f_att, float2* f_tot, hipStream_t s) {
+    const dim3 grid(es.blocks), block(kThreads);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_edges<K, 0>), grid, block, 0, s, pos, pos_out, es, use_part, fpart, b, g, a, set,
+                           f_rep, f_att, f_tot);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_edges<K, 1>), grid, block, 0, s, pos, pos_out, es, use_part, fpart, b, g, a, set,
+                           f_rep, f_att, f_tot);
+    else
+        hipLaunchKernelGGL((k_edges<K, 2>), grid, block, 0, s, pos, pos_out, es, use_part, fpart, b, g, a, set,
+                           f_rep, f_att, f_tot);
+}
+
+void launch_edges(const float2* pos, float2* pos_out, const EdgeSlice& es, int mode, int use_part,
+                  float2* fpart, const Bufs& b, const Geom& g, const ModelArgs& a, int set, float2* f_rep,
+                  float2* f_att, float2* f_tot, hipStream_t s) {
+    // partial modes do not depend on k: one instantiation serves all
+    const int k = mode < 2 ? 1 : g.k;
+    switch (k) {
+        case 1: launch_edges_k<1>(pos, pos_out, es, mode, use_part, fpart, b, g, a, set, f_rep, f_att, f_tot, s); break;
+        case 2: launch_edges_k<2>(pos, pos_out, es, mode, use_part, fpart, b, g, a, set, f_rep, f_att, f_tot, s); break;
+        default: launch_edges_k<3>(pos, pos_out, es, mode, use_part, fpart, b, g, a, set, f_rep, f_att, f_tot, s); break;
     }
 }
 

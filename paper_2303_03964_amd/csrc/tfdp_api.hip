@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/tfdp.h: parameter validation,
 // workspace layout, the per-iteration launch sequence and profiling.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -69,7 +70,26 @@ struct Layout {
     Bufs b;         // tw filled per k
     float2* pos_alt;
     float2* tw[4];  // per k
+    int nslices;
+    int* slice_rp;      // [nslices][n + 1] (nslices > 1)
+    int* slice_col;     // [nnz] packed entries: column | (row index in its wave group) << 26
+    float2* fpart;      // [n] attraction sums of the earlier slices (nslices > 1)
+    int2* sched;        // [4 * edge_blocks_bound] schedules of all slices
+    EdgeSlice slice[kMaxSlices];
 };
+
+// Column-slice width of the edge pass: kSliceNodesDefault, or the value of
+// the environment variable TFDP_EDGE_SLICE_NODES (>= 1024) read at each call.
+// One slice is fastest on MI355X up to millions of nodes (measured); the
+// sliced pass bounds the neighbour working set of one launch.
+long long slice_nodes() {
+    const char* e = std::getenv("TFDP_EDGE_SLICE_NODES");
+    if (e) {
+        const long long v = std::atoll(e);
+        if (v >= 1024) return v;
+    }
+    return kSliceNodesDefault;
+}
 
 Layout carve(void* base, int n, long long nnz, const tfdp_params* p, size_t* bytes) {
     Layout l;
@@ -94,7 +114,14 @@ Layout carve(void* base, int n, long long nnz, const tfdp_params* p, size_t* byt
     l.b.kcol = c.take<float2>((size_t)gw.H * gw.L);
     l.b.pcol = c.take<float2>((size_t)3 * gw.H * gw.m);
     l.b.pot = c.take<float4>((size_t)gw.m * gw.m);
-    l.b.sched = c.take<int2>((size_t)4 * edge_blocks_bound(n, nnz));
+    const long long sn = slice_nodes();
+    l.nslices = edge_slices(n, sn);
+    l.slice_col = c.take<int>((size_t)nnz);
+    if (l.nslices > 1) {
+        l.slice_rp = c.take<int>((size_t)l.nslices * ((size_t)n + 1));
+        l.fpart = c.take<float2>((size_t)n);
+    }
+    l.sched = c.take<int2>((size_t)4 * edge_blocks_bound(n, nnz, sn));
     for (int k = 1; k <= kw; ++k) l.tw[k] = c.take<float2>((size_t)make_geom(p->n_int, k).L);
     *bytes = (c.off + 255) & ~(size_t)255;
     return l;
@@ -106,8 +133,10 @@ bool finite_f(float v) { return std::isfinite(v); }
 // each (slot 0 = {row, -1}); the other rows are cut, in order, into wave
 // groups of at most kGroupRows rows and kGroupEdges entries, four groups per
 // block (slot = {first row, rows}; {0, 0} = idle wave). Heavy blocks first.
-std::vector<int2> build_edge_schedule(const std::vector<int>& rp, int n) {
+// local[r] receives the row's index inside its wave group (0 for heavy rows).
+std::vector<int2> build_edge_schedule(const std::vector<int>& rp, int n, std::vector<int>& local) {
     std::vector<int2> heavy, groups;
+    local.assign((size_t)n, 0);
     int r = 0;
     while (r < n) {
         const int d = rp[r + 1] - rp[r];
@@ -122,6 +151,7 @@ std::vector<int2> build_edge_schedule(const std::vector<int>& rp, int n) {
             const int dd = rp[r + 1] - rp[r];
             if (dd > kGroupEdges || edges + dd > kGroupEdges) break;
             edges += dd;
+            local[r] = cnt;
             ++cnt;
             ++r;
         }
@@ -158,6 +188,9 @@ struct tfdp_layout {
     int k_ws;
     int t;
     Layout lay;
+    // captured iteration pairs: [k][parity of t at the start][orientation]
+    bool graphs;
+    hipGraphExec_t gexec[4][2][2];
     // profiling
     bool prof;
     std::vector<hipEvent_t> ev_pool;
@@ -233,6 +266,128 @@ void enqueue_box(tfdp_layout* h, const float2* pos, int set, hipStream_t s) {
     launch_box_reduce(pos, h->n, h->lay.b.st, set, s);
 }
 
+// Column slices of the edge pass: for slice s (columns [s W, (s+1) W),
+// W = ceil(n / nslices)) a CSR of all rows holding each row's entries of
+// that column range in their original order, and its schedule. Entries are
+// stored packed, column | (row index inside its wave group) << 26, so that a
+// lane knows its row without searching. With one slice the caller's row_ptr
+// is used as is. Built on the host from copies of the caller's CSR (init
+// only).
+tfdp_status build_slices(tfdp_layout* h, hipStream_t stream) {
+    const int n = h->n;
+    const long long nnz = h->nnz;
+    Layout& l = h->lay;
+    std::vector<int> rp((size_t)n + 1);
+    tfdp_status st = check_hip(hipMemcpy(rp.data(), h->row_ptr, rp.size() * sizeof(int), hipMemcpyDeviceToHost),
+                               "hipMemcpy");
+    if (st != TFDP_OK) return st;
+    std::vector<int> ci((size_t)nnz);
+    if (nnz > 0)
+        st = check_hip(hipMemcpy(ci.data(), h->col_idx, ci.size() * sizeof(int), hipMemcpyDeviceToHost),
+                       "hipMemcpy");
+    if (st != TFDP_OK) return st;
+    const int S = l.nslices;
+    const long long W = ((long long)n + S - 1) / S;
+    std::vector<int> srp((size_t)S * ((size_t)n + 1), 0);
+    for (int i = 0; i < n; ++i)
+        for (int e = rp[i]; e < rp[i + 1]; ++e) srp[(size_t)(ci[e] / W) * (n + 1) + i + 1] += 1;
+    std::vector<long long> col_off(S + 1, 0);
+    for (int s = 0; s < S; ++s) {
+        int* r = srp.data() + (size_t)s * (n + 1);
+        for (int i = 0; i < n; ++i) r[i + 1] += r[i];
+        col_off[s + 1] = col_off[s] + r[n];
+    }
+    std::vector<int2> all_sched;
+    std::vector<int> scol((size_t)nnz);
+    std::vector<int> local;
+    for (int s = 0; s < S; ++s) {
+        std::vector<int> r(srp.begin() + (size_t)s * (n + 1), srp.begin() + (size_t)(s + 1) * (n + 1));
+        std::vector<int2> sch = build_edge_schedule(r, n, local);
+        int* out = scol.data() + col_off[s];
+        for (int i = 0; i < n; ++i) {
+            int f = r[i];
+            for (int e = rp[i]; e < rp[i + 1]; ++e)
+                if (ci[e] / W == s) out[f++] = ci[e] | (local[i] << 26);
+        }
+        l.slice[s].rp = S == 1 ? h->row_ptr : l.slice_rp + (size_t)s * (n + 1);
+        l.slice[s].col = l.slice_col + col_off[s];
+        l.slice[s].sched = l.sched + all_sched.size();
+        l.slice[s].blocks = (int)(sch.size() / 4);
+        all_sched.insert(all_sched.end(), sch.begin(), sch.end());
+    }
+    if ((long long)all_sched.size() > 4 * edge_blocks_bound(n, nnz, slice_nodes())) {
+        set_msg("internal: edge schedule exceeds its bound");
+        return TFDP_ERR_WORKSPACE;
+    }
+    if (S > 1)
+        st = check_hip(hipMemcpyAsync(l.slice_rp, srp.data(), srp.size() * sizeof(int), hipMemcpyHostToDevice,
+                                      stream), "hipMemcpyAsync");
+    if (st == TFDP_OK && nnz > 0)
+        st = check_hip(hipMemcpyAsync(l.slice_col, scol.data(), scol.size() * sizeof(int), hipMemcpyHostToDevice,
+                                      stream), "hipMemcpyAsync");
+    if (st == TFDP_OK)
+        st = check_hip(hipMemcpyAsync(l.sched, all_sched.data(), all_sched.size() * sizeof(int2),
+                                      hipMemcpyHostToDevice, stream), "hipMemcpyAsync");
+    if (st == TFDP_OK) st = check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    return st;
+}
+
+// Edge pass of one iteration: slices 0 .. S-2 accumulate attraction sums,
+// the last slice finishes every node (pos_out == nullptr: force outputs).
+void enqueue_edges(tfdp_layout* h, const float2* pos, float2* pos_out, const Bufs& b, const Geom& g,
+                   const ModelArgs& a, int set, float2* fr, float2* fa, float2* ft, hipStream_t s) {
+    const Layout& l = h->lay;
+    const int S = l.nslices;
+    for (int sl = 0; sl + 1 < S; ++sl)
+        launch_edges(pos, nullptr, l.slice[sl], sl == 0 ? 0 : 1, 0, l.fpart, b, g, a, set, nullptr, nullptr,
+                     nullptr, s);
+    launch_edges(pos, pos_out, l.slice[S - 1], 2, S > 1 ? 1 : 0, l.fpart, b, g, a, set, fr, fa, ft, s);
+}
+
+void drop_graphs(tfdp_layout* h) {
+    for (int k = 0; k < 4; ++k)
+        for (int p = 0; p < 2; ++p)
+            for (int o = 0; o < 2; ++o)
+                if (h->gexec[k][p][o]) {
+                    (void)hipGraphExecDestroy(h->gexec[k][p][o]);
+                    h->gexec[k][p][o] = nullptr;
+                }
+}
+
+// One interpolated iteration (k >= 1) from cur to alt; `set` = t & 1 selects
+// the box-extremes slot set read now (set ^ 1 is filled by the update).
+void enqueue_iteration(tfdp_layout* h, int k, int set, const float2* cur, float2* alt, const ModelArgs& a,
+                       hipStream_t s) {
+    const Bufs b = bufs_for(h, k);
+    const Geom g = make_geom(h->p.n_int, k);
+    enqueue_grid(h, cur, b, g, set, s);
+    PhaseTimer pt(h, PH_GATHER, s);
+    enqueue_edges(h, cur, alt, b, g, a, set ^ 1, nullptr, nullptr, nullptr, s);
+}
+
+// Graph of two consecutive iterations at k starting with slot set `parity`
+// and positions in the caller's buffer (orient 0) or the second buffer
+// (orient 1); captured on first use.
+hipGraphExec_t pair_graph(tfdp_layout* h, int k, int parity, int orient, const ModelArgs& a, hipStream_t s) {
+    hipGraphExec_t& ex = h->gexec[k][parity][orient];
+    if (ex) return ex;
+    float2* A = reinterpret_cast<float2*>(h->pos);
+    float2* B = h->lay.pos_alt;
+    if (orient) {
+        float2* t = A;
+        A = B;
+        B = t;
+    }
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
+    enqueue_iteration(h, k, parity, A, B, a, s);
+    enqueue_iteration(h, k, parity ^ 1, B, A, a, s);
+    hipGraph_t graph = nullptr;
+    if (hipStreamEndCapture(s, &graph) != hipSuccess || !graph) return nullptr;
+    if (hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
+    (void)hipGraphDestroy(graph);
+    return ex;
+}
+
 int k_at(const tfdp_params& p, int t) {
     if (p.k_mode >= 0) return p.k_mode;
     const int T = p.total_iters;
@@ -298,6 +453,10 @@ tfdp_status tfdp_params_validate(const tfdp_params* p, int32_t n, int64_t nnz) {
         set_msg("t0 must be finite");
         return TFDP_ERR_INVALID_ARG;
     }
+    if (n > (1 << 26)) {
+        set_msg("n above 2^26 is not supported (packed edge entries)");
+        return TFDP_ERR_UNSUPPORTED;
+    }
     if ((long long)p->n_int * k_workspace(p) > kMaxL / 2) {
         set_msg("n_int * k exceeds 1024 (FFT length above 2048)");
         return TFDP_ERR_UNSUPPORTED;
@@ -355,12 +514,16 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
     h->k_ws = k_workspace(p);
     h->t = 0;
     h->prof = false;
+    h->graphs = true;
+    std::memset(h->gexec, 0, sizeof(h->gexec));
     h->ev_used = 0;
     h->ev_stream = nullptr;
     size_t bytes = 0;
     h->lay = carve(d_ws, n, nnz, p, &bytes);
 
     DevState* dst = h->lay.b.st;
+    static const bool attrs = (init_kernel_attributes(), true);
+    (void)attrs;
     st = check_hip(hipMemsetAsync(dst, 0, sizeof(DevState), stream), "hipMemsetAsync");
     if (st == TFDP_OK) {
         if (nnz > 0 || n > 0) launch_csr_check(d_row_ptr, d_col_idx, n, nnz, dst, stream);
@@ -374,23 +537,7 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
         set_msg("invalid CSR: row_ptr must start at 0, be monotone and end at nnz; columns in [0, n) without self-loops");
         st = TFDP_ERR_INVALID_ARG;
     }
-    if (st == TFDP_OK) {
-        std::vector<int> rp((size_t)n + 1);
-        st = check_hip(hipMemcpy(rp.data(), d_row_ptr, rp.size() * sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy");
-        if (st == TFDP_OK) {
-            std::vector<int2> sched = build_edge_schedule(rp, n);
-            h->lay.b.edge_blocks = (int)(sched.size() / 4);
-            if ((long long)h->lay.b.edge_blocks > edge_blocks_bound(n, nnz)) {
-                set_msg("internal: edge schedule exceeds its bound");
-                st = TFDP_ERR_WORKSPACE;
-            } else {
-                st = check_hip(hipMemcpyAsync(const_cast<int2*>(h->lay.b.sched), sched.data(),
-                                              sched.size() * sizeof(int2), hipMemcpyHostToDevice, stream),
-                               "hipMemcpyAsync");
-                if (st == TFDP_OK) st = check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
-            }
-        }
-    }
+    if (st == TFDP_OK) st = build_slices(h, stream);
     if (st != TFDP_OK) {
         delete h;
         return st;
@@ -411,24 +558,33 @@ tfdp_status tfdp_layout_step(tfdp_layout* h, int32_t iters, hipStream_t s) {
     float2* cur = reinterpret_cast<float2*>(h->pos);
     float2* alt = h->lay.pos_alt;
     enqueue_box(h, cur, h->t & 1, s);
-    for (int it = 0; it < iters; ++it) {
+    const bool use_graphs = h->graphs && !h->prof;
+    for (int it = 0; it < iters;) {
         const int k = k_at(h->p, h->t);
+        if (use_graphs && k > 0 && it + 1 < iters && k_at(h->p, h->t + 1) == k) {
+            const int orient = cur == reinterpret_cast<float2*>(h->pos) ? 0 : 1;
+            hipGraphExec_t ex = pair_graph(h, k, h->t & 1, orient, a, s);
+            if (ex) {
+                tfdp_status st = check_hip(hipGraphLaunch(ex, s), "hipGraphLaunch");
+                if (st != TFDP_OK) return st;
+                h->t += 2;
+                it += 2;
+                continue;  // two swaps: cur and alt keep their roles
+            }
+            (void)hipGetLastError();
+        }
         if (k == 0) {
             PhaseTimer pt(h, PH_BRUTE, s);
             launch_brute(cur, alt, h->row_ptr, h->col_idx, h->n, h->lay.b.st, a, h->t, nullptr, nullptr,
                          nullptr, s);
         } else {
-            const Bufs b = bufs_for(h, k);
-            const Geom g = make_geom(h->p.n_int, k);
-            const int set = h->t & 1;
-            enqueue_grid(h, cur, b, g, set, s);
-            PhaseTimer pt(h, PH_GATHER, s);
-            launch_gather(cur, alt, h->row_ptr, h->col_idx, b, g, a, set ^ 1, nullptr, nullptr, nullptr, s);
+            enqueue_iteration(h, k, h->t & 1, cur, alt, a, s);
         }
         float2* tmp = cur;
         cur = alt;
         alt = tmp;
         h->t += 1;
+        ++it;
     }
     if (cur != reinterpret_cast<float2*>(h->pos)) {
         tfdp_status st = check_hip(hipMemcpyAsync(h->pos, cur, (size_t)h->n * sizeof(float2),
@@ -463,7 +619,7 @@ tfdp_status tfdp_layout_forces(tfdp_layout* h, const float* d_pos_in, int32_t k,
         const Geom g = make_geom(h->p.n_int, k);
         enqueue_grid(h, pos, b, g, 0, s);
         PhaseTimer pt(h, PH_GATHER, s);
-        launch_gather(pos, nullptr, h->row_ptr, h->col_idx, b, g, a, 1, fr, fa, ft, s);
+        enqueue_edges(h, pos, nullptr, b, g, a, 1, fr, fa, ft, s);
     }
     return check_hip(hipGetLastError(), "kernel launch");
 }
@@ -484,6 +640,7 @@ tfdp_status tfdp_layout_set_params(tfdp_layout* h, const tfdp_params* p) {
         return TFDP_ERR_WORKSPACE;
     }
     h->p = *p;
+    drop_graphs(h);
     return TFDP_OK;
 }
 
@@ -529,6 +686,7 @@ tfdp_status tfdp_layout_sync_status(tfdp_layout* h, hipStream_t s) {
 
 void tfdp_layout_destroy(tfdp_layout* h) {
     if (!h) return;
+    drop_graphs(h);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     delete h;
 }
@@ -541,6 +699,16 @@ tfdp_status tfdp_layout_set_profiling(tfdp_layout* h, int32_t enable) {
     h->prof = enable != 0;
     h->ev_used = 0;
     h->ev_phase.clear();
+    return TFDP_OK;
+}
+
+tfdp_status tfdp_layout_set_graphs(tfdp_layout* h, int32_t enable) {
+    if (!h) {
+        set_msg("invalid handle");
+        return TFDP_ERR_INVALID_ARG;
+    }
+    h->graphs = enable != 0;
+    if (!h->graphs) drop_graphs(h);
     return TFDP_OK;
 }
 

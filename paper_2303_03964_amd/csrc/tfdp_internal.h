@@ -14,6 +14,8 @@ constexpr int kBoxSlots = 64;        // slots of the box extremes (one 128-byte 
 constexpr int kMaxL = 2048;          // largest FFT length per side
 constexpr int kMaxNInt = 1024;       // largest number of intervals per side
 constexpr int kGroupEdges = 512;     // CSR entries of one wave group of the edge pass
+constexpr int kSliceNodesDefault = 1 << 24;  // column slice width of the edge pass (nodes)
+constexpr int kMaxSlices = 64;
 constexpr int kGroupRows = 64;       // rows of one wave group of the edge pass
 
 // Square box of the current positions, in float64 (lo, side W, interval h = W / N_int).
@@ -63,9 +65,16 @@ struct Bufs {
     float2* pcol;        // [3][H][M] potential row spectra after the column pass
     float4* pot;         // [M][M] (phi_1, G_x, G_y, 0)
     const float2* tw;    // twiddles for this L: exp(-2 pi i j / L), j < L
-    const int2* sched;   // [4 * edge_blocks] edge-pass schedule (see node_forces.hip)
-    int edge_blocks;
     DevState* st;
+};
+
+// One column slice of the edge pass: the CSR entries whose column lies in one
+// contiguous column range, as a CSR of all n rows, with its schedule.
+struct EdgeSlice {
+    const int* rp;       // [n + 1]
+    const int* col;      // [entries of the slice]
+    const int2* sched;   // [4 * blocks]
+    int blocks;
 };
 
 struct ModelArgs {
@@ -85,9 +94,13 @@ void launch_rowfft(const Bufs& b, const Geom& g, hipStream_t s);
 void launch_colconv(const Bufs& b, const Geom& g, hipStream_t s);
 void launch_rowifft(const Bufs& b, const Geom& g, hipStream_t s);
 void launch_twiddles(float2* tw, int L, hipStream_t s);
-void launch_gather(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx,
-                   const Bufs& b, const Geom& g, const ModelArgs& a, int set,
-                   float2* f_rep, float2* f_att, float2* f_tot, hipStream_t s);
+void init_kernel_attributes();
+// Edge pass of slice `es`: mode 0 writes the slice's attraction sums to
+// fpart, mode 1 adds them to fpart, mode 2 (last slice) adds fpart (when
+// use_part) and finishes every node: repulsion gather, displacement, output.
+void launch_edges(const float2* pos, float2* pos_out, const EdgeSlice& es, int mode, int use_part,
+                  float2* fpart, const Bufs& b, const Geom& g, const ModelArgs& a, int set,
+                  float2* f_rep, float2* f_att, float2* f_tot, hipStream_t s);
 // Workgroups are dispatched to the 8 XCDs round robin. xcd_pair_block maps
 // the physical block index so that logical blocks 2j and 2j+1 run on the
 // same XCD (and so share its L2) when their stores fill one cache line
@@ -100,9 +113,16 @@ __device__ __forceinline__ int xcd_pair_block(int phys, int nb) {
     return logical < nb ? logical : -1;
 }
 
-// Upper bound of edge-pass blocks for n rows and nnz CSR entries.
-inline long long edge_blocks_bound(long long n, long long nnz) {
-    return (n + 3) / 4 + nnz / (kGroupEdges + 1) + 1;
+// Column slices for n nodes with slices of at most slice_nodes columns, and
+// an upper bound of the edge-pass blocks of all slices together (per slice
+// at most ceil(n/4) light blocks and one block per row with more than
+// kGroupEdges entries, plus one).
+inline int edge_slices(long long n, long long slice_nodes) {
+    long long s = (n + slice_nodes - 1) / slice_nodes;
+    return (int)(s < 1 ? 1 : (s > kMaxSlices ? kMaxSlices : s));
+}
+inline long long edge_blocks_bound(long long n, long long nnz, long long slice_nodes) {
+    return (long long)edge_slices(n, slice_nodes) * ((n + 3) / 4 + 1) + nnz / (kGroupEdges + 1) + 1;
 }
 void launch_brute(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx,
                   int n, DevState* st, const ModelArgs& a, int t,

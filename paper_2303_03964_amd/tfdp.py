@@ -67,6 +67,7 @@ _SIGS = {
     "tfdp_layout_destroy": (None, [c_void_p]),
     "tfdp_last_error": (c_char_p, []),
     "tfdp_layout_set_profiling": (c_int32, [c_void_p, c_int32]),
+    "tfdp_layout_set_graphs": (c_int32, [c_void_p, c_int32]),
     "tfdp_phase_count": (c_int32, []),
     "tfdp_phase_name": (c_char_p, [c_int32]),
     "tfdp_layout_phase_times": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64), c_int32]),
@@ -181,6 +182,10 @@ def tfdp_layout_destroy(h):
 
 def tfdp_layout_set_profiling(h, enable):
     return _check(load_library().tfdp_layout_set_profiling(h, int(bool(enable))))
+
+
+def tfdp_layout_set_graphs(h, enable):
+    return _check(load_library().tfdp_layout_set_graphs(h, int(bool(enable))))
 
 
 def tfdp_phase_count() -> int:

@@ -102,6 +102,7 @@ def test_null_handle_calls():
     assert lib.tfdp_layout_set_iter(None, 3) == INVALID
     assert lib.tfdp_layout_sync_status(None, None) == INVALID
     assert lib.tfdp_layout_set_profiling(None, 1) == INVALID
+    assert lib.tfdp_layout_set_graphs(None, 1) == INVALID
     lib.tfdp_layout_destroy(None)
 
 

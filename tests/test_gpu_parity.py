@@ -313,3 +313,100 @@ def test_profiling_phase_times(T):
     assert all(ms >= 0 for ms, _ in times.values())
     T.tfdp_layout_set_profiling(lay.handle, 0)
     lay.close()
+
+
+# ------------------------------------------------------------------ column-sliced edge pass, full size
+
+@pytest.mark.parametrize("n,slice_nodes", [(300001, 262144), (600000, 262144), (20011, 4096)])
+def test_multi_slice_edge_pass(T, n, slice_nodes, monkeypatch):
+    # column-sliced edge pass (slice width set at init), 2 to 5 slices
+    monkeypatch.setenv("TFDP_EDGE_SLICE_NODES", str(slice_nodes))
+    g = sg.chung_lu(n, 2.5, 10.0, 61)
+    pos = sg.uniform_positions(n, 62, -40.0, 40.0)
+    check(T, g, pos, 1, 128)
+    check(T, g, pos, 2, 128)
+    # one update step through the sliced pass
+    import torch
+    lay = make_layout(T, g, pos, n_int=128, k_mode=1, total_iters=10)
+    lay.step(1)
+    torch.cuda.synchronize()
+    got = lay.pos.cpu().numpy().astype(np.float64)
+    op = ot.Params(n_int=128, k_mode=1, total_iters=10)
+    _, _, disp = ot.forces(pos.astype(np.float64), g.row_ptr, g.col_idx, op, 1)
+    want = ot.capped_move(pos.astype(np.float64), disp, ot.step_cap(0, 10, ot.default_t0(n)))
+    assert rel_l2(got - pos, want - pos) <= 1e-5
+    lay.close()
+
+
+def test_chung_lu_1m_bench_configuration(T):
+    # the benchmarked workload and launch configuration, compared in full
+    import torch
+    w = sg.chung_lu_1m()
+    g = w.graph
+    p = T.tfdp_params_default(n_int=w.n_int, total_iters=w.iters)
+    lay = T.Layout(g.row_ptr, g.col_idx, w.pos0, p)
+    for k in (1, 3):
+        got = gpu_forces(lay, w.pos0, k)
+        want = oracle_forces(g, w.pos0, k, w.n_int)
+        errs = [rel_l2(a_, b_) for a_, b_ in zip(got, want)]
+        say(f"1M start k={k}: {errs}")
+        assert max(errs) <= TOL
+    lay.step(30)
+    torch.cuda.synchronize()
+    assert lay.sync_status() == 0
+    pos30 = lay.pos.cpu().numpy()
+    got = gpu_forces(lay, pos30, 1)
+    want = oracle_forces(g, pos30, 1, w.n_int)
+    errs = [rel_l2(a_, b_) for a_, b_ in zip(got, want)]
+    say(f"1M after 30 iterations k=1: {errs}")
+    assert max(errs) <= TOL
+    # interpolation against the exact sum on sampled nodes (a property of the
+    # scheme at this spacing, reported; bound only at k = 3)
+    rows = np.random.default_rng(0).choice(g.n, 64, replace=False)
+    exact = ot.repulsion_exact(pos30.astype(np.float64), 2.0, rows=rows)
+    f3 = gpu_forces(lay, pos30, 3)[0][rows]
+    say(f"1M after 30 iterations: k=3 vs exact on 64 sampled nodes: {rel_l2(f3, exact)}")
+    lay.close()
+
+
+# ------------------------------------------------------------------ captured iteration pairs
+
+def test_graph_replays_match_direct_launches(T):
+    # iteration pairs replayed from HIP graphs on a side stream give the same
+    # positions, bit for bit, as direct launches; checked after every chunk
+    # of steps (eager work and synchronisation between the replays), across
+    # the k = 1 -> 2 -> 3 boundaries and an odd chunk that leaves the
+    # positions in the second buffer
+    import torch
+    w = sg.sbm_1k()
+    p = T.tfdp_params_default(n_int=64, total_iters=300)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        a = T.Layout(w.graph.row_ptr, w.graph.col_idx, w.pos0, p)
+    b = T.Layout(w.graph.row_ptr, w.graph.col_idx, w.pos0, p)
+    T.tfdp_layout_set_graphs(b.handle, 0)
+    for chunk in (10, 7, 50, 203, 30):
+        with torch.cuda.stream(side):
+            a.step(chunk)
+        side.synchronize()
+        b.step(chunk)
+        torch.cuda.synchronize()
+        assert a.iteration == b.iteration
+        assert torch.equal(a.pos, b.pos), f"mismatch after t={a.iteration}"
+        # eager work between replays
+        _ = (a.pos * 2.0).sum().item()
+    with torch.cuda.stream(side):
+        # re-tune drops the graphs; the next steps capture new ones
+        q = T.tfdp_params_default(n_int=64, total_iters=300, gamma=3.0, rep_weight=2.0)
+        a.set_params(q)
+        a.iteration = 100
+        a.step(20)
+    side.synchronize()
+    b.set_params(q)
+    b.iteration = 100
+    b.step(20)
+    torch.cuda.synchronize()
+    assert torch.equal(a.pos, b.pos)
+    assert a.sync_status() == 0 and b.sync_status() == 0
+    a.close()
+    b.close()
