@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations (0: about 15 s of work)")
     ap.add_argument("--repeats", type=int, default=1, help="timed repeats; value is the median")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload section")
+    ap.add_argument("--batch-graphs", type=int, default=512)
+    ap.add_argument("--batch-iters", type=int, default=300)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="copy this many MiB device-to-device once before the run (a plain copy kernel "
                          "of known size for scaling hardware byte counters)")
@@ -115,6 +118,76 @@ def cpu_baseline(w, iters):
         "kind": "oracle",
         "sample": f"{done} iterations (k=1) of the FP64 NumPy oracle on the same {g.n}-node graph; "
                   f"{wall:.1f} s wall, {cpu:.1f} s CPU; host os.cpu_count()={os.cpu_count()}",
+    }
+
+
+def batched_section(T, torch, stream, graphs, iters):
+    """Batched workload: `graphs` SBMs with n log-uniform in [200, 20000]
+    (2..20 blocks, mean degree 8), N_int from the size rule of the grid
+    autotuner, T = iters. Times one tfdp_batch_step(iters) over all graphs
+    against the same graphs stepped one after another with
+    tfdp_layout_step(iters) on the same stream, from the same positions."""
+    import synthgraphs as sg
+    from paper_2303_03964_amd import autotune
+    t_gen = time.perf_counter()
+    members = [sg.sbm_batch_member(i) for i in range(graphs)]
+    gen_s = time.perf_counter() - t_gen
+    lays, pos0 = [], []
+    for g, pos in members:
+        p = T.tfdp_params_default(n_int=autotune.n_int_for_size(g.n), total_iters=iters, k_mode=-1)
+        pt = torch.as_tensor(pos).cuda()
+        pos0.append(pt.clone())
+        lays.append(T.Layout(g.row_ptr, g.col_idx, pt, p))
+    n_tot = sum(l.n for l in lays)
+    nnz_tot = sum(l.nnz for l in lays)
+    B = T.Batch(len(lays))
+    for lay in lays:
+        B.add(lay)
+
+    def reset():
+        for lay, p0 in zip(lays, pos0):
+            lay.pos.copy_(p0)
+            lay.iteration = 0
+        torch.cuda.synchronize()
+
+    # warm-up: device tables, captured graphs, plain graphs
+    B.step(iters)
+    for lay in lays:
+        lay.step(iters)
+    torch.cuda.synchronize()
+    reset()
+    t0 = time.perf_counter()
+    B.step(iters)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    final_batch = [lay.pos.clone() for lay in lays]
+    reset()
+    t0 = time.perf_counter()
+    for lay in lays:
+        lay.step(iters)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    same = all(torch.equal(a, lay.pos) for a, lay in zip(final_batch, lays))
+    bad = [lay.sync_status() for lay in lays]
+    B.close()
+    for lay in lays:
+        lay.close()
+    return {
+        "workload": f"sbm_batch_{graphs}: SBMs, n log-uniform [200, 20000], 2..20 blocks, mean degree 8",
+        "graphs": graphs,
+        "nodes": n_tot,
+        "nnz": nnz_tot,
+        "iters": iters,
+        "n_int_rule": "64 (n/1000)^(1/5) rounded up to a multiple of 8",
+        "value": n_tot * iters / t_batch,
+        "unit": "node-iterations/s",
+        "ms": t_batch * 1e3,
+        "sequential_value": n_tot * iters / t_seq,
+        "sequential_ms": t_seq * 1e3,
+        "speedup_vs_sequential": t_seq / t_batch,
+        "bitwise_equal_to_sequential": bool(same),
+        "nonfinite_members": int(sum(1 for v in bad if v != 0)),
+        "generation_s": gen_s,
     }
 
 
@@ -241,9 +314,12 @@ def main():
         "iteration_ms_k1_events": iter_ms_k1,
         "hip_graphs": not args.no_graphs,
     }
+    lay.close()
+    if not args.no_batch:
+        rec["batched"] = batched_section(T, torch, stream, args.batch_graphs, args.batch_iters)
+        print(f"# batched: {json.dumps(rec['batched'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
-    lay.close()
     print(json.dumps(rec), flush=True)
 
 

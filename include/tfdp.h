@@ -145,9 +145,13 @@ tfdp_status tfdp_layout_forces(tfdp_layout* h, const float* d_pos_in, int32_t k,
                                hipStream_t stream);
 
 /* Replace the parameters (re-tune, Sec. 5 "Global Refinement"). alpha, beta,
- * gamma, rep_weight, total_iters, t0 may change freely; n_int and k_mode only
- * within what the handle's workspace was sized for (TFDP_ERR_WORKSPACE
- * otherwise). Takes effect for work enqueued afterwards. */
+ * gamma, rep_weight, total_iters, t0 may change freely. n_int and k_mode may
+ * change when the handle's workspace (ws_bytes at init) holds the new grid:
+ * size it with tfdp_workspace_size for the largest grid planned
+ * (TFDP_ERR_WORKSPACE otherwise); the grid arrays are then re-laid inside the
+ * workspace, so work of the handle enqueued earlier must be ordered before
+ * later work (one stream, or synchronised). Positions and the counter are
+ * kept. Takes effect for work enqueued afterwards. */
 tfdp_status tfdp_layout_set_params(tfdp_layout* h, const tfdp_params* p);
 
 /* Read / set the iteration counter t (checkpoint and resume: positions plus t
@@ -183,6 +187,49 @@ const char* tfdp_phase_name(int32_t phase);
  * enabled (arrays of at least tfdp_phase_count() entries); then reset. */
 tfdp_status tfdp_layout_phase_times(tfdp_layout* h, double* total_ms, int64_t* launches,
                                     int32_t nphases);
+
+/* ---- Batched stepping ----
+ *
+ * A batch steps many layout handles (graphs of any sizes, each with its own
+ * parameters, grid and iteration counter) together: every phase of an
+ * iteration is one launch per class of graphs that share the kernel shape
+ * (k, FFT length, spreading block), whose blocks each work on one graph, and
+ * iteration pairs are captured as HIP graphs. Each member's positions and
+ * counter after tfdp_batch_step(b, iters) are bit-identical to those after
+ * tfdp_layout_step(h, iters) on that handle alone: the blocks of a batched
+ * launch run the same kernel code on the same data partition.
+ *
+ * The batch references the handles (it does not own them): remove a handle
+ * before destroying it. A handle may be in at most one batch at a time and
+ * may still be used with the plain calls between batch calls (the batch
+ * picks up new parameters and counters). All calls on one batch must be
+ * ordered on the device (one stream, or synchronised). Unlike the plain
+ * handle, the batch allocates small device tables (member descriptors and
+ * block maps, hipMalloc at the first step and when the membership changes)
+ * and frees them in tfdp_batch_destroy. */
+typedef struct tfdp_batch tfdp_batch; /* opaque handle (host memory) */
+
+/* Empty batch for up to `capacity` members (>= 1). No device work. */
+tfdp_status tfdp_batch_create(tfdp_batch** out, int32_t capacity);
+/* Add / remove a member (host bookkeeping; the device tables are rebuilt at
+ * the next step). TFDP_ERR_INVALID_ARG: NULL, already a member (add) or not
+ * a member (remove). TFDP_ERR_UNSUPPORTED: batch full, or a handle whose
+ * edge pass is split into column slices. */
+tfdp_status tfdp_batch_add(tfdp_batch* b, tfdp_layout* h);
+tfdp_status tfdp_batch_remove(tfdp_batch* b, tfdp_layout* h);
+/* Number of members (0 for NULL). */
+int32_t tfdp_batch_count(const tfdp_batch* b);
+/* Advance every member by `iters` iterations (asynchronous, on `stream`),
+ * each from its own counter t with its own k schedule and parameters
+ * (k_mode 0 members run the exact method by their plain kernel). Membership
+ * or counter changes since the last call cost one stream synchronisation.
+ * Asynchronous failures are reported per member by tfdp_layout_sync_status. */
+tfdp_status tfdp_batch_step(tfdp_batch* b, int32_t iters, hipStream_t stream);
+/* Capture iteration pairs as HIP graphs (default on; the stream must then
+ * not be the legacy default stream). */
+tfdp_status tfdp_batch_set_graphs(tfdp_batch* b, int32_t enable);
+/* Free the batch and its device tables (the members stay valid). */
+void tfdp_batch_destroy(tfdp_batch* b);
 
 #ifdef __cplusplus
 }

@@ -6,11 +6,19 @@ binding with the same function names. There is no CPU fallback: every entry
 point raises if the shared library is missing.
 """
 from .tfdp import (  # noqa: F401
+    Batch,
     Layout,
     TfdpError,
     TfdpParams,
     library_path,
     load_library,
+    tfdp_batch_add,
+    tfdp_batch_count,
+    tfdp_batch_create,
+    tfdp_batch_destroy,
+    tfdp_batch_remove,
+    tfdp_batch_set_graphs,
+    tfdp_batch_step,
     tfdp_last_error,
     tfdp_layout_destroy,
     tfdp_layout_forces,

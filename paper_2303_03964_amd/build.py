@@ -5,6 +5,7 @@ repository's entry module). Always recompiles.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
 import shutil
@@ -38,14 +39,18 @@ def build_library(verbose: bool = True) -> str:
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     objdir = os.path.join(ROOT, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in srcs:
-        obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [hipcc(), *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
-        if verbose:
+    objs = [os.path.join(objdir, os.path.basename(src) + ".o") for src in srcs]
+    cmds = [[hipcc(), *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj] for src, obj in zip(srcs, objs)]
+    if verbose:
+        for cmd in cmds:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+    # one compiler process per translation unit, at most four at a time
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(4, len(cmds))) as ex:
+        for res in ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds):
+            if res.stderr:
+                sys.stderr.write(res.stderr)
+            if res.returncode != 0:
+                raise subprocess.CalledProcessError(res.returncode, res.args, res.stdout, res.stderr)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

@@ -39,10 +39,10 @@ __global__ void k_box_begin(DevState* st, int t) {
     if (threadIdx.x == 0) st->t = t - 1;
 }
 
-__global__ __launch_bounds__(kThreads) void k_box_reduce(const float2* __restrict__ pos, int n,
-                                                         DevState* st, int set) {
+__device__ __forceinline__ void box_reduce_body(const float2* __restrict__ pos, int n, DevState* st, int set,
+                                                int bid, int nblocks) {
     float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (int i = bid * blockDim.x + threadIdx.x; i < n; i += nblocks * blockDim.x) {
         float2 p = pos[i];
         if (isfinite(p.x) && isfinite(p.y)) {
             xmin = fminf(xmin, p.x);
@@ -51,18 +51,28 @@ __global__ __launch_bounds__(kThreads) void k_box_reduce(const float2* __restric
             ymax = fmaxf(ymax, p.y);
         }
     }
-    block_minmax_commit(xmin, ymin, xmax, ymax, st, set);
+    block_minmax_commit(xmin, ymin, xmax, ymax, st, set, bid);
+}
+
+__global__ __launch_bounds__(kThreads) void k_box_reduce(const float2* __restrict__ pos, int n,
+                                                         DevState* st, int set) {
+    box_reduce_body(pos, n, st, set, blockIdx.x, gridDim.x);
 }
 
 void launch_box_begin(DevState* st, int t, hipStream_t s) {
     hipLaunchKernelGGL(k_box_begin, dim3(1), dim3(kBoxSlots), 0, s, st, t);
 }
 
-void launch_box_reduce(const float2* pos, int n, DevState* st, int set, hipStream_t s) {
+Dims box_reduce_dims(int n) {
     int blocks = (n + kThreads * 8 - 1) / (kThreads * 8);
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_box_reduce, dim3(blocks), dim3(kThreads), 0, s, pos, n, st, set);
+    return Dims{blocks, kThreads, 0};
+}
+
+void launch_box_reduce(const float2* pos, int n, DevState* st, int set, hipStream_t s) {
+    const Dims d = box_reduce_dims(n);
+    hipLaunchKernelGGL(k_box_reduce, dim3(d.grid), dim3(d.block), 0, s, pos, n, st, set);
 }
 
 // ----------------------------------------------------------------- binning
@@ -70,7 +80,7 @@ void launch_box_reduce(const float2* pos, int n, DevState* st, int set, hipStrea
 // Box of this iteration from slot set `set` (every block derives it; block 0
 // publishes it for the later kernels of the iteration), then the LDS
 // histogram of interval rows of this block's nodes.
-__global__ __launch_bounds__(kThreads) void k_bin_count(const float2* __restrict__ pos, Bufs b, int set) {
+__device__ __forceinline__ void bin_count_body(const float2* __restrict__ pos, const Bufs& b, int set, int bid) {
     extern __shared__ int hist[];
     __shared__ Box sbox;
     const int n_int = b.n_int;
@@ -88,12 +98,12 @@ __global__ __launch_bounds__(kThreads) void k_bin_count(const float2* __restrict
         }
         if (threadIdx.x == 0) {
             sbox = box_from_extremes(a0, a1, a2, a3, n_int);
-            if (blockIdx.x == 0) b.st->box = sbox;
+            if (bid == 0) b.st->box = sbox;
         }
     }
     __syncthreads();
     const Box bx = sbox;
-    const int beg = blockIdx.x * kBinChunk;
+    const int beg = bid * kBinChunk;
     const int end = min(beg + kBinChunk, b.n);
     for (int i0 = beg + threadIdx.x; i0 < end; i0 += 4 * blockDim.x) {
         float yv[4];
@@ -111,7 +121,11 @@ __global__ __launch_bounds__(kThreads) void k_bin_count(const float2* __restrict
     }
     __syncthreads();
     for (int c = threadIdx.x; c < n_int; c += blockDim.x)
-        b.blkcnt[(size_t)c * b.nblk + blockIdx.x] = hist[c];
+        b.blkcnt[(size_t)c * b.nblk + bid] = hist[c];
+}
+
+__global__ __launch_bounds__(kThreads) void k_bin_count(const float2* __restrict__ pos, Bufs b, int set) {
+    bin_count_body(pos, b, set, blockIdx.x);
 }
 
 // Exclusive scan of kThreads values held one per thread; returns the
@@ -140,9 +154,8 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* lds /* kThreads/
 // place, total into bucket_cnt.
 // Block 0 also resets slot set `reset_set` for the coming update and
 // advances the iteration counter.
-__global__ __launch_bounds__(kThreads) void k_bin_scan(Bufs b, int reset_set) {
+__device__ __forceinline__ void bin_scan_body(const Bufs& b, int reset_set, int c) {
     __shared__ int lds[kThreads / 64 + 1];
-    const int c = blockIdx.x;
     if (c == 0) {
         if (threadIdx.x < kBoxSlots) reset_slot(b.st, reset_set, threadIdx.x);
         if (threadIdx.x == 0) b.st->t += 1;
@@ -160,10 +173,14 @@ __global__ __launch_bounds__(kThreads) void k_bin_scan(Bufs b, int reset_set) {
     if (threadIdx.x == 0) b.bucket_cnt[c] = carry;
 }
 
+__global__ __launch_bounds__(kThreads) void k_bin_scan(Bufs b, int reset_set) {
+    bin_scan_body(b, reset_set, blockIdx.x);
+}
+
 // Stable scatter of the positions into interval-row buckets. Block 0 also
 // publishes the bucket starts and the first spreading chunk of each row
 // (rows split into chunks of kSpreadChunk nodes, at least one per row).
-__global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restrict__ pos, Bufs b) {
+__device__ __forceinline__ void bin_scatter_body(const float2* __restrict__ pos, const Bufs& b, int bid) {
     extern __shared__ int sm[];
     const int n_int = b.n_int;
     int* base = sm;                  // [n_int] global slot of this block's first node per row
@@ -181,9 +198,9 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restri
         const int ex = block_exclusive_scan(cnt, scan_lds, tot);
         const int ex2 = block_exclusive_scan(chunks, scan_lds, tot2);
         if (c < n_int) {
-            base[c] = carry + ex + b.blkcnt[(size_t)c * b.nblk + blockIdx.x];
+            base[c] = carry + ex + b.blkcnt[(size_t)c * b.nblk + bid];
             run[c] = 0;
-            if (blockIdx.x == 0) {
+            if (bid == 0) {
                 b.bucket_start[c] = carry + ex;
                 b.chunk_start[c] = chunk_carry + ex2;
                 for (int k = 0; k < chunks; ++k) b.chunk_row[chunk_carry + ex2 + k] = c;
@@ -192,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restri
         carry += tot;
         chunk_carry += tot2;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         b.bucket_start[n_int] = carry;
         b.chunk_start[n_int] = chunk_carry;
     }
@@ -205,7 +222,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restri
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int beg = blockIdx.x * kBinChunk;
+    const int beg = bid * kBinChunk;
     const int end = min(beg + kBinChunk, b.n);
     for (int r0 = beg; r0 < end; r0 += blockDim.x) {
         const int i = r0 + threadIdx.x;
@@ -243,17 +260,125 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restri
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restrict__ pos, Bufs b) {
+    bin_scatter_body(pos, b, blockIdx.x);
+}
+
+Dims bin_count_dims(const Bufs& b) { return Dims{b.nblk, kThreads, (size_t)b.n_int * sizeof(int)}; }
+Dims bin_scan_dims(const Bufs& b) { return Dims{b.n_int, kThreads, 0}; }
+Dims bin_scatter_dims(const Bufs& b) {
+    return Dims{b.nblk, kThreads, (size_t)(6 * b.n_int + kThreads / 64 + 1) * sizeof(int)};
+}
+
 void launch_bin_count(const float2* pos, const Bufs& b, int set, hipStream_t s) {
-    hipLaunchKernelGGL(k_bin_count, dim3(b.nblk), dim3(kThreads), b.n_int * sizeof(int), s, pos, b, set);
+    const Dims d = bin_count_dims(b);
+    hipLaunchKernelGGL(k_bin_count, dim3(d.grid), dim3(d.block), d.lds, s, pos, b, set);
 }
 
 void launch_bin_scan(const Bufs& b, int reset_set, hipStream_t s) {
-    hipLaunchKernelGGL(k_bin_scan, dim3(b.n_int), dim3(kThreads), 0, s, b, reset_set);
+    const Dims d = bin_scan_dims(b);
+    hipLaunchKernelGGL(k_bin_scan, dim3(d.grid), dim3(d.block), 0, s, b, reset_set);
 }
 
 void launch_bin_scatter(const float2* pos, const Bufs& b, hipStream_t s) {
-    size_t lds = (size_t)(6 * b.n_int + kThreads / 64 + 1) * sizeof(int);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(b.nblk), dim3(kThreads), lds, s, pos, b);
+    const Dims d = bin_scatter_dims(b);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(d.grid), dim3(d.block), d.lds, s, pos, b);
+}
+
+// ----------------------------------------------------------------- batched
+//
+// The same bodies over many graphs in one launch. Iteration j of a call
+// reads positions from pos (j even) or alt (j odd) of each member, like the
+// plain step, which swaps the two buffers after every iteration.
+
+__device__ __forceinline__ const float2* batch_cur(const Member& m, int j) { return (j & 1) ? m.alt : m.pos; }
+
+// Start of a call: both slot sets reset and the iteration counter set to
+// t0 - 1 (one block per member), then the box extremes of the positions into
+// set t0 & 1.
+__global__ void kb_box_begin(const Member* __restrict__ mem, const int2* __restrict__ map,
+                             const int* __restrict__ tcall) {
+    const Member& m = mem[map[blockIdx.x].x];
+    DevState* st = m.b.st;
+    if (threadIdx.x < kBoxSlots) {
+        reset_slot(st, 0, threadIdx.x);
+        reset_slot(st, 1, threadIdx.x);
+    }
+    if (threadIdx.x == 0) st->t = tcall[m.slot] - 1;
+}
+
+__global__ __launch_bounds__(kThreads) void kb_box_reduce(const Member* __restrict__ mem,
+                                                          const int2* __restrict__ map,
+                                                          const int* __restrict__ tcall) {
+    const int2 e = map[blockIdx.x];
+    const Member& m = mem[e.x];
+    box_reduce_body(m.pos, m.b.n, m.b.st, tcall[m.slot] & 1, e.y, m.box_blocks);
+}
+
+__global__ __launch_bounds__(kThreads) void kb_bin_count(const Member* __restrict__ mem,
+                                                         const int2* __restrict__ map,
+                                                         const int* __restrict__ tcall, int j) {
+    const int2 e = map[blockIdx.x];
+    const Member& m = mem[e.x];
+    bin_count_body(batch_cur(m, j), m.b, batch_set(tcall, m, j), e.y);
+}
+
+__global__ __launch_bounds__(kThreads) void kb_bin_scan(const Member* __restrict__ mem,
+                                                        const int2* __restrict__ map,
+                                                        const int* __restrict__ tcall, int j) {
+    const int2 e = map[blockIdx.x];
+    const Member& m = mem[e.x];
+    bin_scan_body(m.b, batch_set(tcall, m, j) ^ 1, e.y);
+}
+
+__global__ __launch_bounds__(kThreads) void kb_bin_scatter(const Member* __restrict__ mem,
+                                                           const int2* __restrict__ map, int j) {
+    const int2 e = map[blockIdx.x];
+    const Member& m = mem[e.x];
+    bin_scatter_body(batch_cur(m, j), m.b, e.y);
+}
+
+// Final copy of odd-length calls: alt -> pos, kThreads * 8 nodes per block.
+__global__ __launch_bounds__(kThreads) void kb_copy(const Member* __restrict__ mem,
+                                                    const int2* __restrict__ map) {
+    const int2 e = map[blockIdx.x];
+    const Member& m = mem[e.x];
+    const int beg = e.y * kThreads * 8;
+    const int end = min(beg + kThreads * 8, m.b.n);
+    for (int i = beg + threadIdx.x; i < end; i += kThreads) m.pos[i] = m.alt[i];
+}
+
+void launch_b_box(const Member* mem, const int2* map_begin, int n_begin, const int2* map_red, int n_red,
+                  const int* tcall, hipStream_t s) {
+    if (n_begin > 0) hipLaunchKernelGGL(kb_box_begin, dim3(n_begin), dim3(kBoxSlots), 0, s, mem, map_begin, tcall);
+    if (n_red > 0) hipLaunchKernelGGL(kb_box_reduce, dim3(n_red), dim3(kThreads), 0, s, mem, map_red, tcall);
+}
+
+void launch_b_bin_count(const Member* mem, const int2* map, int blocks, size_t lds, const int* tcall, int j,
+                        hipStream_t s) {
+    if (blocks > 0) hipLaunchKernelGGL(kb_bin_count, dim3(blocks), dim3(kThreads), lds, s, mem, map, tcall, j);
+}
+
+void launch_b_bin_scan(const Member* mem, const int2* map, int blocks, const int* tcall, int j, hipStream_t s) {
+    if (blocks > 0) hipLaunchKernelGGL(kb_bin_scan, dim3(blocks), dim3(kThreads), 0, s, mem, map, tcall, j);
+}
+
+void launch_b_bin_scatter(const Member* mem, const int2* map, int blocks, size_t lds, int j, hipStream_t s) {
+    if (blocks > 0) hipLaunchKernelGGL(kb_bin_scatter, dim3(blocks), dim3(kThreads), lds, s, mem, map, j);
+}
+
+// End of a call: every slot's counter advances by the call's iterations.
+__global__ void kb_advance(int* tcall, int slots, int iters) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < slots) tcall[i] += iters;
+}
+
+void launch_b_advance(int* tcall, int slots, int iters, hipStream_t s) {
+    if (slots > 0) hipLaunchKernelGGL(kb_advance, dim3((slots + 255) / 256), dim3(256), 0, s, tcall, slots, iters);
+}
+
+void launch_b_copy(const Member* mem, const int2* map, int blocks, hipStream_t s) {
+    if (blocks > 0) hipLaunchKernelGGL(kb_copy, dim3(blocks), dim3(kThreads), 0, s, mem, map);
 }
 
 }  // namespace tfdp

@@ -227,16 +227,17 @@ static void allow_big_lds(Kern k) {
 // Blocks past max_chunks: RBK kernel rows each, FFT over a of
 // K(a, b) + i H_x(a, b); the result is real, its even part the row spectrum of
 // K, minus its odd part the row spectrum of H_x divided by i.
+// bid < max_chunks: chunk block; otherwise lb = logical kernel-row block.
 template <int K, int LOGL>
-__global__ __launch_bounds__(512) void k_spread(Bufs b, Geom g, float gamma, int nw, int nkb) {
+__device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float gamma, int nw, int bid, int lb) {
     extern __shared__ float4 smem4[];
     const int M = g.m;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    if ((int)blockIdx.x < b.max_chunks) {
+    if (bid < b.max_chunks) {
         float* acc = reinterpret_cast<float*>(smem4);  // [nw][K][M][3]
         const int per = K * M * 3;
-        const int blk = blockIdx.x;
+        const int blk = bid;
         const int n_int = b.n_int;
         const int nchunks = b.chunk_start[n_int];
         const int cy = b.chunk_row[blk];
@@ -296,8 +297,6 @@ __global__ __launch_bounds__(512) void k_spread(Bufs b, Geom g, float gamma, int
     constexpr int TL = F * L;
     constexpr int RBK = RowTile<LOGL>::RBK;
     constexpr int NKT = (RBK + F - 1) / F;
-    const int lb = xcd_pair_block((int)blockIdx.x - b.max_chunks, nkb);
-    if (lb < 0) return;
     float2* z = reinterpret_cast<float2*>(smem4);
     const int H = g.H;
     const int r0 = lb * RBK;
@@ -332,17 +331,74 @@ __global__ __launch_bounds__(512) void k_spread(Bufs b, Geom g, float gamma, int
 }
 
 template <int K, int LOGL>
-static void launch_spread_t(const Bufs& b, const Geom& g, float gamma, hipStream_t s) {
-    const size_t per = (size_t)K * g.m * 3 * sizeof(float);
+__global__ __launch_bounds__(512) void k_spread(Bufs b, Geom g, float gamma, int nw, int nkb) {
+    const int bid = blockIdx.x;
+    int lb = -1;
+    if (bid >= b.max_chunks) {
+        lb = xcd_pair_block(bid - b.max_chunks, nkb);
+        if (lb < 0) return;
+    }
+    spread_body<K, LOGL>(b, g, gamma, nw, bid, lb);
+}
+
+// Batched: map entry {member, block}; blocks past the member's max_chunks
+// are its logical kernel-row blocks.
+template <int K, int LOGL>
+__global__ __launch_bounds__(512) void kb_spread(const Member* __restrict__ mem, const int2* __restrict__ map) {
+    const int2 e = map[blockIdx.x];
+    const Member& m = mem[e.x];
+    spread_body<K, LOGL>(m.b, m.g, m.a.gamma, m.nw, e.y, e.y - m.b.max_chunks);
+}
+
+Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
+    const size_t per = (size_t)g.k * g.m * 3 * sizeof(float);
     int nw = 8;
     while (nw > 1 && nw * per > 128 * 1024) nw >>= 1;
-    constexpr int F = task_ffts<LOGL>();
-    constexpr int RBK = RowTile<LOGL>::RBK;
-    const size_t kern = (size_t)((RBK + F - 1) / F) * F * (1 << LOGL) * sizeof(float2);
+    const int F = g.L < 512 ? 512 / g.L : 1;
+    const int RBK = 8;
+    const size_t kern = (size_t)((RBK + F - 1) / F) * F * g.L * sizeof(float2);
     const size_t lds = nw * per > kern ? nw * per : kern;
     const int nkb = (g.L + RBK - 1) / RBK;
-    hipLaunchKernelGGL((k_spread<K, LOGL>), dim3(b.max_chunks + xcd_pair_grid(nkb)), dim3(nw * 64), lds, s, b, g,
+    *nw_out = nw;
+    *nkb_out = nkb;
+    return Dims{b.max_chunks + nkb, nw * 64, lds};
+}
+
+template <int K, int LOGL>
+static void launch_spread_t(const Bufs& b, const Geom& g, float gamma, hipStream_t s) {
+    static_assert(RowTile<LOGL>::RBK == 8, "spread_dims assumes 8 kernel rows per block");
+    int nw, nkb;
+    const Dims d = spread_dims(b, g, &nw, &nkb);
+    hipLaunchKernelGGL((k_spread<K, LOGL>), dim3(b.max_chunks + xcd_pair_grid(nkb)), dim3(d.block), d.lds, s, b, g,
                        gamma, nw, nkb);
+}
+
+template <int K, int LOGL>
+static void launch_b_spread_t(const Member* mem, const int2* map, int blocks, int nw, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((kb_spread<K, LOGL>), dim3(blocks), dim3(nw * 64), lds, s, mem, map);
+}
+
+template <int K>
+static void launch_b_spread_k(int logL, int nw, const Member* mem, const int2* map, int blocks, size_t lds,
+                              hipStream_t s) {
+    switch (logL) {
+        case 6: launch_b_spread_t<K, 6>(mem, map, blocks, nw, lds, s); break;
+        case 7: launch_b_spread_t<K, 7>(mem, map, blocks, nw, lds, s); break;
+        case 8: launch_b_spread_t<K, 8>(mem, map, blocks, nw, lds, s); break;
+        case 9: launch_b_spread_t<K, 9>(mem, map, blocks, nw, lds, s); break;
+        case 10: launch_b_spread_t<K, 10>(mem, map, blocks, nw, lds, s); break;
+        default: launch_b_spread_t<K, 11>(mem, map, blocks, nw, lds, s); break;
+    }
+}
+
+void launch_b_spread(int k, int logL, int nw, const Member* mem, const int2* map, int blocks, size_t lds,
+                     hipStream_t s) {
+    if (blocks <= 0) return;
+    switch (k) {
+        case 1: launch_b_spread_k<1>(logL, nw, mem, map, blocks, lds, s); break;
+        case 2: launch_b_spread_k<2>(logL, nw, mem, map, blocks, lds, s); break;
+        default: launch_b_spread_k<3>(logL, nw, mem, map, blocks, lds, s); break;
+    }
 }
 
 template <int K>
@@ -370,15 +426,13 @@ void launch_spread(const Bufs& b, const Geom& g, float gamma, hipStream_t s) {
 // RB grid rows per (logical) block. Transforms of row pair q:
 // 3q = q1 + i qdx (row 2q), 3q+1 = qdy(2q) + i qdy(2q+1), 3q+2 = q1 + i qdx (row 2q+1).
 template <int LOGL>
-__global__ __launch_bounds__(RowTile<LOGL>::THREADS) void k_rowfft(Bufs b, Geom g, int nqb) {
+__device__ __forceinline__ void rowfft_body(const Bufs& b, const Geom& g, int lb) {
     extern __shared__ float2 z[];
     constexpr int L = 1 << LOGL;
     constexpr int F = task_ffts<LOGL>();
     constexpr int TL = F * L;
     constexpr int RB = RowTile<LOGL>::RB;
     constexpr int NQT = (3 * RB / 2 + F - 1) / F;
-    const int lb = xcd_pair_block(blockIdx.x, nqb);
-    if (lb < 0) return;
     const int M = g.m, H = g.H, K = g.k;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -433,14 +487,35 @@ __global__ __launch_bounds__(RowTile<LOGL>::THREADS) void k_rowfft(Bufs b, Geom 
 }
 
 template <int LOGL>
-static void launch_rowfft_t(const Bufs& b, const Geom& g, hipStream_t s) {
+__global__ __launch_bounds__(RowTile<LOGL>::THREADS) void k_rowfft(Bufs b, Geom g, int nqb) {
+    const int lb = xcd_pair_block(blockIdx.x, nqb);
+    if (lb < 0) return;
+    rowfft_body<LOGL>(b, g, lb);
+}
+
+template <int LOGL>
+__global__ __launch_bounds__(RowTile<LOGL>::THREADS) void kb_rowfft(const Member* __restrict__ mem,
+                                                                     const int2* __restrict__ map) {
+    const int2 e = map[blockIdx.x];
+    const Member& m = mem[e.x];
+    rowfft_body<LOGL>(m.b, m.g, e.y);
+}
+
+template <int LOGL>
+static Dims rowfft_dims_t(const Geom& g, int* nqb) {
     constexpr int F = task_ffts<LOGL>();
     constexpr int TL = F * (1 << LOGL);
     constexpr int RB = RowTile<LOGL>::RB;
     constexpr int NQT = (3 * RB / 2 + F - 1) / F;
-    const size_t lds = (size_t)NQT * TL * sizeof(float2);
-    const int nqb = (g.m + RB - 1) / RB;
-    hipLaunchKernelGGL(k_rowfft<LOGL>, dim3(xcd_pair_grid(nqb)), dim3(RowTile<LOGL>::THREADS), lds, s, b, g, nqb);
+    *nqb = (g.m + RB - 1) / RB;
+    return Dims{*nqb, RowTile<LOGL>::THREADS, (size_t)NQT * TL * sizeof(float2)};
+}
+
+template <int LOGL>
+static void launch_rowfft_t(const Bufs& b, const Geom& g, hipStream_t s) {
+    int nqb;
+    const Dims d = rowfft_dims_t<LOGL>(g, &nqb);
+    hipLaunchKernelGGL(k_rowfft<LOGL>, dim3(xcd_pair_grid(nqb)), dim3(d.block), d.lds, s, b, g, nqb);
 }
 
 void launch_rowfft(const Bufs& b, const Geom& g, hipStream_t s) {
@@ -463,7 +538,7 @@ void launch_rowfft(const Bufs& b, const Geom& g, hipStream_t s) {
 // then phi_1 = K^ Q1, G_x = H_x^ Q1 - K^ Qdx, G_y = H_y^ Q1 - K^ Qdy (scaled by
 // 1/L^2) and three inverse column FFTs; rows y < M stored column-major.
 template <int LOGL>
-__global__ __launch_bounds__(512) void k_colconv(Bufs b, Geom g) {
+__device__ __forceinline__ void colconv_body(const Bufs& b, const Geom& g, int bid) {
     extern __shared__ float2 sm2[];
     constexpr int L = 1 << LOGL;
     constexpr int logL = LOGL;
@@ -472,7 +547,7 @@ __global__ __launch_bounds__(512) void k_colconv(Bufs b, Geom g) {
     const int M = g.m, H = g.H;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int u0 = blockIdx.x * F;
+    const int u0 = bid * F;
     const Box bx = b.st->box;
     const float s = (float)(bx.h / (double)g.k);
     const float inv = 1.f / ((float)L * (float)L);
@@ -516,11 +591,27 @@ __global__ __launch_bounds__(512) void k_colconv(Bufs b, Geom g) {
 }
 
 template <int LOGL>
+__global__ __launch_bounds__(512) void k_colconv(Bufs b, Geom g) {
+    colconv_body<LOGL>(b, g, blockIdx.x);
+}
+
+template <int LOGL>
+__global__ __launch_bounds__(512) void kb_colconv(const Member* __restrict__ mem, const int2* __restrict__ map) {
+    const int2 e = map[blockIdx.x];
+    const Member& m = mem[e.x];
+    colconv_body<LOGL>(m.b, m.g, e.y);
+}
+
+Dims colconv_dims(const Geom& g) {
+    const int F = g.L < 512 ? 512 / g.L : 1;
+    return Dims{(g.H + F - 1) / F, 512, (size_t)5 * F * g.L * sizeof(float2)};
+}
+
+template <int LOGL>
 static void launch_colconv_t(const Bufs& b, const Geom& g, hipStream_t s) {
-    constexpr int F = task_ffts<LOGL>();
-    const int blocks = (g.H + F - 1) / F;
-    const size_t lds = (size_t)5 * F * g.L * sizeof(float2);
-    hipLaunchKernelGGL(k_colconv<LOGL>, dim3(blocks), dim3(512), lds, s, b, g);
+    static_assert(task_ffts<LOGL>() == ((1 << LOGL) < 512 ? 512 / (1 << LOGL) : 1), "colconv_dims");
+    const Dims d = colconv_dims(g);
+    hipLaunchKernelGGL(k_colconv<LOGL>, dim3(d.grid), dim3(d.block), d.lds, s, b, g);
 }
 
 void launch_colconv(const Bufs& b, const Geom& g, hipStream_t s) {
@@ -540,15 +631,13 @@ void launch_colconv(const Bufs& b, const Geom& g, hipStream_t s) {
 // phi_1 + i G_x (task area r), row pair q holds G_y(2q) + i G_y(2q+1)
 // (area RB + q); the spectra of real rows are extended by Hermitian symmetry.
 template <int LOGL>
-__global__ __launch_bounds__(RowTile<LOGL>::THREADS) void k_rowifft(Bufs b, Geom g, int nrb) {
+__device__ __forceinline__ void rowifft_body(const Bufs& b, const Geom& g, int lb) {
     extern __shared__ float2 z[];
     constexpr int L = 1 << LOGL;
     constexpr int F = task_ffts<LOGL>();
     constexpr int TL = F * L;
     constexpr int RB = RowTile<LOGL>::RB;
     constexpr int NT = (3 * RB / 2 + F - 1) / F;
-    const int lb = xcd_pair_block(blockIdx.x, nrb);
-    if (lb < 0) return;
     const int M = g.m, H = g.H;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -592,14 +681,35 @@ __global__ __launch_bounds__(RowTile<LOGL>::THREADS) void k_rowifft(Bufs b, Geom
 }
 
 template <int LOGL>
-static void launch_rowifft_t(const Bufs& b, const Geom& g, hipStream_t s) {
+__global__ __launch_bounds__(RowTile<LOGL>::THREADS) void k_rowifft(Bufs b, Geom g, int nrb) {
+    const int lb = xcd_pair_block(blockIdx.x, nrb);
+    if (lb < 0) return;
+    rowifft_body<LOGL>(b, g, lb);
+}
+
+template <int LOGL>
+__global__ __launch_bounds__(RowTile<LOGL>::THREADS) void kb_rowifft(const Member* __restrict__ mem,
+                                                                      const int2* __restrict__ map) {
+    const int2 e = map[blockIdx.x];
+    const Member& m = mem[e.x];
+    rowifft_body<LOGL>(m.b, m.g, e.y);
+}
+
+template <int LOGL>
+static Dims rowifft_dims_t(const Geom& g, int* nrb) {
     constexpr int F = task_ffts<LOGL>();
     constexpr int TL = F * (1 << LOGL);
     constexpr int RB = RowTile<LOGL>::RB;
     constexpr int NT = (3 * RB / 2 + F - 1) / F;
-    const int nrb = (g.m + RB - 1) / RB;
-    hipLaunchKernelGGL(k_rowifft<LOGL>, dim3(xcd_pair_grid(nrb)), dim3(RowTile<LOGL>::THREADS),
-                       (size_t)NT * TL * sizeof(float2), s, b, g, nrb);
+    *nrb = (g.m + RB - 1) / RB;
+    return Dims{*nrb, RowTile<LOGL>::THREADS, (size_t)NT * TL * sizeof(float2)};
+}
+
+template <int LOGL>
+static void launch_rowifft_t(const Bufs& b, const Geom& g, hipStream_t s) {
+    int nrb;
+    const Dims d = rowifft_dims_t<LOGL>(g, &nrb);
+    hipLaunchKernelGGL(k_rowifft<LOGL>, dim3(xcd_pair_grid(nrb)), dim3(d.block), d.lds, s, b, g, nrb);
 }
 
 void launch_rowifft(const Bufs& b, const Geom& g, hipStream_t s) {
@@ -613,6 +723,61 @@ void launch_rowifft(const Bufs& b, const Geom& g, hipStream_t s) {
     }
 }
 
+#define TFDP_LOGL_SWITCH(logL, CALL)        \
+    switch (logL) {                            \
+        case 6: CALL(6); break;                \
+        case 7: CALL(7); break;                \
+        case 8: CALL(8); break;                \
+        case 9: CALL(9); break;                \
+        case 10: CALL(10); break;              \
+        default: CALL(11); break;              \
+    }
+
+Dims rowfft_dims(const Geom& g, int* nqb) {
+    Dims d{};
+#define TFDP_D(LG) d = rowfft_dims_t<LG>(g, nqb)
+    TFDP_LOGL_SWITCH(g.logL, TFDP_D)
+#undef TFDP_D
+    return d;
+}
+
+Dims rowifft_dims(const Geom& g, int* nrb) {
+    Dims d{};
+#define TFDP_D(LG) d = rowifft_dims_t<LG>(g, nrb)
+    TFDP_LOGL_SWITCH(g.logL, TFDP_D)
+#undef TFDP_D
+    return d;
+}
+
+void launch_b_rowfft(int logL, const Member* mem, const int2* map, int blocks, hipStream_t s) {
+    if (blocks <= 0) return;
+    const Geom g{1, 1, 1 << logL, logL, (1 << logL) / 2 + 1, 1};
+    int nqb;
+    const Dims d = rowfft_dims(g, &nqb);
+#define TFDP_L(LG) hipLaunchKernelGGL(kb_rowfft<LG>, dim3(blocks), dim3(d.block), d.lds, s, mem, map)
+    TFDP_LOGL_SWITCH(logL, TFDP_L)
+#undef TFDP_L
+}
+
+void launch_b_colconv(int logL, const Member* mem, const int2* map, int blocks, hipStream_t s) {
+    if (blocks <= 0) return;
+    const Geom g{1, 1, 1 << logL, logL, (1 << logL) / 2 + 1, 1};
+    const Dims d = colconv_dims(g);
+#define TFDP_L(LG) hipLaunchKernelGGL(kb_colconv<LG>, dim3(blocks), dim3(d.block), d.lds, s, mem, map)
+    TFDP_LOGL_SWITCH(logL, TFDP_L)
+#undef TFDP_L
+}
+
+void launch_b_rowifft(int logL, const Member* mem, const int2* map, int blocks, hipStream_t s) {
+    if (blocks <= 0) return;
+    const Geom g{1, 1, 1 << logL, logL, (1 << logL) / 2 + 1, 1};
+    int nrb;
+    const Dims d = rowifft_dims(g, &nrb);
+#define TFDP_L(LG) hipLaunchKernelGGL(kb_rowifft<LG>, dim3(blocks), dim3(d.block), d.lds, s, mem, map)
+    TFDP_LOGL_SWITCH(logL, TFDP_L)
+#undef TFDP_L
+}
+
 // Large-LDS attribute for every kernel instantiation that can exceed 64 KB
 // (called once at set-up, so that no attribute call happens during stream
 // capture).
@@ -624,6 +789,12 @@ static void allow_big_lds_all_l() {
     allow_big_lds(k_rowfft<LOGL>);
     allow_big_lds(k_colconv<LOGL>);
     allow_big_lds(k_rowifft<LOGL>);
+    allow_big_lds(kb_spread<1, LOGL>);
+    allow_big_lds(kb_spread<2, LOGL>);
+    allow_big_lds(kb_spread<3, LOGL>);
+    allow_big_lds(kb_rowfft<LOGL>);
+    allow_big_lds(kb_colconv<LOGL>);
+    allow_big_lds(kb_rowifft<LOGL>);
 }
 
 void init_kernel_attributes() {

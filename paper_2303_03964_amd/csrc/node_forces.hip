@@ -100,11 +100,10 @@ __device__ __forceinline__ void node_output(int i, float2 p, float frx, float fr
 // Slicing bounds the neighbour positions read by one launch to one column
 // range.
 template <int K, int MODE>
-__global__ __launch_bounds__(kThreads) void k_edges(const float2* __restrict__ pos,
-                                                    float2* __restrict__ pos_out, EdgeSlice es,
-                                                    int use_part, float2* __restrict__ fpart, Bufs b,
-                                                    Geom g, ModelArgs a, int set, float2* f_rep,
-                                                    float2* f_att, float2* f_tot) {
+__device__ __forceinline__ void edges_body(const float2* __restrict__ pos, float2* __restrict__ pos_out,
+                                           const EdgeSlice& es, int use_part, float2* __restrict__ fpart,
+                                           const Bufs& b, const Geom& g, const ModelArgs& a, int set,
+                                           float2* f_rep, float2* f_att, float2* f_tot, int bid) {
     __shared__ float accx[kThreads];
     __shared__ float accy[kThreads];
     __shared__ float hred[2][kThreads / 64];
@@ -116,7 +115,7 @@ __global__ __launch_bounds__(kThreads) void k_edges(const float2* __restrict__ p
     accx[threadIdx.x] = 0.f;
     accy[threadIdx.x] = 0.f;
     __syncthreads();
-    const int2 s0 = es.sched[4 * blockIdx.x];
+    const int2 s0 = es.sched[4 * bid];
     float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
     bool have = false;
     int i = 0;
@@ -163,7 +162,7 @@ __global__ __launch_bounds__(kThreads) void k_edges(const float2* __restrict__ p
             p = pr;
         }
     } else {
-        const int2 gd = es.sched[4 * blockIdx.x + w];
+        const int2 gd = es.sched[4 * bid + w];
         const int r0 = gd.x, nr = gd.y;
         if (nr > 0) {
             // positions of the group's rows in LDS; entry e carries its row's
@@ -230,7 +229,40 @@ __global__ __launch_bounds__(kThreads) void k_edges(const float2* __restrict__ p
             node_output(i, p, frx, fry, sax, say, a, b.st->t, b.st, pos_out, f_rep, f_att, f_tot, xmin, ymin,
                         xmax, ymax);
         }
-        if (pos_out != nullptr) block_minmax_commit(xmin, ymin, xmax, ymax, b.st, set);
+        if (pos_out != nullptr) block_minmax_commit(xmin, ymin, xmax, ymax, b.st, set, bid);
+    }
+}
+
+template <int K, int MODE>
+__global__ __launch_bounds__(kThreads) void k_edges(const float2* __restrict__ pos,
+                                                    float2* __restrict__ pos_out, EdgeSlice es,
+                                                    int use_part, float2* __restrict__ fpart, Bufs b,
+                                                    Geom g, ModelArgs a, int set, float2* f_rep,
+                                                    float2* f_att, float2* f_tot) {
+    edges_body<K, MODE>(pos, pos_out, es, use_part, fpart, b, g, a, set, f_rep, f_att, f_tot, blockIdx.x);
+}
+
+// Batched edge pass of iteration j of a call (single slice, positions moved
+// from the current buffer to the other one).
+template <int K>
+__global__ __launch_bounds__(kThreads) void kb_edges(const Member* __restrict__ mem, const int2* __restrict__ map,
+                                                     const int* __restrict__ tcall, int j) {
+    const int2 e = map[blockIdx.x];
+    const Member& m = mem[e.x];
+    const float2* cur = (j & 1) ? m.alt : m.pos;
+    float2* nxt = (j & 1) ? m.pos : m.alt;
+    edges_body<K, 2>(cur, nxt, m.es, 0, nullptr, m.b, m.g, m.a, batch_set(tcall, m, j) ^ 1, nullptr, nullptr,
+                     nullptr, e.y);
+}
+
+void launch_b_edges(int k, const Member* mem, const int2* map, int blocks, const int* tcall, int j,
+                    hipStream_t s) {
+    if (blocks <= 0) return;
+    const dim3 grid(blocks), block(kThreads);
+    switch (k) {
+        case 1: hipLaunchKernelGGL(kb_edges<1>, grid, block, 0, s, mem, map, tcall, j); break;
+        case 2: hipLaunchKernelGGL(kb_edges<2>, grid, block, 0, s, mem, map, tcall, j); break;
+        default: hipLaunchKernelGGL(kb_edges<3>, grid, block, 0, s, mem, map, tcall, j); break;
     }
 }
 

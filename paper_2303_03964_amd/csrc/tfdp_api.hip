@@ -7,16 +7,34 @@
 #include <string>
 #include <vector>
 
-#include "tfdp.h"
-#include "tfdp_internal.h"
+#include "tfdp_handle.h"
 
 using namespace tfdp;
 
-namespace {
+namespace tfdp {
 
+namespace {
 thread_local std::string g_msg;
+}
 
 void set_msg(const std::string& s) { g_msg = s; }
+const char* last_msg() { return g_msg.c_str(); }
+
+tfdp_status check_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return TFDP_OK;
+    set_msg(std::string(what) + ": " + hipGetErrorString(e));
+    return TFDP_ERR_HIP;
+}
+
+void enqueue_twiddles(tfdp_layout* h, hipStream_t s) {
+    if (!h->tw_pending) return;
+    for (int k = 1; k <= h->k_ws; ++k) launch_twiddles(h->lay.tw[k], make_geom(h->p.n_int, k).L, s);
+    h->tw_pending = false;
+}
+
+}  // namespace tfdp
+
+namespace {
 
 enum Phase {
     PH_BOX = 0,
@@ -35,48 +53,8 @@ enum Phase {
 const char* kPhaseNames[PH_COUNT] = {"box",     "bin_count", "bin_scan", "bin_scatter",   "spread",
                                      "rowfft",  "colconv",   "rowifft",  "gather_update", "brute"};
 
-int k_workspace(const tfdp_params* p) { return (p->k_mode == 1 || p->k_mode == 2) ? p->k_mode : 3; }
 
-Geom make_geom(int n_int, int k) {
-    Geom g;
-    g.k = k;
-    g.m = n_int * k;
-    int L = 64, logL = 6;
-    while (L < 2 * g.m) {
-        L <<= 1;
-        ++logL;
-    }
-    g.L = L;
-    g.logL = logL;
-    g.H = L / 2 + 1;
-    g.cw = L >= 512 ? 1 : 512 / L;  // transforms per FFT task
-    return g;
-}
 
-// Bump allocator over the caller's workspace (base == nullptr: size only).
-struct Carve {
-    char* base;
-    size_t off;
-    template <class T>
-    T* take(size_t count) {
-        off = (off + 255) & ~(size_t)255;
-        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-        off += count * sizeof(T);
-        return p;
-    }
-};
-
-struct Layout {
-    Bufs b;         // tw filled per k
-    float2* pos_alt;
-    float2* tw[4];  // per k
-    int nslices;
-    int* slice_rp;      // [nslices][n + 1] (nslices > 1)
-    int* slice_col;     // [nnz] packed entries: column | (row index in its wave group) << 26
-    float2* fpart;      // [n] attraction sums of the earlier slices (nslices > 1)
-    int2* sched;        // [4 * edge_blocks_bound] schedules of all slices
-    EdgeSlice slice[kMaxSlices];
-};
 
 // Column-slice width of the edge pass: kSliceNodesDefault, or the value of
 // the environment variable TFDP_EDGE_SLICE_NODES (>= 1024) read at each call.
@@ -91,7 +69,10 @@ long long slice_nodes() {
     return kSliceNodesDefault;
 }
 
-Layout carve(void* base, int n, long long nnz, const tfdp_params* p, size_t* bytes) {
+// Workspace layout. The arrays that do not depend on the grid (state,
+// positions, edge-pass entries and schedules) come first, so that a new
+// N_int or k range (tfdp_layout_set_params) re-lays only the tail.
+Layout carve(void* base, int n, long long nnz, const tfdp_params* p, long long sn, size_t* bytes) {
     Layout l;
     std::memset(&l, 0, sizeof(l));
     Carve c{static_cast<char*>(base), 0};
@@ -104,6 +85,13 @@ Layout carve(void* base, int n, long long nnz, const tfdp_params* p, size_t* byt
     l.b.st = c.take<DevState>(1);
     l.pos_alt = c.take<float2>((size_t)n);
     l.b.spos = c.take<float2>((size_t)n);
+    l.nslices = edge_slices(n, sn);
+    l.slice_col = c.take<int>((size_t)nnz);
+    if (l.nslices > 1) {
+        l.slice_rp = c.take<int>((size_t)l.nslices * ((size_t)n + 1));
+        l.fpart = c.take<float2>((size_t)n);
+    }
+    l.sched = c.take<int2>((size_t)4 * edge_blocks_bound(n, nnz, sn));
     l.b.blkcnt = c.take<int>((size_t)p->n_int * l.b.nblk);
     l.b.bucket_cnt = c.take<int>((size_t)p->n_int);
     l.b.bucket_start = c.take<int>((size_t)p->n_int + 1);
@@ -114,14 +102,6 @@ Layout carve(void* base, int n, long long nnz, const tfdp_params* p, size_t* byt
     l.b.kcol = c.take<float2>((size_t)gw.H * gw.L);
     l.b.pcol = c.take<float2>((size_t)3 * gw.H * gw.m);
     l.b.pot = c.take<float4>((size_t)gw.m * gw.m);
-    const long long sn = slice_nodes();
-    l.nslices = edge_slices(n, sn);
-    l.slice_col = c.take<int>((size_t)nnz);
-    if (l.nslices > 1) {
-        l.slice_rp = c.take<int>((size_t)l.nslices * ((size_t)n + 1));
-        l.fpart = c.take<float2>((size_t)n);
-    }
-    l.sched = c.take<int2>((size_t)4 * edge_blocks_bound(n, nnz, sn));
     for (int k = 1; k <= kw; ++k) l.tw[k] = c.take<float2>((size_t)make_geom(p->n_int, k).L);
     *bytes = (c.off + 255) & ~(size_t)255;
     return l;
@@ -168,50 +148,6 @@ std::vector<int2> build_edge_schedule(const std::vector<int>& rp, int n, std::ve
     return out;
 }
 
-tfdp_status check_hip(hipError_t e, const char* what) {
-    if (e == hipSuccess) return TFDP_OK;
-    set_msg(std::string(what) + ": " + hipGetErrorString(e));
-    return TFDP_ERR_HIP;
-}
-
-}  // namespace
-
-struct tfdp_layout {
-    int n;
-    int64_t nnz;
-    const int* row_ptr;
-    const int* col_idx;
-    float* pos;
-    void* ws;
-    size_t ws_bytes;
-    tfdp_params p;
-    int k_ws;
-    int t;
-    Layout lay;
-    // captured iteration pairs: [k][parity of t at the start][orientation]
-    bool graphs;
-    hipGraphExec_t gexec[4][2][2];
-    // profiling
-    bool prof;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used;
-    std::vector<int> ev_phase;  // phase of each recorded pair
-    hipStream_t ev_stream;
-};
-
-namespace {
-
-ModelArgs model_args(const tfdp_layout* h) {
-    ModelArgs a;
-    a.alpha = h->p.alpha;
-    a.beta = h->p.beta;
-    a.gamma = h->p.gamma;
-    a.rep_weight = h->p.rep_weight;
-    a.t0 = h->p.t0 > 0.f ? h->p.t0 : std::fmax(1.0f, (float)(std::sqrt((double)h->n) / 10.0));
-    a.total_iters = h->p.total_iters;
-    return a;
-}
-
 // Event bracket around the launches of one phase when profiling.
 struct PhaseTimer {
     tfdp_layout* h;
@@ -240,11 +176,6 @@ struct PhaseTimer {
     }
 };
 
-Bufs bufs_for(const tfdp_layout* h, int k) {
-    Bufs b = h->lay.b;
-    b.tw = h->lay.tw[k];
-    return b;
-}
 
 // One evaluation of the interpolated repulsion up to the grid potentials;
 // the box comes from extremes slot set `set`, set ^ 1 is reset for the
@@ -388,19 +319,12 @@ hipGraphExec_t pair_graph(tfdp_layout* h, int k, int parity, int orient, const M
     return ex;
 }
 
-int k_at(const tfdp_params& p, int t) {
-    if (p.k_mode >= 0) return p.k_mode;
-    const int T = p.total_iters;
-    if (t < (9 * T) / 10) return 1;
-    if (t < (19 * T) / 20) return 2;
-    return 3;
-}
 
 }  // namespace
 
 extern "C" {
 
-const char* tfdp_last_error(void) { return g_msg.c_str(); }
+const char* tfdp_last_error(void) { return last_msg(); }
 
 void tfdp_params_default(tfdp_params* p) {
     if (!p) return;
@@ -469,7 +393,7 @@ tfdp_status tfdp_params_validate(const tfdp_params* p, int32_t n, int64_t nnz) {
 size_t tfdp_workspace_size(int32_t n, int64_t nnz, const tfdp_params* p) {
     if (tfdp_params_validate(p, n, nnz) != TFDP_OK) return 0;
     size_t bytes = 0;
-    carve(nullptr, n, nnz, p, &bytes);
+    carve(nullptr, n, nnz, p, slice_nodes(), &bytes);
     return bytes;
 }
 
@@ -489,7 +413,8 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
         return TFDP_ERR_INVALID_ARG;
     }
     size_t need = 0;
-    carve(nullptr, n, nnz, p, &need);
+    const long long sn = slice_nodes();
+    carve(nullptr, n, nnz, p, sn, &need);
     if (!d_ws || ws_bytes < need) {
         set_msg("workspace too small: need " + std::to_string(need) + " bytes");
         return TFDP_ERR_WORKSPACE;
@@ -519,7 +444,8 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
     h->ev_used = 0;
     h->ev_stream = nullptr;
     size_t bytes = 0;
-    h->lay = carve(d_ws, n, nnz, p, &bytes);
+    h->slice_nodes = sn;
+    h->lay = carve(d_ws, n, nnz, p, sn, &bytes);
 
     DevState* dst = h->lay.b.st;
     static const bool attrs = (init_kernel_attributes(), true);
@@ -527,7 +453,8 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
     st = check_hip(hipMemsetAsync(dst, 0, sizeof(DevState), stream), "hipMemsetAsync");
     if (st == TFDP_OK) {
         if (nnz > 0 || n > 0) launch_csr_check(d_row_ptr, d_col_idx, n, nnz, dst, stream);
-        for (int k = 1; k <= h->k_ws; ++k) launch_twiddles(h->lay.tw[k], make_geom(p->n_int, k).L, stream);
+        h->tw_pending = true;
+        enqueue_twiddles(h, stream);
         st = check_hip(hipGetLastError(), "kernel launch");
     }
     DevState hs;
@@ -557,6 +484,7 @@ tfdp_status tfdp_layout_step(tfdp_layout* h, int32_t iters, hipStream_t s) {
     const ModelArgs a = model_args(h);
     float2* cur = reinterpret_cast<float2*>(h->pos);
     float2* alt = h->lay.pos_alt;
+    enqueue_twiddles(h, s);
     enqueue_box(h, cur, h->t & 1, s);
     const bool use_graphs = h->graphs && !h->prof;
     for (int it = 0; it < iters;) {
@@ -606,6 +534,7 @@ tfdp_status tfdp_layout_forces(tfdp_layout* h, const float* d_pos_in, int32_t k,
     }
     set_msg("");
     const ModelArgs a = model_args(h);
+    enqueue_twiddles(h, s);
     const float2* pos = reinterpret_cast<const float2*>(d_pos_in);
     float2* fr = reinterpret_cast<float2*>(d_f_rep);
     float2* fa = reinterpret_cast<float2*>(d_f_att);
@@ -631,15 +560,21 @@ tfdp_status tfdp_layout_set_params(tfdp_layout* h, const tfdp_params* p) {
     }
     tfdp_status st = tfdp_params_validate(p, h->n, h->nnz);
     if (st != TFDP_OK) return st;
-    if (p->n_int != h->p.n_int) {
-        set_msg("n_int cannot change on an existing handle");
-        return TFDP_ERR_UNSUPPORTED;
-    }
-    if (k_workspace(p) > h->k_ws) {
-        set_msg("k_mode needs a larger workspace than the handle has");
-        return TFDP_ERR_WORKSPACE;
+    if (p->n_int != h->p.n_int || k_workspace(p) != h->k_ws) {
+        // new grid: re-lay the grid arrays inside the same workspace
+        size_t need = 0;
+        Layout nl = carve(h->ws, h->n, h->nnz, p, h->slice_nodes, &need);
+        if (need > h->ws_bytes) {
+            set_msg("workspace too small for this n_int / k_mode: need " + std::to_string(need) + " bytes");
+            return TFDP_ERR_WORKSPACE;
+        }
+        for (int s = 0; s < kMaxSlices; ++s) nl.slice[s] = h->lay.slice[s];
+        h->lay = nl;
+        h->k_ws = k_workspace(p);
+        h->tw_pending = true;
     }
     h->p = *p;
+    h->version += 1;
     drop_graphs(h);
     return TFDP_OK;
 }

@@ -1,0 +1,125 @@
+// Host-side definitions shared by the translation units of the C ABI: the
+// layout handle, its workspace views and small helpers. Not part of the
+// public ABI (see include/tfdp.h).
+#pragma once
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "tfdp.h"
+#include "tfdp_internal.h"
+
+namespace tfdp {
+
+// Thread-local text returned by tfdp_last_error().
+void set_msg(const std::string& s);
+const char* last_msg();
+// TFDP_OK, or TFDP_ERR_HIP with the HIP error text as the message.
+tfdp_status check_hip(hipError_t e, const char* what);
+
+inline int k_workspace(const tfdp_params* p) { return (p->k_mode == 1 || p->k_mode == 2) ? p->k_mode : 3; }
+
+inline Geom make_geom(int n_int, int k) {
+    Geom g;
+    g.k = k;
+    g.m = n_int * k;
+    int L = 64, logL = 6;
+    while (L < 2 * g.m) {
+        L <<= 1;
+        ++logL;
+    }
+    g.L = L;
+    g.logL = logL;
+    g.H = L / 2 + 1;
+    g.cw = L >= 512 ? 1 : 512 / L;  // transforms per FFT task
+    return g;
+}
+
+// Bump allocator over the caller's workspace (base == nullptr: size only).
+struct Carve {
+    char* base;
+    size_t off;
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct Layout {
+    Bufs b;         // tw filled per k
+    float2* pos_alt;
+    float2* tw[4];  // per k
+    int nslices;
+    int* slice_rp;      // [nslices][n + 1] (nslices > 1)
+    int* slice_col;     // [nnz] packed entries: column | (row index in its wave group) << 26
+    float2* fpart;      // [n] attraction sums of the earlier slices (nslices > 1)
+    int2* sched;        // [4 * edge_blocks_bound] schedules of all slices
+    EdgeSlice slice[kMaxSlices];
+};
+
+}  // namespace tfdp
+
+struct tfdp_layout {
+    int n;
+    int64_t nnz;
+    const int* row_ptr;
+    const int* col_idx;
+    float* pos;
+    void* ws;
+    size_t ws_bytes;
+    tfdp_params p;
+    int k_ws;
+    int t;
+    tfdp::Layout lay;
+    // captured iteration pairs: [k][parity of t at the start][orientation]
+    bool graphs;
+    hipGraphExec_t gexec[4][2][2];
+    // profiling
+    bool prof;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used;
+    std::vector<int> ev_phase;  // phase of each recorded pair
+    hipStream_t ev_stream;
+    // bumped by every change a batch that holds the handle must pick up
+    unsigned int version;
+    long long slice_nodes;  // column-slice width fixed at init
+    bool tw_pending;        // twiddle tables to (re)compute before the next launch
+};
+
+namespace tfdp {
+
+// Twiddle tables of every k of the workspace, on stream s, if the grid
+// changed since they were last computed.
+void enqueue_twiddles(tfdp_layout* h, hipStream_t s);
+
+inline ModelArgs model_args(const tfdp_layout* h) {
+    ModelArgs a;
+    a.alpha = h->p.alpha;
+    a.beta = h->p.beta;
+    a.gamma = h->p.gamma;
+    a.rep_weight = h->p.rep_weight;
+    a.t0 = h->p.t0 > 0.f ? h->p.t0 : std::fmax(1.0f, (float)(std::sqrt((double)h->n) / 10.0));
+    a.total_iters = h->p.total_iters;
+    return a;
+}
+
+inline Bufs bufs_for(const tfdp_layout* h, int k) {
+    Bufs b = h->lay.b;
+    b.tw = h->lay.tw[k];
+    return b;
+}
+
+// k of iteration t: k_mode, or the schedule of Sec. 3.4 ("Choices of k").
+inline int k_at(const tfdp_params& p, int t) {
+    if (p.k_mode >= 0) return p.k_mode;
+    const int T = p.total_iters;
+    if (t < (9 * T) / 10) return 1;
+    if (t < (19 * T) / 20) return 2;
+    return 3;
+}
+
+}  // namespace tfdp

@@ -83,6 +83,29 @@ struct ModelArgs {
     int total_iters;
 };
 
+// One graph of a batched launch: the arguments of its plain launches for one
+// k. Batched kernels read it through a block map entry {member, block} and
+// run the plain kernel's body for that block, so every graph gets exactly
+// the arithmetic of its plain launch.
+struct Member {
+    Bufs b;             // views for this entry's k
+    Geom g;
+    ModelArgs a;
+    EdgeSlice es;       // the single column slice of the edge pass
+    float2* pos;        // caller's positions (current at even iterations of a call)
+    float2* alt;        // second buffer (current at odd iterations)
+    int slot;           // index of the graph's iteration counter at the start of the call
+    int nw;             // waves per block of the spreading pass
+    int nkb, nqb, nrb;  // logical blocks of the kernel-row, row-FFT and inverse-row passes
+    int box_blocks;     // blocks of the box reduction
+};
+
+// Slot-set parity and position buffers of iteration j of a batched call for
+// a graph whose counter was t0 at the start of the call.
+__device__ __forceinline__ int batch_set(const int* tcall, const Member& m, int j) {
+    return (tcall[m.slot] + j) & 1;
+}
+
 // ---- launchers (each defined next to its kernels) ----
 void launch_box_begin(DevState* st, int t, hipStream_t s);
 void launch_box_reduce(const float2* pos, int n, DevState* st, int set, hipStream_t s);
@@ -129,6 +152,42 @@ void launch_brute(const float2* pos, float2* pos_out, const int* row_ptr, const 
                   float2* f_rep, float2* f_att, float2* f_tot, hipStream_t s);
 void launch_csr_check(const int* row_ptr, const int* col_idx, int n, long long nnz,
                       DevState* st, hipStream_t s);
+
+// ---- launch geometry shared by the plain and the batched launchers ----
+struct Dims {
+    int grid;     // blocks of the plain launch (logical blocks for the batched map)
+    int block;    // threads per block
+    size_t lds;   // dynamic LDS bytes
+};
+Dims box_reduce_dims(int n);
+Dims bin_count_dims(const Bufs& b);
+Dims bin_scan_dims(const Bufs& b);
+Dims bin_scatter_dims(const Bufs& b);
+// spreading: grid = chunk blocks + logical kernel-row blocks (nkb); nw waves
+Dims spread_dims(const Bufs& b, const Geom& g, int* nw, int* nkb);
+Dims rowfft_dims(const Geom& g, int* nqb);
+Dims colconv_dims(const Geom& g);
+Dims rowifft_dims(const Geom& g, int* nrb);
+
+// ---- batched launchers: one launch for every map entry {member, block} ----
+// tcall: per-slot iteration counters at the start of the call; j: iteration
+// index inside the call. Members of one launch share k, L and the spreading
+// block size (the launch's template and block shape).
+void launch_b_box(const Member* mem, const int2* map_begin, int n_begin, const int2* map_red, int n_red,
+                  const int* tcall, hipStream_t s);
+void launch_b_bin_count(const Member* mem, const int2* map, int blocks, size_t lds, const int* tcall, int j,
+                        hipStream_t s);
+void launch_b_bin_scan(const Member* mem, const int2* map, int blocks, const int* tcall, int j, hipStream_t s);
+void launch_b_bin_scatter(const Member* mem, const int2* map, int blocks, size_t lds, int j, hipStream_t s);
+void launch_b_spread(int k, int logL, int nw, const Member* mem, const int2* map, int blocks, size_t lds,
+                     hipStream_t s);
+void launch_b_rowfft(int logL, const Member* mem, const int2* map, int blocks, hipStream_t s);
+void launch_b_colconv(int logL, const Member* mem, const int2* map, int blocks, hipStream_t s);
+void launch_b_rowifft(int logL, const Member* mem, const int2* map, int blocks, hipStream_t s);
+void launch_b_edges(int k, const Member* mem, const int2* map, int blocks, const int* tcall, int j,
+                    hipStream_t s);
+void launch_b_copy(const Member* mem, const int2* map, int blocks, hipStream_t s);
+void launch_b_advance(int* tcall, int slots, int iters, hipStream_t s);
 
 // ---- device helpers used by several translation units ----
 
@@ -214,10 +273,11 @@ __device__ __forceinline__ void node_deltas(double t, double h, double* d) {
     }
 }
 
-// Block-wide min/max of the given extremes, committed to st->mm with one
-// set of integer atomics per block (blockDim.x a multiple of 64, <= kThreads).
+// Block-wide min/max of the given extremes, committed to st->mm[set][slot]
+// with one set of integer atomics per block (blockDim.x a multiple of 64,
+// <= kThreads).
 __device__ __forceinline__ void block_minmax_commit(float xmin, float ymin, float xmax, float ymax,
-                                                    DevState* st, int set) {
+                                                    DevState* st, int set, int slot) {
     // wave reduction, then one lane per wave commits with atomics
     for (int off = 32; off > 0; off >>= 1) {
         xmin = fminf(xmin, __shfl_xor(xmin, off));
@@ -243,11 +303,11 @@ __device__ __forceinline__ void block_minmax_commit(float xmin, float ymin, floa
             ymax = fmaxf(ymax, red[3][i]);
         }
         if (xmin <= xmax) {  // at least one finite position in the block
-            unsigned int* slot = st->mm[set][blockIdx.x % kBoxSlots];
-            atomicMin(slot + 0, enc_ord(xmin));
-            atomicMin(slot + 1, enc_ord(ymin));
-            atomicMax(slot + 2, enc_ord(xmax));
-            atomicMax(slot + 3, enc_ord(ymax));
+            unsigned int* mm = st->mm[set][slot % kBoxSlots];
+            atomicMin(mm + 0, enc_ord(xmin));
+            atomicMin(mm + 1, enc_ord(ymin));
+            atomicMax(mm + 2, enc_ord(xmax));
+            atomicMax(mm + 3, enc_ord(ymax));
         }
     }
 }

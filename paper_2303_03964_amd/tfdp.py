@@ -71,6 +71,13 @@ _SIGS = {
     "tfdp_phase_count": (c_int32, []),
     "tfdp_phase_name": (c_char_p, [c_int32]),
     "tfdp_layout_phase_times": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64), c_int32]),
+    "tfdp_batch_create": (c_int32, [POINTER(c_void_p), c_int32]),
+    "tfdp_batch_add": (c_int32, [c_void_p, c_void_p]),
+    "tfdp_batch_remove": (c_int32, [c_void_p, c_void_p]),
+    "tfdp_batch_count": (c_int32, [c_void_p]),
+    "tfdp_batch_step": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "tfdp_batch_set_graphs": (c_int32, [c_void_p, c_int32]),
+    "tfdp_batch_destroy": (None, [c_void_p]),
 }
 
 _lib = None
@@ -204,7 +211,37 @@ def tfdp_layout_phase_times(h):
     return {tfdp_phase_name(i): (ms[i], cnt[i]) for i in range(n)}
 
 
-# ------------------------------------------------------------------ convenience owner of the buffers
+def tfdp_batch_create(capacity):
+    b = c_void_p()
+    _check(load_library().tfdp_batch_create(ctypes.byref(b), capacity))
+    return b
+
+
+def tfdp_batch_add(b, h):
+    return _check(load_library().tfdp_batch_add(b, h))
+
+
+def tfdp_batch_remove(b, h):
+    return _check(load_library().tfdp_batch_remove(b, h))
+
+
+def tfdp_batch_count(b) -> int:
+    return load_library().tfdp_batch_count(b)
+
+
+def tfdp_batch_step(b, iters, stream=None):
+    return _check(load_library().tfdp_batch_step(b, iters, _stream(stream)))
+
+
+def tfdp_batch_set_graphs(b, enable):
+    return _check(load_library().tfdp_batch_set_graphs(b, int(bool(enable))))
+
+
+def tfdp_batch_destroy(b):
+    load_library().tfdp_batch_destroy(b)
+
+
+# ------------------------------------------------------------------ convenience owners of the buffers
 
 class Layout:
     """Owns the device CSR, positions and workspace of one layout handle.
@@ -214,7 +251,8 @@ class Layout:
     used in place.
     """
 
-    def __init__(self, row_ptr, col_idx, pos, params: TfdpParams | None = None, device="cuda", stream=None):
+    def __init__(self, row_ptr, col_idx, pos, params: TfdpParams | None = None, device="cuda", stream=None,
+                 workspace_params: TfdpParams | None = None):
         dev = torch.device(device)
         self.row_ptr = torch.as_tensor(row_ptr, dtype=torch.int32).to(dev).contiguous()
         self.col_idx = torch.as_tensor(col_idx, dtype=torch.int32).to(dev).contiguous()
@@ -230,9 +268,14 @@ class Layout:
         if self.row_ptr.numel() != self.n + 1:
             raise ValueError("row_ptr must have n + 1 entries")
         self.params = params if params is not None else tfdp_params_default()
-        size = tfdp_workspace_size(self.n, self.nnz, self.params)
-        if size == 0:
-            raise TfdpError(tfdp_params_validate(self.params, self.n, self.nnz), tfdp_last_error())
+        # the workspace may be sized for a larger grid than the first one
+        # (tfdp_layout_set_params can then move to it)
+        sizing = [self.params] + ([workspace_params] if workspace_params is not None else [])
+        sizes = [tfdp_workspace_size(self.n, self.nnz, q) for q in sizing]
+        if min(sizes) == 0:
+            bad = sizing[sizes.index(0)]
+            raise TfdpError(tfdp_params_validate(bad, self.n, self.nnz), tfdp_last_error())
+        size = max(sizes)
         self.workspace = torch.empty(size + 256, dtype=torch.uint8, device=dev)
         off = (-self.workspace.data_ptr()) % 256
         self.workspace = self.workspace[off:off + size]
@@ -268,6 +311,43 @@ class Layout:
         if getattr(self, "handle", None) is not None:
             tfdp_layout_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A tfdp_batch over Layout objects (kept alive while they are members)."""
+
+    def __init__(self, capacity):
+        self.handle = tfdp_batch_create(capacity)
+        self.members = []
+
+    def add(self, lay: Layout):
+        tfdp_batch_add(self.handle, lay.handle)
+        self.members.append(lay)
+
+    def remove(self, lay: Layout):
+        tfdp_batch_remove(self.handle, lay.handle)
+        self.members.remove(lay)
+
+    def __len__(self):
+        return tfdp_batch_count(self.handle)
+
+    def step(self, iters, stream=None):
+        tfdp_batch_step(self.handle, iters, stream)
+
+    def set_graphs(self, enable):
+        tfdp_batch_set_graphs(self.handle, enable)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            tfdp_batch_destroy(self.handle)
+            self.handle = None
+            self.members = []
 
     def __del__(self):
         try:

@@ -114,3 +114,25 @@ def test_phase_names():
 
 def test_params_struct_layout():
     assert ctypes.sizeof(TfdpParams) == 32
+
+
+def test_batch_host_bookkeeping():
+    lib = T.load_library()
+    out = ctypes.c_void_p()
+    assert lib.tfdp_batch_create(None, 4) == INVALID
+    assert lib.tfdp_batch_create(ctypes.byref(out), 0) == INVALID
+    assert lib.tfdp_batch_create(ctypes.byref(out), 4) == OK and out.value
+    b = out
+    assert lib.tfdp_batch_count(b) == 0 and lib.tfdp_batch_count(None) == 0
+    # NULL members and removal of a non-member are rejected without device work
+    assert lib.tfdp_batch_add(b, None) == INVALID
+    assert lib.tfdp_batch_add(None, ctypes.c_void_p(8)) == INVALID
+    assert lib.tfdp_batch_remove(b, ctypes.c_void_p(8)) == INVALID
+    assert "not a member" in T.tfdp_last_error()
+    # an empty batch steps without touching a device; negative counts fail
+    assert lib.tfdp_batch_step(b, 5, None) == OK
+    assert lib.tfdp_batch_step(b, -1, None) == INVALID
+    assert lib.tfdp_batch_step(None, 1, None) == INVALID
+    assert lib.tfdp_batch_set_graphs(b, 0) == OK and lib.tfdp_batch_set_graphs(None, 1) == INVALID
+    lib.tfdp_batch_destroy(b)
+    lib.tfdp_batch_destroy(None)

@@ -410,3 +410,34 @@ def test_graph_replays_match_direct_launches(T):
     assert a.sync_status() == 0 and b.sync_status() == 0
     a.close()
     b.close()
+
+
+def test_grid_change_keeps_state(T):
+    """tfdp_layout_set_params with a new N_int / k range inside a workspace
+    sized for the larger grid: stepping on is bit-identical to a fresh handle
+    created with the new grid at the same positions and counter."""
+    import torch
+    w = sg.sbm_1k()
+    g = w.graph
+    big = T.tfdp_params_default(n_int=96, total_iters=60)
+    a = T.Layout(g.row_ptr, g.col_idx, w.pos0, T.tfdp_params_default(n_int=32, total_iters=60, k_mode=1),
+                 workspace_params=big)
+    a.step(11)
+    a.set_params(big)
+    b = T.Layout(g.row_ptr, g.col_idx, a.pos.clone(), big)
+    b.iteration = a.iteration
+    a.step(40)
+    b.step(40)
+    torch.cuda.synchronize()
+    assert a.iteration == b.iteration == 51
+    assert torch.equal(a.pos, b.pos)
+    # a grid that does not fit the workspace is refused and changes nothing
+    with pytest.raises(T.TfdpError):
+        a.set_params(T.tfdp_params_default(n_int=200, total_iters=60))
+    assert a.params.n_int == 96
+    fr, fa, ft = a.forces(k=3)
+    torch.cuda.synchronize()
+    x = a.pos.cpu().numpy().astype(np.float64)
+    assert rel_l2(fr.cpu().numpy(), ot.repulsion_ibfft_stable(x, 2.0, 96, 3)) <= TOL
+    a.close()
+    b.close()
