@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload section")
     ap.add_argument("--batch-graphs", type=int, default=512)
     ap.add_argument("--batch-iters", type=int, default=300)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="copy this many MiB device-to-device once before the run (a plain copy kernel "
                          "of known size for scaling hardware byte counters)")
@@ -191,6 +193,67 @@ def batched_section(T, torch, stream, graphs, iters):
     }
 
 
+def serving_section(T, torch, stream, requests):
+    """Serving workload: Poisson arrivals of layout requests (Chung-Lu, n
+    log-uniform in [1000, 200000], exponent in [2, 3], 200 iterations) and
+    re-tune requests (30%: new alpha, beta, gamma, repulsion weight on a
+    resident graph, 50 iterations). The sequential capacity is measured
+    first (every request arriving at once, served one by one with
+    tfdp_layout_step); the continuous-batching server then runs at offered
+    loads of 0.5, 0.8 and 1.2 times that capacity."""
+    import synthgraphs as sg
+    from paper_2303_03964_amd import serve
+    pool_n = 48
+    t_gen = time.perf_counter()
+    pool = [sg.serving_graph(i) for i in range(pool_n)]
+    gen_s = time.perf_counter() - t_gen
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.5 * free)
+    out = {"workload": "serving: Chung-Lu n log-uniform [1e3, 2e5], exponent [2, 3], mean degree 10; "
+                       "30% re-tunes (alpha, beta, gamma, w_r) of resident graphs",
+           "pool_graphs": pool_n, "requests": requests, "layout_iters": 200, "retune_iters": 50,
+           "hbm_budget_bytes": budget, "chunk": 10, "generation_s": gen_s}
+    # warm-up: kernels, allocator
+    warm = sg.serving_trace(6, 1e6, pool_n, seed=1)
+    for plain in (True, False):
+        srv = serve.Server(pool, budget, stream=stream, plain=plain)
+        srv.run(warm)
+        srv.close()
+    burst = sg.serving_trace(requests, 1e9, pool_n, seed=sg.SEED_BASE + 7)
+    srv = serve.Server(pool, budget, stream=stream, plain=True)
+    t0 = time.perf_counter()
+    recs = srv.run(burst)
+    seq_s = time.perf_counter() - t0
+    srv.close()
+    cap = requests / seq_s
+    seq = serve.summarize(recs, seq_s)
+    out["sequential"] = {"capacity_req_per_s": cap, **seq}
+    srv = serve.Server(pool, budget, stream=stream)
+    t0 = time.perf_counter()
+    recs = srv.run(burst)
+    bat_s = time.perf_counter() - t0
+    srv.close()
+    out["batched_burst"] = {"req_per_s": requests / bat_s, **serve.summarize(recs, bat_s)}
+    loads = {}
+    for f in (0.5, 0.8, 1.2):
+        trace = sg.serving_trace(requests, f * cap, pool_n, seed=sg.SEED_BASE + 7)
+        srv = serve.Server(pool, budget, stream=stream)
+        t0 = time.perf_counter()
+        recs = srv.run(trace)
+        wall = time.perf_counter() - t0
+        srv.close()
+        seq_trace = serve.Server(pool, budget, stream=stream, plain=True)
+        t1 = time.perf_counter()
+        recs_seq = seq_trace.run(trace)
+        wall_seq = time.perf_counter() - t1
+        seq_trace.close()
+        loads[f"{f}x"] = {"offered_req_per_s": f * cap, "batched": serve.summarize(recs, wall),
+                          "sequential": serve.summarize(recs_seq, wall_seq)}
+        print(f"# serving load {f}x: {json.dumps(loads[f'{f}x'])}", file=sys.stderr, flush=True)
+    out["loads"] = loads
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -318,6 +381,8 @@ def main():
     if not args.no_batch:
         rec["batched"] = batched_section(T, torch, stream, args.batch_graphs, args.batch_iters)
         print(f"# batched: {json.dumps(rec['batched'])}", file=sys.stderr, flush=True)
+    if not args.no_serve:
+        rec["serving"] = serving_section(T, torch, stream, args.serve_requests)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
     print(json.dumps(rec), flush=True)

@@ -1,19 +1,119 @@
 """Grid choice for the interpolated repulsion (Sec. 3.4).
 
-The cost of one iteration is a per-node part (spreading, gather, edges) and
+The cost of one iteration has a per-node part (spreading, gather, edges) and
 a grid part that grows like (N_int k)^2 log(N_int k); the accuracy of the
 interpolation is set by the interval width h = W / N_int (W = side of the
-layout box) and by k.
+layout box) and by k: the relative L2 error of the repulsion behaves like
+C_k h^k (k-point Lagrange interpolation per interval).
 
-``n_int_for_size`` is the starting grid of a graph of n nodes: it follows
-the grids used for 10^3 (64), 10^5 (128) and 10^6 (256) nodes, i.e.
-N_int = 64 (n / 1000)^(1/5), rounded up to a multiple of 8.
+The tuner works in two stages, matching the k schedule of Sec. 3.4:
+
+* start (k = 1, the first 90% of the iterations): N_int from the graph size,
+  ``n_int_for_size``, which follows the grids used for 10^3 (64), 10^5 (128)
+  and 10^6 (256) nodes: N_int = 64 (n / 1000)^(1/5), a multiple of 8;
+* final (k = 2, 3): at the switch, the box side W of the current layout
+  fixes N_int = ceil(margin W / h_k(tol)) with h_k(tol) = (tol / C_k)^(1/k),
+  so that the repulsion of the last iterations is within ``tol`` of the
+  exact sums. ``retune`` applies it with tfdp_layout_set_params (the
+  workspace is sized for the cap at creation, ``workspace_grid``).
+
+C_k comes from ``calibrate``: exact (k = 0) against interpolated forces of
+the library on laid-out graphs at several N_int, fitted in log space.
+``DEFAULT_C`` holds the values measured that way for gamma = 2.
 """
 from __future__ import annotations
 
 import math
 
+import numpy as np
+
+# C_k of err ~ C_k h^k for gamma = 2 (relative L2 of the repulsion): fits to
+# the errors of the interpolated against the exact sums on four SBM layouts
+# of 357..2047 nodes after 300 iterations, N_int 8..128 (calibrate() measures
+# the same on the device)
+DEFAULT_C = {1: 2.0, 2: 0.095, 3: 0.022}
+MAX_N_INT_K3 = 341  # N_int * 3 * 2 <= 2048 (largest FFT length)
+
 
 def n_int_for_size(n: int) -> int:
     v = 64.0 * (max(n, 1) / 1000.0) ** 0.2
     return int(min(1024, max(8, 8 * math.ceil(v / 8.0))))
+
+
+def interval_width(tol: float, k: int, consts=None) -> float:
+    c = (consts or DEFAULT_C)[k]
+    return (tol / c) ** (1.0 / k)
+
+
+def final_n_int(width: float, tol: float = 1e-3, k: int = 3, consts=None, margin: float = 1.1,
+                lo: int = 8, hi: int = MAX_N_INT_K3) -> int:
+    """Intervals per side for a box of side `width` so that k-point
+    interpolation stays within `tol` (relative L2 of the repulsion)."""
+    v = math.ceil(margin * width / interval_width(tol, k, consts))
+    return int(min(hi, max(lo, v)))
+
+
+def workspace_grid(n: int, cap: int = MAX_N_INT_K3) -> int:
+    """Largest N_int a graph's workspace is sized for: the final grid of a
+    box whose side is 3 sqrt(n) (final boxes of SBM layouts with the default
+    parameters measured 0.8..1.6 sqrt(n)), capped."""
+    return final_n_int(3.0 * math.sqrt(max(n, 1)), hi=cap, lo=n_int_for_size(n))
+
+
+def box_side(pos) -> float:
+    """Side of the square layout box (max of the x and y ranges) from the
+    positions (torch tensor or array, [n, 2])."""
+    p = pos.detach().float().cpu().numpy() if hasattr(pos, "detach") else np.asarray(pos, dtype=np.float32)
+    p = p[np.all(np.isfinite(p), axis=1)]
+    if p.size == 0:
+        return 1.0
+    ext = p.max(axis=0) - p.min(axis=0)
+    return float(max(ext.max(), 1e-6))
+
+
+def retune(lay, tol: float = 1e-3, consts=None, k: int = 3, cap: int | None = None) -> int:
+    """Set the final-stage grid of a Layout from its current box; returns
+    the new N_int (never below the current one)."""
+    from . import tfdp as T
+    cur = lay.params.n_int
+    hi = cap if cap is not None else MAX_N_INT_K3
+    new = max(cur, final_n_int(box_side(lay.pos), tol, k, consts, hi=hi))
+    if new != cur:
+        p = T.TfdpParams(**{**lay.params.as_dict(), "n_int": new})
+        lay.set_params(p)
+    return new
+
+
+def calibrate(T, layouts, n_ints=(16, 24, 32, 48, 64, 96), ks=(1, 2, 3)):
+    """Fit C_k from the library's own forces: for each Layout (positions of
+    a laid-out graph; workspace large enough for max(n_ints)), the relative
+    L2 error of the k-point repulsion against the exact sums at every N_int,
+    then log err = log C_k + k log h by least squares on log C_k.
+    Returns ({k: C_k}, samples). Restores each layout's parameters."""
+    import torch
+    samples = {k: [] for k in ks}
+    for lay in layouts:
+        keep = lay.params
+        exact, _, _ = lay.forces(k=0)
+        torch.cuda.synchronize()
+        ex = exact.double()
+        norm = torch.linalg.norm(ex).item()
+        w = box_side(lay.pos)
+        for ni in n_ints:
+            for k in ks:
+                if ni * k > 1024:
+                    continue
+                p = T.TfdpParams(**{**keep.as_dict(), "n_int": ni, "k_mode": k})
+                lay.set_params(p)
+                fr, _, _ = lay.forces(k=k)
+                torch.cuda.synchronize()
+                err = torch.linalg.norm(fr.double() - ex).item() / max(norm, 1e-300)
+                samples[k].append((w / ni, err))
+        lay.set_params(keep)
+    consts = {}
+    for k in ks:
+        h = np.array([s[0] for s in samples[k]])
+        e = np.array([s[1] for s in samples[k]])
+        ok = (e > 0) & np.isfinite(e)
+        consts[k] = float(np.exp(np.mean(np.log(e[ok]) - k * np.log(h[ok])))) if ok.any() else DEFAULT_C[k]
+    return consts, samples

@@ -270,3 +270,63 @@ def sbm_batch_member(index: int, seed: int = SEED_BASE + 4):
     p_out = min(1.0, 0.2 * 8.0 / max(n - bs, 1.0))
     g = sbm(sizes, p_in, p_out, int(rng.integers(0, 2**31 - 1)))
     return g, uniform_positions(g.n, int(rng.integers(0, 2**31 - 1)))
+
+
+# --------------------------------------------------------------------------
+# Request stream of the serving workload
+# --------------------------------------------------------------------------
+
+def serving_graph(index: int, seed: int = SEED_BASE + 5):
+    """One graph of the serving workload: Chung-Lu with n log-uniform in
+    [1000, 200000], exponent uniform in [2.0, 3.0], mean degree 10."""
+    rng = np.random.default_rng([seed, index])
+    n = int(round(math.exp(rng.uniform(math.log(1000), math.log(200000)))))
+    expo = float(rng.uniform(2.0, 3.0))
+    g = chung_lu(n, expo, 10.0, int(rng.integers(0, 2**31 - 1)))
+    return g, uniform_positions(g.n, int(rng.integers(0, 2**31 - 1)))
+
+
+@dataclass
+class Request:
+    """One request of a serving trace. kind "layout": lay out pool graph
+    `graph` from its initial positions for `iters` iterations; kind
+    "retune": `iters` more iterations of the graph of layout request
+    `target` (resident, from its current positions) with the parameter
+    values in `params`."""
+
+    rid: int
+    arrival: float  # seconds after the start of the trace
+    kind: str
+    graph: int = -1
+    target: int = -1
+    params: dict | None = None
+    iters: int = 200
+
+
+def serving_trace(count: int, rate: float, pool: int, seed: int = SEED_BASE + 6, retune_share: float = 0.3,
+                  layout_iters: int = 200, retune_iters: int = 50):
+    """Poisson arrivals at `rate` requests/s. A request is a re-tune with
+    probability retune_share once a layout request exists; it targets a
+    uniformly chosen earlier layout request and draws alpha in [0.01, 0.5],
+    beta in [1, 50], gamma in [1.5, 8] and rep_weight in [0.5, 4] uniformly.
+    Layout requests take pool graphs round robin from a random start."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    layouts = []
+    g0 = int(rng.integers(0, pool))
+    for rid in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        if layouts and rng.random() < retune_share:
+            params = {
+                "alpha": float(rng.uniform(0.01, 0.5)),
+                "beta": float(rng.uniform(1.0, 50.0)),
+                "gamma": float(rng.uniform(1.5, 8.0)),
+                "rep_weight": float(rng.uniform(0.5, 4.0)),
+            }
+            out.append(Request(rid, t, "retune", target=int(layouts[rng.integers(0, len(layouts))]),
+                               params=params, iters=retune_iters))
+        else:
+            out.append(Request(rid, t, "layout", graph=(g0 + len(layouts)) % pool, iters=layout_iters))
+            layouts.append(rid)
+    return out

@@ -291,12 +291,18 @@ def test_set_params_retune(T):
     w = sg.sbm_1k()
     p = T.tfdp_params_default(n_int=64, k_mode=2)
     lay = T.Layout(w.graph.row_ptr, w.graph.col_idx, w.pos0, p)
+    # grids that need more workspace than the handle has are refused
     with pytest.raises(T.TfdpError):
-        lay.set_params(T.tfdp_params_default(n_int=32, k_mode=2))
+        lay.set_params(T.tfdp_params_default(n_int=128, k_mode=2))
     with pytest.raises(T.TfdpError):
         lay.set_params(T.tfdp_params_default(n_int=64, k_mode=3))
-    lay.set_params(T.tfdp_params_default(n_int=64, k_mode=1, gamma=4.0, rep_weight=2.0, alpha=0.05))
     check_pos = sg.uniform_positions(1000, 3, -5, 5)
+    # a smaller grid fits and is re-laid in place
+    lay.set_params(T.tfdp_params_default(n_int=32, k_mode=2))
+    got = gpu_forces(lay, check_pos, 2)
+    want = oracle_forces(w.graph, check_pos, 2, 32)
+    assert rel_l2(got[2], want[2]) <= TOL
+    lay.set_params(T.tfdp_params_default(n_int=64, k_mode=1, gamma=4.0, rep_weight=2.0, alpha=0.05))
     got = gpu_forces(lay, check_pos, 1)
     want = oracle_forces(w.graph, check_pos, 1, 64, alpha=0.05, gamma=4.0, rep_weight=2.0)
     assert rel_l2(got[2], want[2]) <= TOL
