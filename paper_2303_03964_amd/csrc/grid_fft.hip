@@ -221,9 +221,9 @@ static void allow_big_lds(Kern k) {
 // ----------------------------------------------------------------- spread + kernel rows
 
 // Blocks [0, max_chunks): one chunk of <= kSpreadChunk sorted nodes of one
-// interval row each; per-wave LDS copies of the row's K grid rows (a fixed
-// subset and order of nodes per copy, hence a reproducible sum), summed in
-// wave order and written as one contiguous partial row set.
+// interval row each, accumulated into the row's K grid rows in LDS (exact
+// fixed-point sums, hence reproducible) and written as one contiguous
+// partial row set.
 // Blocks past max_chunks: RBK kernel rows each, FFT over a of
 // K(a, b) + i H_x(a, b); the result is real, its even part the row spectrum of
 // K, minus its odd part the row spectrum of H_x divided by i.
@@ -235,7 +235,13 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     if (bid < b.max_chunks) {
-        float* acc = reinterpret_cast<float*>(smem4);  // [nw][K][M][3]
+        // One block-wide copy of the interval row's K grid rows in 64-bit
+        // fixed point (units of 2^-32; offsets in interval units): integer
+        // LDS atomics are exact, so the sums do not depend on the order of
+        // the adds, and they run several times faster than float LDS
+        // atomics. A chunk holds at most kSpreadChunk nodes with Lagrange
+        // weights of magnitude < 2, far from the 2^63 limit.
+        unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem4);  // [K][M][3]
         const int per = K * M * 3;
         const int blk = bid;
         const int n_int = b.n_int;
@@ -244,10 +250,10 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
         if (blk >= nchunks) return;
         const int beg = b.bucket_start[cy] + (blk - b.chunk_start[cy]) * kSpreadChunk;
         const int end = min(beg + kSpreadChunk, b.bucket_start[cy + 1]);
-        for (int i = threadIdx.x; i < nw * per; i += blockDim.x) acc[i] = 0.f;
+        for (int i = threadIdx.x; i < per; i += blockDim.x) acc[i] = 0ull;
         __syncthreads();
         const Box bx = b.st->box;
-        float* my = acc + w * per;
+        constexpr double kFix = 4294967296.0;  // 2^32
         const int stride = blockDim.x;
         for (int j0 = beg + threadIdx.x; j0 < end; j0 += 4 * stride) {
             float2 pp[4];
@@ -261,11 +267,11 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
                 double tx, ty;
                 bin_axis(p.x, bx.lo_x, bx.h, n_int, cx, tx);
                 bin_axis(p.y, bx.lo_y, bx.h, n_int, cyy, ty);
-                double wx[K], wy[K], dx[K], dy[K];
+                double wx[K], wy[K], ux[K], uy[K];
                 lagrange<K>(tx, wx);
                 lagrange<K>(ty, wy);
-                node_deltas<K>(tx, bx.h, dx);
-                node_deltas<K>(ty, bx.h, dy);
+                node_deltas<K>(tx, 1.0, ux);
+                node_deltas<K>(ty, 1.0, uy);
 #pragma unroll
                 for (int bb = 0; bb < K; ++bb) {
 #pragma unroll
@@ -275,21 +281,20 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
 #pragma clang fp contract(off)
                             wt = wx[a] * wy[bb];
                         }
-                        float* cell = my + ((bb * M) + cx * K + a) * 3;
-                        atomicAdd(cell + 0, (float)wt);
-                        atomicAdd(cell + 1, (float)(wt * dx[a]));
-                        atomicAdd(cell + 2, (float)(wt * dy[bb]));
+                        unsigned long long* cell = acc + ((bb * M) + cx * K + a) * 3;
+                        atomicAdd(cell + 0, (unsigned long long)__double2ll_rn(wt * kFix));
+                        atomicAdd(cell + 1, (unsigned long long)__double2ll_rn(wt * ux[a] * kFix));
+                        atomicAdd(cell + 2, (unsigned long long)__double2ll_rn(wt * uy[bb] * kFix));
                     }
                 }
             }
         }
         __syncthreads();
+        // back to layout units: charges 1 as is, offsets times h
         float* out = b.spart + (size_t)blk * per;
-        for (int i = threadIdx.x; i < per; i += blockDim.x) {
-            float v = acc[i];
-            for (int ww = 1; ww < nw; ++ww) v += acc[ww * per + i];
-            out[i] = v;
-        }
+        const double unit[3] = {1.0 / kFix, bx.h / kFix, bx.h / kFix};
+        for (int i = threadIdx.x; i < per; i += blockDim.x)
+            out[i] = (float)((double)(long long)acc[i] * unit[i % 3]);
         return;
     }
     constexpr int L = 1 << LOGL;
@@ -351,13 +356,12 @@ __global__ __launch_bounds__(512) void kb_spread(const Member* __restrict__ mem,
 }
 
 Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
-    const size_t per = (size_t)g.k * g.m * 3 * sizeof(float);
-    int nw = 8;
-    while (nw > 1 && nw * per > 128 * 1024) nw >>= 1;
+    const size_t per = (size_t)g.k * g.m * 3 * sizeof(unsigned long long);  // <= 74 KB (M <= 1023)
+    const int nw = 8;
     const int F = g.L < 512 ? 512 / g.L : 1;
     const int RBK = 8;
     const size_t kern = (size_t)((RBK + F - 1) / F) * F * g.L * sizeof(float2);
-    const size_t lds = nw * per > kern ? nw * per : kern;
+    const size_t lds = per > kern ? per : kern;
     const int nkb = (g.L + RBK - 1) / RBK;
     *nw_out = nw;
     *nkb_out = nkb;

@@ -8,8 +8,10 @@
 // four per block; a row with more than kGroupEdges entries gets a block of
 // its own. In a wave group, lane l walks CSR entry e0 + l (coalesced reads of
 // packed entries: column plus the row's index in the group), reads its row's
-// position from LDS, and adds its term to a wave-private LDS accumulator;
-// lane r then finishes row r0 + r. A heavy row is summed by all 256 threads and
+// position from LDS and computes its term; a segmented wave sum adds the terms
+// of each row's run into a wave-private LDS accumulator (no float LDS
+// atomics, which are several times slower than the rest of the pass on
+// gfx950); lane r then finishes row r0 + r. A heavy row is summed by all 256 threads and
 // reduced in a fixed order. Every wave handles at most kGroupEdges entries,
 // whatever the degree distribution.
 #include "tfdp_internal.h"
@@ -50,6 +52,42 @@ __device__ __forceinline__ void grid_repulsion(const Bufs& b, const Geom& g, con
             fry += w * (ddy * v.x + v.z);
         }
     }
+}
+
+// Segmented inclusive sums of (x, y) over the lanes of a wave whose keys are
+// non-decreasing with the lane index (a run of equal keys is a segment):
+// afterwards the last lane of every segment holds the segment's sum. Steps of
+// 1, 2, 4, 8 lanes inside each 16-lane row by DPP row shifts, then rows 1 and
+// 3 take the end of rows 0 and 2, then rows 2 and 3 the end of row 1 (a fixed
+// association order, so the sums are reproducible).
+template <int N>
+__device__ __forceinline__ void seg_step_dpp(float& x, float& y, int key) {
+    const int kk = __builtin_amdgcn_update_dpp(-1, key, 0x110 | N, 0xf, 0xf, false);
+    const float xx = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 | N, 0xf, 0xf, false));
+    const float yy = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x110 | N, 0xf, 0xf, false));
+    if (kk == key) {
+        x += xx;
+        y += yy;
+    }
+}
+
+__device__ __forceinline__ void seg_step_lane(float& x, float& y, int key, int lane, int src) {
+    const int kk = __shfl(key, src);
+    const float xx = __shfl(x, src);
+    const float yy = __shfl(y, src);
+    if (src != lane && kk == key) {
+        x += xx;
+        y += yy;
+    }
+}
+
+__device__ __forceinline__ void wave_segmented_sum(float& x, float& y, int key, int lane) {
+    seg_step_dpp<1>(x, y, key);
+    seg_step_dpp<2>(x, y, key);
+    seg_step_dpp<4>(x, y, key);
+    seg_step_dpp<8>(x, y, key);
+    seg_step_lane(x, y, key, lane, ((lane >> 4) & 1) ? (lane & ~15) - 1 : lane);
+    seg_step_lane(x, y, key, lane, lane >= 32 ? 31 : lane);
 }
 
 // Attraction term of one CSR entry: (1 + beta / (1 + d^2)) (x_i - x_j).
@@ -187,15 +225,22 @@ __device__ __forceinline__ void edges_body(const float2* __restrict__ pos, float
             float2 q[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) q[r] = pos[ent[r] & 0x3ffffffu];
+            // per round: terms of 64 consecutive entries, summed per row by
+            // a segmented wave sum; the last lane of each row's run adds the
+            // run's sum to the row (one lane per row and round, so plain LDS
+            // updates suffice: no float atomics)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (eb + r * 64 + lane < ee) {
-                    const int lr = (int)(ent[r] >> 26);
-                    const float2 pr = pw[lr];
-                    float ax, ay;
-                    edge_term(pr.x, pr.y, q[r], a.beta, ax, ay);
-                    atomicAdd(ax_w + lr, ax);
-                    atomicAdd(ay_w + lr, ay);
+                if (eb + r * 64 >= ee) break;
+                const bool valid = eb + r * 64 + lane < ee;
+                const int key = valid ? (int)(ent[r] >> 26) : 127;
+                float ax = 0.f, ay = 0.f;
+                if (valid) edge_term(pw[key].x, pw[key].y, q[r], a.beta, ax, ay);
+                wave_segmented_sum(ax, ay, key, lane);
+                const int knext = __shfl_down(key, 1);
+                if (valid && (lane == 63 || knext != key)) {
+                    ax_w[key] += ax;
+                    ay_w[key] += ay;
                 }
             }
             if (lane < nr) {
