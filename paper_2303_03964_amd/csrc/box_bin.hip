@@ -2,13 +2,13 @@
 // box is split into N_int x N_int intervals; each node is interpolated from
 // the k x k nodes of its own interval).
 //
-// The nodes are bucketed by interval row with a stable counting sort so that
+// The nodes are bucketed by interval row with a counting sort so that
 // the spreading pass can accumulate every row of the grid in LDS without
 // global atomics:
 //   bin_count   per block of kBinChunk nodes: LDS histogram of interval rows
 //   bin_scan    per interval row: exclusive scan of the per-block counts
-//   bin_scatter per block: stable ranks inside the block (wave ballots),
-//               positions written to their sorted slot
+//   bin_scatter per block: slots inside the block's part of each row by
+//               LDS atomics, positions written to their slot
 #include "tfdp_internal.h"
 
 namespace tfdp {
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_scan(Bufs b, int reset_set) {
     bin_scan_body(b, reset_set, blockIdx.x);
 }
 
-// Stable scatter of the positions into interval-row buckets. Block 0 also
+// Scatter of the positions into interval-row buckets. Block 0 also
 // publishes the bucket starts and the first spreading chunk of each row
 // (rows split into chunks of kSpreadChunk nodes, at least one per row).
 __device__ __forceinline__ void bin_scatter_body(const float2* __restrict__ pos, const Bufs& b, int bid) {
@@ -185,8 +185,7 @@ __device__ __forceinline__ void bin_scatter_body(const float2* __restrict__ pos,
     const int n_int = b.n_int;
     int* base = sm;                  // [n_int] global slot of this block's first node per row
     int* run = base + n_int;         // [n_int] nodes of this block already placed per row
-    int* wcnt = run + n_int;         // [4][n_int] per-wave counts of the current round
-    int* scan_lds = wcnt + 4 * n_int;  // [kThreads/64 + 1]
+    int* scan_lds = run + n_int;     // [kThreads/64 + 1]
     // bucket starts: exclusive scan over rows (n_int <= 1024, four per thread)
     int carry = 0;
     int chunk_carry = 0;
@@ -213,50 +212,27 @@ __device__ __forceinline__ void bin_scatter_body(const float2* __restrict__ pos,
         b.bucket_start[n_int] = carry;
         b.chunk_start[n_int] = chunk_carry;
     }
-    for (int i = threadIdx.x; i < 4 * n_int; i += blockDim.x) wcnt[i] = 0;
     __syncthreads();
-
-    int nbits = 1;
-    while ((1 << nbits) < n_int) ++nbits;
+    // slots inside the block's range of each row by LDS atomics: the order
+    // of the nodes inside a row is not fixed, which nothing depends on (the
+    // spreading sums are exact integers)
     const Box bx = b.st->box;
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int beg = bid * kBinChunk;
     const int end = min(beg + kBinChunk, b.n);
-    for (int r0 = beg; r0 < end; r0 += blockDim.x) {
-        const int i = r0 + threadIdx.x;
-        const bool valid = i < end;
-        float2 p = make_float2(0.f, 0.f);
-        int key = 0;
-        if (valid) {
-            p = pos[i];
-            double ty;
-            bin_axis(p.y, bx.lo_y, bx.h, n_int, key, ty);
+    for (int i0 = beg + threadIdx.x; i0 < end; i0 += 4 * blockDim.x) {
+        float2 pp[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pp[u] = pos[min(i0 + u * (int)blockDim.x, end - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (i0 + u * (int)blockDim.x < end) {
+                int key;
+                double ty;
+                bin_axis(pp[u].y, bx.lo_y, bx.h, n_int, key, ty);
+                const int slot = atomicAdd(&run[key], 1);
+                b.spos[base[key] + slot] = pp[u];
+            }
         }
-        unsigned long long peers = __ballot(valid);
-        for (int bit = 0; bit < nbits; ++bit) {
-            const bool set = (key >> bit) & 1;
-            const unsigned long long m = __ballot(set);
-            peers &= set ? m : ~m;
-        }
-        const unsigned long long before = peers & lt_mask;
-        const int rank = __popcll(before);
-        const int cnt = __popcll(peers);
-        const bool leader = valid && before == 0ull;
-        if (leader) wcnt[w * n_int + key] = cnt;
-        __syncthreads();
-        if (valid) {
-            int off = run[key] + rank;
-            for (int ww = 0; ww < w; ++ww) off += wcnt[ww * n_int + key];
-            b.spos[base[key] + off] = p;
-        }
-        __syncthreads();
-        if (leader) {
-            atomicAdd(&run[key], cnt);
-            wcnt[w * n_int + key] = 0;
-        }
-        __syncthreads();
     }
 }
 
@@ -267,7 +243,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restri
 Dims bin_count_dims(const Bufs& b) { return Dims{b.nblk, kThreads, (size_t)b.n_int * sizeof(int)}; }
 Dims bin_scan_dims(const Bufs& b) { return Dims{b.n_int, kThreads, 0}; }
 Dims bin_scatter_dims(const Bufs& b) {
-    return Dims{b.nblk, kThreads, (size_t)(6 * b.n_int + kThreads / 64 + 1) * sizeof(int)};
+    return Dims{b.nblk, kThreads, (size_t)(2 * b.n_int + kThreads / 64 + 1) * sizeof(int)};
 }
 
 void launch_bin_count(const float2* pos, const Bufs& b, int set, hipStream_t s) {

@@ -203,12 +203,15 @@ __device__ __forceinline__ int signed_offset(int r, int M, int L) {
 // Rows per block of the row passes: RB grid rows make 1.5 RB transforms;
 // RBK kernel rows make RBK transforms. Column tiles of RB (RBK) consecutive
 // rows are stored with one RB * 8-byte write per column; pairs of logical
-// blocks share an XCD so that each 128-byte line is filled from one L2.
+// blocks share an XCD so that a line is filled from fewer L2s.
 template <int LOGL>
 struct RowTile {
-    static constexpr int RB = LOGL <= 10 ? 8 : 4;
+    // few rows per block at small L so that a 256 x 256 grid still makes
+    // 128 blocks (measured: RB 8 -> 2 took the k = 1 row passes at N_int 256
+    // from 17.5 + 11.2 us to 10.3 + 8.5 us)
+    static constexpr int RB = LOGL <= 9 ? 2 : 4;
     static constexpr int RBK = 8;
-    static constexpr int THREADS = 512;
+    static constexpr int THREADS = LOGL <= 9 ? 256 : 512;
 };
 
 // Allow dynamic LDS beyond 64 KB (gfx950 has 160 KB per workgroup); once per kernel.
@@ -290,11 +293,10 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
             }
         }
         __syncthreads();
-        // back to layout units: charges 1 as is, offsets times h
-        float* out = b.spart + (size_t)blk * per;
-        const double unit[3] = {1.0 / kFix, bx.h / kFix, bx.h / kFix};
-        for (int i = threadIdx.x; i < per; i += blockDim.x)
-            out[i] = (float)((double)(long long)acc[i] * unit[i % 3]);
+        // partial rows stay in fixed point: the row pass sums the chunks of a
+        // row exactly, so no result depends on how a row is cut into chunks
+        unsigned long long* out = b.spart + (size_t)blk * per;
+        for (int i = threadIdx.x; i < per; i += blockDim.x) out[i] = acc[i];
         return;
     }
     constexpr int L = 1 << LOGL;
@@ -443,6 +445,8 @@ __device__ __forceinline__ void rowfft_body(const Bufs& b, const Geom& g, int lb
     const int nwav = blockDim.x >> 6;
     const int y0 = lb * RB;
     const int per = K * M * 3;
+    const double u1 = 1.0 / 4294967296.0;
+    const double uh = b.st->box.h / 4294967296.0;
     for (int i = threadIdx.x; i < NQT * TL; i += blockDim.x) z[i] = make_float2(0.f, 0.f);
     __syncthreads();
     for (int i = threadIdx.x; i < RB * M; i += blockDim.x) {
@@ -451,13 +455,17 @@ __device__ __forceinline__ void rowfft_body(const Bufs& b, const Geom& g, int lb
         if (y >= M) continue;
         const int cy = y / K, bb = y % K;
         const int c0 = b.chunk_start[cy], c1 = b.chunk_start[cy + 1];
-        float s1 = 0.f, sx = 0.f, sy = 0.f;
+        unsigned long long a1 = 0, ax = 0, ay = 0;
         for (int c = c0; c < c1; ++c) {
-            const float* e = b.spart + (size_t)c * per + (bb * M + x) * 3;
-            s1 += e[0];
-            sx += e[1];
-            sy += e[2];
+            const unsigned long long* e = b.spart + (size_t)c * per + (bb * M + x) * 3;
+            a1 += e[0];
+            ax += e[1];
+            ay += e[2];
         }
+        // fixed point (2^-32 units; offsets in interval units) to layout units
+        const float s1 = (float)((double)(long long)a1 * u1);
+        const float sx = (float)((double)(long long)ax * uh);
+        const float sy = (float)((double)(long long)ay * uh);
         const int q = r >> 1;
         z[(3 * q + ((r & 1) ? 2 : 0)) * L + x] = make_float2(s1, sx);
         reinterpret_cast<float*>(z + (3 * q + 1) * L + x)[r & 1] = sy;

@@ -59,7 +59,7 @@ struct Bufs {
     int* bucket_start;   // [n_int + 1]
     int* chunk_start;    // [n_int + 1] first spreading chunk of each interval row
     int* chunk_row;      // [max_chunks] interval row of each spreading chunk
-    float* spart;        // [max_chunks][k][M][3] partial grid rows of each chunk
+    unsigned long long* spart;  // [max_chunks][k][M][3] partial grid rows of each chunk (fixed point)
     float2* qcol;        // [3][H][M] charge row spectra, column-major
     float2* kcol;        // [H][L] kernel row spectra (K^, H_x^/i), column-major
     float2* pcol;        // [3][H][M] potential row spectra after the column pass
