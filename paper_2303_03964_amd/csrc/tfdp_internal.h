@@ -8,7 +8,7 @@
 namespace tfdp {
 
 constexpr int kThreads = 256;        // threads per block of the node and FFT kernels
-constexpr int kBinChunk = 1024;      // nodes per block of the binning passes
+constexpr int kBinChunk = 2048;      // nodes per block of the binning passes
 constexpr int kSpreadChunk = 4096;   // sorted nodes per block of the spreading pass
 constexpr int kBoxSlots = 64;        // slots of the box extremes (one 128-byte line each)
 constexpr int kMaxL = 2048;          // largest FFT length per side
