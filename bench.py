@@ -123,54 +123,78 @@ def cpu_baseline(w, iters):
     }
 
 
-def batched_section(T, torch, stream, graphs, iters):
+def batched_section(T, torch, stream, graphs, iters, accuracy=True):
     """Batched workload: `graphs` SBMs with n log-uniform in [200, 20000]
-    (2..20 blocks, mean degree 8), N_int from the size rule of the grid
-    autotuner, T = iters. Times one tfdp_batch_step(iters) over all graphs
-    against the same graphs stepped one after another with
-    tfdp_layout_step(iters) on the same stream, from the same positions."""
+    (2..20 blocks, mean degree 8), T = iters, grids from the autotuner: the
+    size rule for the k = 1 and k = 2 stages and, with `accuracy`, at the
+    switch to k = 3 the final grid from each layout's box for a k = 3
+    repulsion error of 1e-3 (workspaces sized for the cap at creation).
+    Times the whole schedule stepped by one tfdp_batch against the same
+    graphs stepped one after another with tfdp_layout_step on the same
+    stream, from the same positions, with the same re-tune in between."""
     import synthgraphs as sg
     from paper_2303_03964_amd import autotune
     t_gen = time.perf_counter()
     members = [sg.sbm_batch_member(i) for i in range(graphs)]
     gen_s = time.perf_counter() - t_gen
-    lays, pos0 = [], []
+    lays, pos0, p1 = [], [], []
     for g, pos in members:
         p = T.tfdp_params_default(n_int=autotune.n_int_for_size(g.n), total_iters=iters, k_mode=-1)
+        ws = T.tfdp_params_default(n_int=autotune.workspace_grid(g.n), total_iters=iters, k_mode=-1)
         pt = torch.as_tensor(pos).cuda()
         pos0.append(pt.clone())
-        lays.append(T.Layout(g.row_ptr, g.col_idx, pt, p))
+        p1.append(p)
+        lays.append(T.Layout(g.row_ptr, g.col_idx, pt, p, workspace_params=ws))
     n_tot = sum(l.n for l in lays)
     nnz_tot = sum(l.nnz for l in lays)
+    stage1 = (19 * iters) // 20 if accuracy else iters  # first k = 3 iteration
     B = T.Batch(len(lays))
     for lay in lays:
         B.add(lay)
 
     def reset():
-        for lay, p0 in zip(lays, pos0):
+        for lay, p0, p in zip(lays, pos0, p1):
+            lay.set_params(p)
             lay.pos.copy_(p0)
             lay.iteration = 0
         torch.cuda.synchronize()
 
-    # warm-up: device tables, captured graphs, plain graphs
-    B.step(iters)
-    for lay in lays:
-        lay.step(iters)
-    torch.cuda.synchronize()
-    reset()
-    t0 = time.perf_counter()
-    B.step(iters)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
+    def run(batched):
+        reset()
+        t0 = time.perf_counter()
+        if batched:
+            B.step(stage1)
+        else:
+            for lay in lays:
+                lay.step(stage1)
+        torch.cuda.synchronize()
+        if stage1 < iters:
+            grids = autotune.retune_many(lays)
+            if batched:
+                B.step(iters - stage1)
+            else:
+                for lay in lays:
+                    lay.step(iters - stage1)
+            torch.cuda.synchronize()
+        else:
+            grids = [lay.params.n_int for lay in lays]
+        return time.perf_counter() - t0, grids
+
+    run(True)   # warm-up: device tables, captured graphs of both stages
+    run(False)
+    t_batch, grids = run(True)
     final_batch = [lay.pos.clone() for lay in lays]
-    reset()
-    t0 = time.perf_counter()
-    for lay in lays:
-        lay.step(iters)
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    same = all(torch.equal(a, lay.pos) for a, lay in zip(final_batch, lays))
+    t_seq, grids_seq = run(False)
+    same = all(torch.equal(a, lay.pos) for a, lay in zip(final_batch, lays)) and grids == grids_seq
     bad = [lay.sync_status() for lay in lays]
+    # repulsion error of the final grid at the final positions (k = 3 against
+    # the exact sums), on every 16th graph
+    errs = []
+    for lay in lays[::16]:
+        ex, _, _ = lay.forces(k=0)
+        fr, _, _ = lay.forces(k=3)
+        torch.cuda.synchronize()
+        errs.append(float(torch.linalg.norm((fr - ex).double()) / torch.linalg.norm(ex.double())))
     B.close()
     for lay in lays:
         lay.close()
@@ -180,7 +204,10 @@ def batched_section(T, torch, stream, graphs, iters):
         "nodes": n_tot,
         "nnz": nnz_tot,
         "iters": iters,
-        "n_int_rule": "64 (n/1000)^(1/5) rounded up to a multiple of 8",
+        "grid_rule": ("k=1,2: N_int = 64 (n/1000)^(1/5); k=3: N_int = ceil(1.2 W / h3(1e-3)) at the switch"
+                      if accuracy else "N_int = 64 (n/1000)^(1/5) for the whole schedule"),
+        "final_n_int": {"min": min(grids), "median": int(np.median(grids)), "max": max(grids)},
+        "final_k3_rel_err_vs_exact": {"graphs": len(errs), "median": float(np.median(errs)), "max": max(errs)},
         "value": n_tot * iters / t_batch,
         "unit": "node-iterations/s",
         "ms": t_batch * 1e3,
@@ -381,6 +408,10 @@ def main():
     if not args.no_batch:
         rec["batched"] = batched_section(T, torch, stream, args.batch_graphs, args.batch_iters)
         print(f"# batched: {json.dumps(rec['batched'])}", file=sys.stderr, flush=True)
+        rec["batched_size_rule_grids"] = batched_section(T, torch, stream, args.batch_graphs, args.batch_iters,
+                                                         accuracy=False)
+        print(f"# batched (size-rule grids): {json.dumps(rec['batched_size_rule_grids'])}", file=sys.stderr,
+              flush=True)
     if not args.no_serve:
         rec["serving"] = serving_section(T, torch, stream, args.serve_requests)
     if not args.no_cpu_baseline:

@@ -1,0 +1,56 @@
+"""Grid autotuner rules (host only) and its error model against the FP64
+oracle: on laid-out graphs, the final-stage grid it picks keeps the k = 3
+repulsion within the requested tolerance of the exact sums."""
+import math
+
+import numpy as np
+import pytest
+
+import synthgraphs as sg
+from oracle import tfdp as ot
+from paper_2303_03964_amd import autotune
+
+
+def test_size_rule_passes_through_workload_grids():
+    assert autotune.n_int_for_size(1000) == 64
+    assert autotune.n_int_for_size(1_000_000) == 256
+    vals = [autotune.n_int_for_size(n) for n in (200, 2000, 20000, 200000)]
+    assert vals == sorted(vals) and all(v % 8 == 0 for v in vals)
+
+
+def test_final_grid_meets_model_tolerance():
+    for w in (5.0, 40.0, 120.0):
+        for tol in (1e-2, 1e-3, 1e-4):
+            m = 1.2
+            ni = autotune.final_n_int(w, tol, margin=m, hi=10 ** 6)
+            # the widened box meets the tolerance, one interval fewer would not
+            assert autotune.DEFAULT_C[3] * (m * w / ni) ** 3 <= tol * (1 + 1e-9)
+            assert ni == 8 or autotune.DEFAULT_C[3] * (m * w / (ni - 1)) ** 3 > tol * 0.999
+
+
+def test_workspace_grid_caps():
+    assert autotune.workspace_grid(20000) == autotune.MAX_N_INT_K3
+    assert autotune.n_int_for_size(200) <= autotune.workspace_grid(200) <= autotune.MAX_N_INT_K3
+
+
+def test_box_side():
+    p = np.array([[0, 0], [3, 1], [1, -1], [np.nan, 5]], np.float32)
+    assert autotune.box_side(p) == pytest.approx(3.0)
+
+
+@pytest.mark.parametrize("index", [1, 11, 13])
+def test_error_model_against_oracle(index):
+    """Lay out a batch-workload graph with the oracle, pick the final grid for
+    tol = 1e-3 and check the oracle's k = 3 interpolated repulsion against its
+    exact sums."""
+    g, pos0 = sg.sbm_batch_member(index)
+    if g.n > 1500:
+        pytest.skip("kept small for the CPU suite")
+    p = ot.Params(n_int=autotune.n_int_for_size(g.n), total_iters=300, k_mode=1)
+    x = ot.layout(pos0.astype(np.float64), g.row_ptr, g.col_idx, p, iters=270)
+    tol = 1e-3
+    ni = autotune.final_n_int(autotune.box_side(x), tol)
+    ex = ot.repulsion_exact(x, 2.0)
+    fr = ot.repulsion_ibfft_stable(x, 2.0, ni, 3)
+    err = np.linalg.norm(fr - ex) / np.linalg.norm(ex)
+    assert err <= tol, (g.n, ni, err)
