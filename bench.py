@@ -139,8 +139,10 @@ def batched_section(T, torch, stream, graphs, iters, accuracy=True):
     gen_s = time.perf_counter() - t_gen
     lays, pos0, p1 = [], [], []
     for g, pos in members:
-        p = T.tfdp_params_default(n_int=autotune.n_int_for_size(g.n), total_iters=iters, k_mode=-1)
-        ws = T.tfdp_params_default(n_int=autotune.workspace_grid(g.n), total_iters=iters, k_mode=-1)
+        k_mode, n_int = autotune.start_params(g.n)
+        p = T.tfdp_params_default(n_int=n_int, total_iters=iters, k_mode=k_mode)
+        ws = (T.tfdp_params_default(n_int=max(n_int, autotune.workspace_grid(g.n)), total_iters=iters)
+              if accuracy and k_mode != 0 else p)
         pt = torch.as_tensor(pos).cuda()
         pos0.append(pt.clone())
         p1.append(p)
@@ -190,7 +192,7 @@ def batched_section(T, torch, stream, graphs, iters, accuracy=True):
     # repulsion error of the final grid at the final positions (k = 3 against
     # the exact sums), on every 16th graph
     errs = []
-    for lay in lays[::16]:
+    for lay in [l for l in lays if l.params.k_mode != 0][::16]:
         ex, _, _ = lay.forces(k=0)
         fr, _, _ = lay.forces(k=3)
         torch.cuda.synchronize()
@@ -204,8 +206,10 @@ def batched_section(T, torch, stream, graphs, iters, accuracy=True):
         "nodes": n_tot,
         "nnz": nnz_tot,
         "iters": iters,
-        "grid_rule": ("k=1,2: N_int = 64 (n/1000)^(1/5); k=3: N_int = ceil(1.2 W / h3(1e-3)) at the switch"
-                      if accuracy else "N_int = 64 (n/1000)^(1/5) for the whole schedule"),
+        "grid_rule": ("n <= 1024: exact method; else k=1,2: N_int = 64 (n/1000)^(1/5) rounded down to a "
+                      "power of two when within 25%; k=3: N_int = ceil(1.2 W / h3(1e-3)) at the switch"
+                      if accuracy else "n <= 1024: exact method; else the k=1,2 grid for the whole schedule"),
+        "exact_method_graphs": sum(1 for l in lays if l.params.k_mode == 0),
         "final_n_int": {"min": min(grids), "median": int(np.median(grids)), "max": max(grids)},
         "final_k3_rel_err_vs_exact": {"graphs": len(errs), "median": float(np.median(errs)), "max": max(errs)},
         "value": n_tot * iters / t_batch,

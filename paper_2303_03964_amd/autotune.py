@@ -6,12 +6,15 @@ interpolation is set by the interval width h = W / N_int (W = side of the
 layout box) and by k: the relative L2 error of the repulsion behaves like
 C_k h^k (k-point Lagrange interpolation per interval).
 
-The tuner works in two stages, matching the k schedule of Sec. 3.4:
+The tuner works in two stages, matching the k schedule of Sec. 3.4
+(graphs of at most EXACT_MAX_N nodes use the exact method instead):
 
 * start (k = 1 and 2, the first 95% of the iterations): N_int from the
   graph size, ``n_int_for_size``: N_int = 64 (n / 1000)^(1/5), a multiple
   of 8, which passes through the grids of the 10^3-node (64) and
-  10^6-node (256) workloads;
+  10^6-node (256) workloads; ``start_params`` rounds it down to a power of
+  two when it exceeds one by at most 25% (half the FFT length, a quarter of
+  the grid work);
 * final (k = 3, the last 5%): at the switch, the box side W of the current
   layout fixes N_int = ceil(margin W / h_k(tol)) with h_k(tol) =
   (tol / C_k)^(1/k) and margin 1.2 for the growth of the box over the last
@@ -42,6 +45,26 @@ MAX_N_INT_K3 = 341  # N_int * 3 * 2 <= 2048 (largest FFT length)
 def n_int_for_size(n: int) -> int:
     v = 64.0 * (max(n, 1) / 1000.0) ** 0.2
     return int(min(1024, max(8, 8 * math.ceil(v / 8.0))))
+
+
+EXACT_MAX_N = 1024  # at most this many nodes: the exact O(n^2) method
+
+
+def fft_rounded(n_int: int, slack: float = 1.25) -> int:
+    """The FFT length per side is the power of two >= 2 N_int k: a grid just
+    above a power of two doubles the FFT length of every pass. Round N_int
+    down to that power of two when it exceeds it by at most `slack`."""
+    p = 1 << max(0, (n_int - 1).bit_length() - 1)  # largest power of two < n_int
+    return p if p >= 8 and n_int <= slack * p else n_int
+
+
+def start_params(n: int):
+    """(k_mode, N_int) for the start of a layout of n nodes: the exact method
+    up to EXACT_MAX_N nodes (cheaper than a grid there, and exact), else the
+    k schedule on the size-rule grid rounded down to an FFT-friendly size."""
+    if n <= EXACT_MAX_N:
+        return 0, 8
+    return -1, fft_rounded(n_int_for_size(n))
 
 
 def interval_width(tol: float, k: int, consts=None) -> float:
@@ -89,7 +112,8 @@ def retune(lay, tol: float = 1e-3, consts=None, k: int = 3, cap: int | None = No
 
 
 def retune_many(layouts, tol: float = 1e-3, consts=None, k: int = 3):
-    """retune for many Layouts with one device-to-host copy of all positions."""
+    """retune for many Layouts with one device-to-host copy of all positions
+    (exact-method layouts keep their parameters)."""
     import torch
     from . import tfdp as T
     host = torch.cat([lay.pos for lay in layouts]).cpu().numpy()
@@ -98,6 +122,9 @@ def retune_many(layouts, tol: float = 1e-3, consts=None, k: int = 3):
         w = box_side(host[off:off + lay.n])
         off += lay.n
         cur = lay.params.n_int
+        if lay.params.k_mode == 0:
+            out.append(cur)
+            continue
         new = max(cur, final_n_int(w, tol, k, consts))
         if new != cur:
             lay.set_params(T.TfdpParams(**{**lay.params.as_dict(), "n_int": new}))

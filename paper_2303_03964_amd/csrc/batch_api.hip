@@ -19,12 +19,12 @@ using namespace tfdp;
 
 namespace {
 
-enum BPhase { B_BIN_COUNT, B_BIN_SCAN, B_BIN_SCATTER, B_SPREAD, B_ROWFFT, B_COLCONV, B_ROWIFFT, B_EDGES };
+enum BPhase { B_BIN_COUNT, B_BIN_SCAN, B_BIN_SCATTER, B_SPREAD, B_ROWFFT, B_COLCONV, B_ROWIFFT, B_EDGES, B_BRUTE };
 
 struct BLaunch {
     int phase;
-    int k, logL, nw;
-    size_t off;  // first map entry
+    int k, logL, nw;  // B_BRUTE: nw = offset of the tick map (one entry per member), k = members
+    size_t off;       // first map entry
     int blocks;
     size_t lds;
 };
@@ -33,7 +33,6 @@ struct BLaunch {
 struct Comp {
     std::vector<int> ks;            // k per slot (0: exact method)
     std::vector<BLaunch> launches;  // one iteration, in dependency order
-    std::vector<int> brute;         // slots with k == 0 (plain launches)
     int2* d_map = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};  // pairs starting at an even / odd j
     unsigned long long last_use = 0;
@@ -176,21 +175,18 @@ long long member_work(const tfdp_layout* h) { return (long long)h->n + h->nnz; }
 tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s, Comp& c) {
     c.ks = ks;
     const int nm = (int)b->mem.size();
-    std::vector<int> order;
-    for (int i = 0; i < nm; ++i) {
-        if (ks[i] == 0)
-            c.brute.push_back(i);
-        else
-            order.push_back(i);
-    }
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return member_work(b->mem[x]) > member_work(b->mem[y]); });
+    std::vector<int> order, brute;
+    for (int i = 0; i < nm; ++i) (ks[i] == 0 ? brute : order).push_back(i);
+    auto bigger_first = [&](int x, int y) { return member_work(b->mem[x]) > member_work(b->mem[y]); };
+    std::stable_sort(order.begin(), order.end(), bigger_first);
+    std::stable_sort(brute.begin(), brute.end(), bigger_first);
     std::vector<int2> map;
     auto emit = [&](int phase, int k, int logL, int nw, size_t lds, const std::vector<int>& who,
                     const std::vector<int>& blocks) {
         BLaunch L{phase, k, logL, nw, map.size(), 0, lds};
         for (size_t q = 0; q < who.size(); ++q)
-            for (int j = 0; j < blocks[q]; ++j) map.push_back(make_int2(entry_of(who[q], ks[who[q]]), j));
+            for (int j = 0; j < blocks[q]; ++j)
+                map.push_back(make_int2(entry_of(who[q], ks[who[q]] > 0 ? ks[who[q]] : 1), j));
         L.blocks = (int)(map.size() - L.off);
         if (L.blocks > 0) c.launches.push_back(L);
     };
@@ -266,6 +262,14 @@ tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s,
             emit(B_EDGES, kv.first, 0, 0, 0, kv.second, blocks);
         }
     }
+    // exact method: one launch for all such members, then their counters
+    if (!brute.empty()) {
+        std::vector<int> blocks;
+        for (int i : brute) blocks.push_back((b->mem[i]->n + kThreads - 1) / kThreads);
+        const size_t tick = map.size();
+        for (int i : brute) map.push_back(make_int2(entry_of(i, 1), 0));
+        emit(B_BRUTE, (int)brute.size(), 0, (int)tick, 0, brute, blocks);
+    }
     if (!map.empty()) {
         tfdp_status st = check_hip(hipMalloc(&c.d_map, map.size() * sizeof(int2)), "hipMalloc");
         if (st != TFDP_OK) return st;
@@ -302,8 +306,8 @@ Comp* get_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s, tfdp_st
     return &c;
 }
 
-// Iteration j of the call (j only matters by its parity, except for the
-// exact-method members, whose plain launches take the iteration index).
+// Iteration j of the call (the kernels read each member's counter at the
+// start of the call from the device and add j).
 void enqueue_iter(tfdp_batch* b, const Comp& c, int j, hipStream_t s) {
     const Member* mem = b->d_mem;
     for (const BLaunch& L : c.launches) {
@@ -316,17 +320,9 @@ void enqueue_iter(tfdp_batch* b, const Comp& c, int j, hipStream_t s) {
             case B_ROWFFT: launch_b_rowfft(L.logL, mem, map, L.blocks, s); break;
             case B_COLCONV: launch_b_colconv(L.logL, mem, map, L.blocks, s); break;
             case B_ROWIFFT: launch_b_rowifft(L.logL, mem, map, L.blocks, s); break;
-            default: launch_b_edges(L.k, mem, map, L.blocks, b->d_t, j, s); break;
+            case B_EDGES: launch_b_edges(L.k, mem, map, L.blocks, b->d_t, j, s); break;
+            default: launch_b_brute(mem, map, L.blocks, c.d_map + L.nw, L.k, j, s); break;
         }
-    }
-    for (int i : c.brute) {
-        tfdp_layout* h = b->mem[i];
-        float2* A = reinterpret_cast<float2*>(h->pos);
-        float2* B = h->lay.pos_alt;
-        const float2* cur = (j & 1) ? B : A;
-        float2* nxt = (j & 1) ? A : B;
-        launch_brute(cur, nxt, h->row_ptr, h->col_idx, h->n, h->lay.b.st, model_args(h), h->t + j, nullptr, nullptr,
-                     nullptr, s);
     }
 }
 
@@ -481,7 +477,7 @@ tfdp_status tfdp_batch_step(tfdp_batch* b, int32_t iters, hipStream_t s) {
                     pair_same = false;
                     break;
                 }
-        if (b->graphs && pair_same && c->brute.empty()) {
+        if (b->graphs && pair_same) {
             hipGraphExec_t ex = pair_graph(b, *c, j & 1, s);
             if (ex) {
                 st = check_hip(hipGraphLaunch(ex, s), "hipGraphLaunch");

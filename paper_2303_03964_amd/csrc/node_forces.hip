@@ -342,14 +342,14 @@ void launch_edges(const float2* pos, float2* pos_out, const EdgeSlice& es, int m
 // Exact repulsion: F_i = sum_j K_ij (x_i - x_j), K_ij = (1 + d_ij^2)^-gamma
 // (Eq.11; the j = i term is zero), positions streamed through LDS tiles;
 // attraction by a per-thread row loop (used for small graphs).
-__global__ __launch_bounds__(kThreads) void k_brute(const float2* __restrict__ pos, int n,
-                                                    float2* __restrict__ pos_out,
-                                                    const int* __restrict__ row_ptr,
-                                                    const int* __restrict__ col_idx, DevState* st,
-                                                    ModelArgs a, int t, float2* f_rep, float2* f_att,
-                                                    float2* f_tot) {
+// Columns are read through the 26-bit column mask, so the packed edge-pass
+// entries (column | row-in-group << 26) serve as well as a plain CSR.
+__device__ __forceinline__ void brute_body(const float2* __restrict__ pos, int n, float2* __restrict__ pos_out,
+                                           const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
+                                           DevState* st, const ModelArgs& a, int t, float2* f_rep, float2* f_att,
+                                           float2* f_tot, int bid) {
     __shared__ float2 tile[kThreads];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = bid * blockDim.x + threadIdx.x;
     const bool active = i < n;
     const float2 p = active ? pos[i] : make_float2(0.f, 0.f);
     const bool g2 = a.gamma == 2.0f;
@@ -382,12 +382,47 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float2* __restrict__ p
         const int e1 = row_ptr[i + 1];
         for (int e = row_ptr[i]; e < e1; ++e) {
             float ax, ay;
-            edge_term(p.x, p.y, pos[col_idx[e]], a.beta, ax, ay);
+            edge_term(p.x, p.y, pos[col_idx[e] & 0x3ffffff], a.beta, ax, ay);
             sax += ax;
             say += ay;
         }
         node_output(i, p, frx, fry, sax, say, a, t, st, pos_out, f_rep, f_att, f_tot, xmin, ymin, xmax, ymax);
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_brute(const float2* __restrict__ pos, int n,
+                                                    float2* __restrict__ pos_out,
+                                                    const int* __restrict__ row_ptr,
+                                                    const int* __restrict__ col_idx, DevState* st,
+                                                    ModelArgs a, int t, float2* f_rep, float2* f_att,
+                                                    float2* f_tot) {
+    brute_body(pos, n, pos_out, row_ptr, col_idx, st, a, t, f_rep, f_att, f_tot, blockIdx.x);
+}
+
+// Batched exact method, iteration j of a call (j by its parity only: the
+// kernels are replayed from captured graphs). The update's counter is the
+// member's device counter plus one; kb_tick then advances that counter
+// (the call start sets it to t0 - 1, like the binning scan of the
+// interpolated path).
+__global__ __launch_bounds__(kThreads) void kb_brute(const Member* __restrict__ mem, const int2* __restrict__ map,
+                                                     int j) {
+    const int2 e = map[blockIdx.x];
+    const Member& m = mem[e.x];
+    const float2* cur = (j & 1) ? m.alt : m.pos;
+    float2* nxt = (j & 1) ? m.pos : m.alt;
+    brute_body(cur, m.b.n, nxt, m.es.rp, m.es.col, m.b.st, m.a, m.b.st->t + 1, nullptr, nullptr, nullptr, e.y);
+}
+
+__global__ void kb_tick(const Member* __restrict__ mem, const int2* __restrict__ map, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) mem[map[i].x].b.st->t += 1;
+}
+
+void launch_b_brute(const Member* mem, const int2* map, int blocks, const int2* tick_map, int members, int j,
+                    hipStream_t s) {
+    if (blocks <= 0) return;
+    hipLaunchKernelGGL(kb_brute, dim3(blocks), dim3(kThreads), 0, s, mem, map, j);
+    hipLaunchKernelGGL(kb_tick, dim3((members + 255) / 256), dim3(256), 0, s, mem, tick_map, members);
 }
 
 void launch_brute(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx, int n,

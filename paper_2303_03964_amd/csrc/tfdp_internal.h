@@ -188,6 +188,10 @@ void launch_b_edges(int k, const Member* mem, const int2* map, int blocks, const
                     hipStream_t s);
 void launch_b_copy(const Member* mem, const int2* map, int blocks, hipStream_t s);
 void launch_b_advance(int* tcall, int slots, int iters, hipStream_t s);
+// exact method of the k = 0 members, then their counters advance (tick_map:
+// one entry per member)
+void launch_b_brute(const Member* mem, const int2* map, int blocks, const int2* tick_map, int members, int j,
+                    hipStream_t s);
 
 // ---- device helpers used by several translation units ----
 

@@ -7,9 +7,10 @@ as soon as its iterations are done, so requests that arrive while others are
 on the device join the running batch at the next chunk.
 
 * layout request: the graph's CSR and initial positions are uploaded, a
-  layout handle is created with its grid from the autotuner's size rule
-  (workspace sized for the largest final grid the tuner may choose) and
-  added to the batch for `iters` iterations (k schedule over T = iters).
+  layout handle is created with the autotuner's start choice (exact method
+  for small graphs, else its grid; workspace sized for the largest final
+  grid the tuner may choose) and added to the batch for `iters` iterations
+  (k schedule over T = iters).
 * re-tune request (Sec. 5, global refinement): a finished graph stays
   resident; the request changes alpha, beta, gamma and the repulsion weight,
   restarts the counter with T = iters and a unit step cap, and runs again
@@ -104,7 +105,8 @@ class Server:
 
     def _make_layout(self, g: _Graph, pos, params):
         n, nnz = g.graph.n, g.graph.nnz
-        ws = T.TfdpParams(**{**params.as_dict(), "n_int": autotune.workspace_grid(n), "k_mode": -1})
+        ws = params if params.k_mode == 0 else T.TfdpParams(
+            **{**params.as_dict(), "n_int": max(params.n_int, autotune.workspace_grid(n)), "k_mode": -1})
         need = footprint(n, nnz, ws)
         if not self._evict_for(need):
             return False
@@ -121,7 +123,8 @@ class Server:
         if req.kind == "layout":
             graph, pos0 = self.pool[req.graph]
             g = _Graph(req.rid, graph)
-            p = T.tfdp_params_default(n_int=autotune.n_int_for_size(graph.n), total_iters=req.iters, k_mode=-1)
+            k_mode, n_int = autotune.start_params(graph.n)
+            p = T.tfdp_params_default(n_int=n_int, total_iters=req.iters, k_mode=k_mode)
             if not self._make_layout(g, torch.as_tensor(pos0).cuda(), p):
                 return False
             self.graphs[req.rid] = g
@@ -130,8 +133,7 @@ class Server:
             if g is None or g.busy:
                 return False  # target not laid out yet, or still running
             base = g.lay.params if g.lay is not None else self._last_params[req.target]
-            p = T.TfdpParams(**{**base.as_dict(), **req.params, "total_iters": req.iters, "t0": 1.0,
-                                "n_int": autotune.n_int_for_size(g.graph.n), "k_mode": -1})
+            p = T.TfdpParams(**{**base.as_dict(), **req.params, "total_iters": req.iters, "t0": 1.0})
             if g.lay is None:
                 if not self._make_layout(g, torch.as_tensor(g.host_pos).cuda(), p):
                     return False
