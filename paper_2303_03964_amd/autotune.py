@@ -17,10 +17,11 @@ The tuner works in two stages, matching the k schedule of Sec. 3.4
   the grid work);
 * final (k = 3, the last 5%): at the switch, the box side W of the current
   layout fixes N_int = ceil(margin W / h_k(tol)) with h_k(tol) =
-  (tol / C_k)^(1/k) and margin 1.2 for the growth of the box over the last
+  (tol / C_k)^(1/k) and margin 1.4 for the growth of the box over the last
   iterations, so that the repulsion of the last iterations is within ``tol``
   of the exact sums (k = 2 keeps the starting grid: 1e-3 at k = 2 would need
-  h ~ 0.1). ``retune`` applies it with tfdp_layout_set_params (the
+  h ~ 0.1); where the exact method costs less than that grid
+  (``final_choice``), the last stage switches to it instead. ``retune`` applies it with tfdp_layout_set_params (the
   workspace is sized for the cap at creation, ``workspace_grid``).
 
 C_k comes from ``calibrate``: exact (k = 0) against interpolated forces of
@@ -72,7 +73,7 @@ def interval_width(tol: float, k: int, consts=None) -> float:
     return (tol / c) ** (1.0 / k)
 
 
-def final_n_int(width: float, tol: float = 1e-3, k: int = 3, consts=None, margin: float = 1.2,
+def final_n_int(width: float, tol: float = 1e-3, k: int = 3, consts=None, margin: float = 1.4,
                 lo: int = 8, hi: int = MAX_N_INT_K3) -> int:
     """Intervals per side for a box of side `width` so that k-point
     interpolation stays within `tol` (relative L2 of the repulsion)."""
@@ -111,9 +112,33 @@ def retune(lay, tol: float = 1e-3, consts=None, k: int = 3, cap: int | None = No
     return new
 
 
-def retune_many(layouts, tol: float = 1e-3, consts=None, k: int = 3):
-    """retune for many Layouts with one device-to-host copy of all positions
-    (exact-method layouts keep their parameters)."""
+# Exact against interpolated cost per iteration, measured on MI355X in
+# batches: n^2 pair terms of the exact method cost about as much as 12^2 L^2
+# grid points of the k = 3 passes (L = FFT length per side)
+EXACT_PER_FFT_LENGTH = 12
+
+
+def fft_length(n_int: int, k: int) -> int:
+    L = 64
+    while L < 2 * n_int * k:
+        L *= 2
+    return L
+
+
+def final_choice(n: int, width: float, tol: float = 1e-3, consts=None):
+    """(k_mode, N_int) for the k = 3 stage: the grid that meets `tol`, or the
+    exact method when that is cheaper than the grid."""
+    ni = final_n_int(width, tol, 3, consts)
+    if n <= EXACT_PER_FFT_LENGTH * fft_length(ni, 3):
+        return 0, None
+    return -1, ni
+
+
+def retune_many(layouts, tol: float = 1e-3, consts=None, allow_exact: bool = True):
+    """The k = 3 stage choice for many Layouts (one device-to-host copy of
+    all positions): the exact method where it is cheaper, else the grid from
+    each box. Exact-method layouts keep their parameters. Returns the N_int
+    of each layout (0 for the exact method)."""
     import torch
     from . import tfdp as T
     host = torch.cat([lay.pos for lay in layouts]).cpu().numpy()
@@ -121,14 +146,19 @@ def retune_many(layouts, tol: float = 1e-3, consts=None, k: int = 3):
     for lay in layouts:
         w = box_side(host[off:off + lay.n])
         off += lay.n
-        cur = lay.params.n_int
-        if lay.params.k_mode == 0:
-            out.append(cur)
+        cur = lay.params
+        if cur.k_mode == 0:
+            out.append(0)
             continue
-        new = max(cur, final_n_int(w, tol, k, consts))
-        if new != cur:
-            lay.set_params(T.TfdpParams(**{**lay.params.as_dict(), "n_int": new}))
-        out.append(new)
+        k_mode, ni = final_choice(lay.n, w, tol, consts)
+        if k_mode == 0 and allow_exact:
+            lay.set_params(T.TfdpParams(**{**cur.as_dict(), "k_mode": 0}))
+            out.append(0)
+            continue
+        ni = max(cur.n_int, ni if ni is not None else final_n_int(w, tol, 3, consts))
+        if ni != cur.n_int:
+            lay.set_params(T.TfdpParams(**{**cur.as_dict(), "n_int": ni}))
+        out.append(ni)
     return out
 
 

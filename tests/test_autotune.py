@@ -21,7 +21,7 @@ def test_size_rule_passes_through_workload_grids():
 def test_final_grid_meets_model_tolerance():
     for w in (5.0, 40.0, 120.0):
         for tol in (1e-2, 1e-3, 1e-4):
-            m = 1.2
+            m = 1.4
             ni = autotune.final_n_int(w, tol, margin=m, hi=10 ** 6)
             # the widened box meets the tolerance, one interval fewer would not
             assert autotune.DEFAULT_C[3] * (m * w / ni) ** 3 <= tol * (1 + 1e-9)
@@ -54,3 +54,20 @@ def test_error_model_against_oracle(index):
     fr = ot.repulsion_ibfft_stable(x, 2.0, ni, 3)
     err = np.linalg.norm(fr - ex) / np.linalg.norm(ex)
     assert err <= tol, (g.n, ni, err)
+
+
+def test_final_choice_prefers_exact_when_cheaper():
+    # a few thousand nodes in a wide box: a 1e-3 grid is far costlier than n^2
+    assert autotune.final_choice(5000, 60.0)[0] == 0
+    # a million nodes: the grid
+    k_mode, ni = autotune.final_choice(1_000_000, 300.0)
+    assert k_mode == -1 and ni == autotune.MAX_N_INT_K3
+    assert autotune.fft_length(64, 1) == 128 and autotune.fft_length(341, 3) == 2048
+
+
+def test_start_params():
+    assert autotune.start_params(500) == (0, 8)
+    k_mode, ni = autotune.start_params(2000)
+    assert k_mode == -1 and ni == 64  # size rule 80 rounded to the FFT-friendly 64
+    assert autotune.start_params(1_000_000) == (-1, 256)
+    assert autotune.fft_rounded(72) == 64 and autotune.fft_rounded(88) == 88
