@@ -84,16 +84,18 @@ def attractive_magnitude(d, beta):
     return d + beta * t_force(d, 1.0)
 
 
-def kernel(d2, gamma):
-    """The kernel of Eq.12 as a function of the squared distance."""
-    return (1.0 + np.asarray(d2, dtype=np.float64)) ** (-gamma)
+def kernel(d2, gamma, tau=1.0):
+    """The kernel of Eq.12 as a function of the squared distance; with tau
+    the generalised t-force of Eq.3 (the paper's model has tau = 1):
+    (1 + tau d^2)^-gamma."""
+    return (1.0 + tau * np.asarray(d2, dtype=np.float64)) ** (-gamma)
 
 
 # ---------------------------------------------------------------------------
 # Exact sums
 # ---------------------------------------------------------------------------
 
-def repulsion_exact(pos, gamma, rows=None, block=2048):
+def repulsion_exact(pos, gamma, rows=None, block=2048, tau=1.0):
     """Exact all-pairs repulsion, Eq.11: F_i = sum_j K_ij (x_i - x_j).
 
     ``rows`` selects the nodes i to evaluate (all by default); every j is
@@ -106,18 +108,21 @@ def repulsion_exact(pos, gamma, rows=None, block=2048):
         sel = idx[b0:b0 + block]
         diff = x[sel, None, :] - x[None, :, :]
         d2 = diff[..., 0] ** 2 + diff[..., 1] ** 2
-        k = kernel(d2, gamma)
+        k = kernel(d2, gamma, tau)
         out[b0:b0 + block, 0] = (k * diff[..., 0]).sum(axis=1)
         out[b0:b0 + block, 1] = (k * diff[..., 1]).sum(axis=1)
     return out
 
 
-def attraction(pos, row_ptr, col_idx, alpha, beta, rows=None):
+def attraction(pos, row_ptr, col_idx, alpha, beta, rows=None, tau=1.0, weights=None):
     """Attraction along edges (Eq.6, weighted by alpha as in Eq.7), as a
     motion towards the neighbours:
         F^a_i = -alpha * sum_{j in N(i)} (1 + beta / (1 + d_ij^2)) (x_i - x_j).
     (|Delta| + beta |Delta| / (1 + |Delta|^2)) * Delta / |Delta| simplifies to
-    the factor above, so no square root is needed.)
+    the factor above, so no square root is needed.) With tau the attractive
+    t-force is the generalised one of Eq.3 (1 + tau d^2 in the denominator);
+    with per-node ``weights`` a (local refinement, Sec. 5) the term of edge
+    (i, j) is scaled by (a_i + a_j) / 2, the same for both ends.
     """
     x = np.asarray(pos, dtype=np.float64)
     rp = np.asarray(row_ptr, dtype=np.int64)
@@ -129,7 +134,11 @@ def attraction(pos, row_ptr, col_idx, alpha, beta, rows=None):
         src = np.repeat(np.arange(n), np.diff(rp))
         diff = x[src] - x[ci]
         d2 = diff[:, 0] ** 2 + diff[:, 1] ** 2
-        f = (1.0 + beta / (1.0 + d2))[:, None] * diff
+        fac = 1.0 + beta / (1.0 + tau * d2)
+        if weights is not None:
+            a = np.asarray(weights, dtype=np.float64)
+            fac = fac * 0.5 * (a[src] + a[ci])
+        f = fac[:, None] * diff
         out[:, 0] = np.bincount(src, weights=f[:, 0], minlength=n)
         out[:, 1] = np.bincount(src, weights=f[:, 1], minlength=n)
     else:
@@ -137,7 +146,11 @@ def attraction(pos, row_ptr, col_idx, alpha, beta, rows=None):
             nb = ci[rp[i]:rp[i + 1]]
             diff = x[i] - x[nb]
             d2 = diff[:, 0] ** 2 + diff[:, 1] ** 2
-            out[o] = ((1.0 + beta / (1.0 + d2))[:, None] * diff).sum(axis=0)
+            fac = 1.0 + beta / (1.0 + tau * d2)
+            if weights is not None:
+                a = np.asarray(weights, dtype=np.float64)
+                fac = fac * 0.5 * (a[i] + a[nb])
+            out[o] = (fac[:, None] * diff).sum(axis=0)
     return -alpha * out
 
 
@@ -238,14 +251,14 @@ class Interp:
         return acc
 
 
-def kernel_tables(m, s, gamma):
+def kernel_tables(m, s, gamma, tau=1.0):
     """Kernel on the node offsets (a, b), a, b in (-M, M), as arrays indexed
-    [b + M - 1, a + M - 1]: K = (1 + s^2 (a^2 + b^2))^-gamma, and the two
+    [b + M - 1, a + M - 1]: K = (1 + tau s^2 (a^2 + b^2))^-gamma, and the two
     tables of the displacement-weighted kernel H_x = K s a, H_y = K s b."""
     off = np.arange(-(m - 1), m, dtype=np.float64)
     a = off[None, :]
     b = off[:, None]
-    k = (1.0 + s * s * (a * a + b * b)) ** (-gamma)
+    k = kernel(s * s * (a * a + b * b), gamma, tau)
     return k, k * s * a, k * s * b
 
 
@@ -288,14 +301,14 @@ def convolve_direct(grids, table):
     return (flat @ op.T).reshape(grids.shape)
 
 
-def repulsion_ibfft_paper(pos, gamma, n_int, k, box=None, direct=False):
+def repulsion_ibfft_paper(pos, gamma, n_int, k, box=None, direct=False, tau=1.0):
     """Interpolated repulsion in the paper's form (Eq.13-15): three kernel
     sums psi_v with charges v in {1, x, y}, then
     F_x(i) = x_i psi_1(i) - psi_x(i), F_y(i) = y_i psi_1(i) - psi_y(i)."""
     it = Interp(pos, n_int, k, box)
     x = it.pos
     q = it.spread([np.ones(x.shape[0]), x[:, 0], x[:, 1]])
-    kt, _, _ = kernel_tables(it.m, it.s, gamma)
+    kt, _, _ = kernel_tables(it.m, it.s, gamma, tau)
     phi = convolve_direct(q, kt) if direct else convolve_fft(q, kt)
     psi1 = it.gather(phi, lambda v, dx, dy: v[0])
     psix = it.gather(phi, lambda v, dx, dy: v[1])
@@ -303,7 +316,7 @@ def repulsion_ibfft_paper(pos, gamma, n_int, k, box=None, direct=False):
     return np.stack([x[:, 0] * psi1 - psix, x[:, 1] * psi1 - psiy], axis=1)
 
 
-def repulsion_ibfft_stable(pos, gamma, n_int, k, box=None, direct=False):
+def repulsion_ibfft_stable(pos, gamma, n_int, k, box=None, direct=False, tau=1.0):
     """Interpolated repulsion in offset form: the same algebra as Eq.13-15
     with every position written relative to the grid node it is spread to or
     gathered from, x = y_g + delta. Charges {1, delta_x, delta_y};
@@ -315,7 +328,7 @@ def repulsion_ibfft_stable(pos, gamma, n_int, k, box=None, direct=False):
     it = Interp(pos, n_int, k, box)
     n = it.pos.shape[0]
     q = it.spread([np.ones(n), lambda dx, dy: dx, lambda dx, dy: dy])
-    kt, hx, hy = kernel_tables(it.m, it.s, gamma)
+    kt, hx, hy = kernel_tables(it.m, it.s, gamma, tau)
     conv = convolve_direct if direct else convolve_fft
     k_q = conv(q, kt)                  # [K*q1, K*qdx, K*qdy]
     hx_q1 = conv(q[0:1], hx)[0]
@@ -337,7 +350,7 @@ class Params:
     """Model and schedule parameters (defaults of Sec. 3.3)."""
 
     def __init__(self, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, gamma=DEFAULT_GAMMA,
-                 rep_weight=1.0, n_int=64, k_mode=-1, total_iters=300, t0=0.0):
+                 rep_weight=1.0, n_int=64, k_mode=-1, total_iters=300, t0=0.0, tau=1.0):
         self.alpha = float(alpha)
         self.beta = float(beta)
         self.gamma = float(gamma)
@@ -346,6 +359,7 @@ class Params:
         self.k_mode = int(k_mode)
         self.total_iters = int(total_iters)
         self.t0 = float(t0)
+        self.tau = float(tau)
 
 
 def k_for_iteration(t, total):
@@ -368,16 +382,21 @@ def step_cap(t, total, t0):
     return t0 * (1.0 - t / total)
 
 
-def forces(pos, row_ptr, col_idx, params, k):
+def forces(pos, row_ptr, col_idx, params, k, rep_w=None, att_w=None):
     """Repulsion, attraction and displacement D = w_r F^r + F^a (Eq.7 as a
     motion). k = 0 evaluates the repulsion exactly, k >= 1 by the
-    interpolation scheme (offset form)."""
+    interpolation scheme (offset form). Local refinement (Sec. 5): per-node
+    weights r (``rep_w``) scale each node's repulsion in D,
+    D_i = w_r r_i F^r_i + F^a_i, and a (``att_w``) the attraction of its
+    edges (see attraction); F^r is returned unweighted."""
+    tau = getattr(params, "tau", 1.0)
     if k == 0:
-        fr = repulsion_exact(pos, params.gamma)
+        fr = repulsion_exact(pos, params.gamma, tau=tau)
     else:
-        fr = repulsion_ibfft_stable(pos, params.gamma, params.n_int, k)
-    fa = attraction(pos, row_ptr, col_idx, params.alpha, params.beta)
-    return fr, fa, params.rep_weight * fr + fa
+        fr = repulsion_ibfft_stable(pos, params.gamma, params.n_int, k, tau=tau)
+    fa = attraction(pos, row_ptr, col_idx, params.alpha, params.beta, tau=tau, weights=att_w)
+    r = 1.0 if rep_w is None else np.asarray(rep_w, dtype=np.float64)[:, None]
+    return fr, fa, params.rep_weight * r * fr + fa
 
 
 def capped_move(pos, disp, cap):
@@ -392,7 +411,7 @@ def capped_move(pos, disp, cap):
 
 
 def layout(pos0, row_ptr, col_idx, params, iters=None, t_start=0,
-           round_fp32=False, callback=None):
+           round_fp32=False, callback=None, rep_w=None, att_w=None):
     """Run the iteration loop: at each t pick k (fixed or scheduled),
     evaluate the forces at the current positions, move every node
     synchronously. Returns the final positions (float64; rounded to float32
@@ -404,7 +423,7 @@ def layout(pos0, row_ptr, col_idx, params, iters=None, t_start=0,
     iters = total - t_start if iters is None else iters
     for t in range(t_start, t_start + iters):
         k = params.k_mode if params.k_mode >= 0 else k_for_iteration(t, total)
-        _, _, disp = forces(x, row_ptr, col_idx, params, k)
+        _, _, disp = forces(x, row_ptr, col_idx, params, k, rep_w, att_w)
         x = capped_move(x, disp, step_cap(t, total, t0))
         if round_fp32:
             x = x.astype(np.float32).astype(np.float64)

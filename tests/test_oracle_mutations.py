@@ -18,8 +18,8 @@ def fails(fn, *args):
 def test_flipped_hx_sign_is_caught(monkeypatch):
     orig = ot.kernel_tables
 
-    def bad(m, s, gamma):
-        k, hx, hy = orig(m, s, gamma)
+    def bad(m, s, gamma, tau=1.0):
+        k, hx, hy = orig(m, s, gamma, tau)
         return k, -hx, hy
     monkeypatch.setattr(ot, "kernel_tables", bad)
     assert fails(pins.test_on_grid_points_are_exact, 2, "stable")
@@ -28,8 +28,8 @@ def test_flipped_hx_sign_is_caught(monkeypatch):
 def test_transposed_hy_is_caught(monkeypatch):
     orig = ot.kernel_tables
 
-    def bad(m, s, gamma):
-        k, hx, hy = orig(m, s, gamma)
+    def bad(m, s, gamma, tau=1.0):
+        k, hx, hy = orig(m, s, gamma, tau)
         return k, hx, hy.T
     monkeypatch.setattr(ot, "kernel_tables", bad)
     assert fails(pins.test_on_grid_points_are_exact, 1, "stable")
@@ -41,7 +41,7 @@ def test_wrong_node_placement_is_caught(monkeypatch):
 
 
 def test_dropped_spring_term_is_caught(monkeypatch):
-    def bad(pos, row_ptr, col_idx, alpha, beta, rows=None):
+    def bad(pos, row_ptr, col_idx, alpha, beta, rows=None, tau=1.0, weights=None):
         x = np.asarray(pos, dtype=np.float64)
         n = x.shape[0]
         src = np.repeat(np.arange(n), np.diff(row_ptr))
@@ -54,7 +54,7 @@ def test_dropped_spring_term_is_caught(monkeypatch):
 
 
 def test_wrong_exponent_is_caught(monkeypatch):
-    monkeypatch.setattr(ot, "kernel", lambda d2, gamma: (1.0 + np.asarray(d2)) ** (-(gamma - 1)))
+    monkeypatch.setattr(ot, "kernel", lambda d2, gamma, tau=1.0: (1.0 + tau * np.asarray(d2)) ** (-(gamma - 1)))
     assert fails(pins.test_three_points_hand_computed)
     assert fails(pins.test_forces_are_minus_energy_gradient, 2.0)
 
@@ -83,3 +83,21 @@ def test_missing_gather_offset_term_is_caught(monkeypatch):
 def test_wrong_k_schedule_is_caught(monkeypatch):
     monkeypatch.setattr(ot, "k_for_iteration", lambda t, total: 1 if t < 0.9 * total else 3)
     assert fails(pins.test_k_schedule)
+
+
+def test_kernel_tables_ignoring_tau_are_caught(monkeypatch):
+    orig = ot.kernel_tables
+    monkeypatch.setattr(ot, "kernel_tables", lambda m, s, gamma, tau=1.0: orig(m, s, gamma))
+    assert fails(pins.test_tau_is_a_change_of_length_scale, 1)
+
+
+def test_one_sided_edge_weights_are_caught(monkeypatch):
+    orig = ot.attraction
+
+    def bad(pos, row_ptr, col_idx, alpha, beta, rows=None, tau=1.0, weights=None):
+        if weights is None:
+            return orig(pos, row_ptr, col_idx, alpha, beta, rows, tau)
+        return orig(pos, row_ptr, col_idx, alpha, beta, rows, tau) * np.asarray(weights)[:, None]
+    monkeypatch.setattr(ot, "attraction", bad)
+    assert fails(pins.test_local_refinement_two_nodes_closed_form)
+    assert fails(pins.test_generalised_forces_are_minus_energy_gradient, 1.7, True)

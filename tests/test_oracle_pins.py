@@ -449,3 +449,84 @@ def test_np_known_case():
     # nodes 2,3,4: ring {0}, 1-NN {0} -> 1; node 5: ring {1}, 1-NN {1} -> 1
     assert abs(np1 - (1 + 1 / 3 + 1 + 1 + 1 + 1) / 6) < 1e-15
     assert om.relative_error(0.9, 1.0) == pytest.approx(-0.1)
+
+
+# --------------------------------------------------------------- generalised t-force and local refinement
+
+def energy_general(x, edges, alpha, beta, gamma, tau, a=None):
+    """Energy of the generalised model (Eq.3 with tau) with per-edge weights
+    w_ij = (a_i + a_j) / 2, written independently of the oracle:
+    sum_{i<j} (1 + tau d^2)^(1-gamma) / (2 tau (gamma - 1))
+    + alpha sum_edges w_ij (d^2 / 2 + beta / (2 tau) ln(1 + tau d^2))."""
+    n = x.shape[0]
+    e = 0.0
+    for i in range(n):
+        for j in range(i + 1, n):
+            d2 = float(((x[i] - x[j]) ** 2).sum())
+            e += (1 + tau * d2) ** (1 - gamma) / (2 * tau * (gamma - 1))
+    for i, j in edges:
+        d2 = float(((x[i] - x[j]) ** 2).sum())
+        w = 1.0 if a is None else 0.5 * (a[i] + a[j])
+        e += alpha * w * (d2 / 2 + beta / (2 * tau) * math.log1p(tau * d2))
+    return e
+
+
+@pytest.mark.parametrize("tau,weighted", [(0.3, False), (2.5, False), (1.7, True)])
+def test_generalised_forces_are_minus_energy_gradient(tau, weighted):
+    rng = np.random.default_rng(8)
+    n = 7
+    x = rng.normal(size=(n, 2)) * 1.1
+    edges = [(0, 1), (1, 2), (2, 3), (0, 4), (4, 5), (5, 6), (6, 1)]
+    rp, ci = csr_of(n, edges)
+    a = rng.uniform(0.5, 3.0, size=n) if weighted else None
+    p = ot.Params(alpha=0.11, beta=4.0, gamma=2.5, tau=tau)
+    _, _, disp = ot.forces(x, rp, ci, p, 0, att_w=a)
+    h = 1e-6
+    grad = np.zeros_like(x)
+    for i in range(n):
+        for c in range(2):
+            xp = x.copy()
+            xm = x.copy()
+            xp[i, c] += h
+            xm[i, c] -= h
+            grad[i, c] = (energy_general(xp, edges, 0.11, 4.0, 2.5, tau, a)
+                          - energy_general(xm, edges, 0.11, 4.0, 2.5, tau, a)) / (2 * h)
+    assert np.allclose(disp, -grad, atol=1e-7, rtol=1e-6)
+
+
+@pytest.mark.parametrize("k", [0, 1, 3])
+def test_tau_is_a_change_of_length_scale(k):
+    """(1 + tau d^2) = (1 + |sqrt(tau) x_i - sqrt(tau) x_j|^2): every force of
+    the generalised model at x equals the tau = 1 force at sqrt(tau) x
+    divided by sqrt(tau) (the grid scales with the box, so this holds for the
+    interpolated repulsion too)."""
+    rng = np.random.default_rng(9)
+    x = rng.uniform(-4, 4, size=(150, 2))
+    rp, ci = csr_of(150, [(i, (11 * i + 5) % 150) for i in range(150) if (11 * i + 5) % 150 != i])
+    tau = 3.7
+    pt = ot.Params(n_int=16, tau=tau)
+    p1 = ot.Params(n_int=16)
+    got = ot.forces(x, rp, ci, pt, k)
+    ref = ot.forces(math.sqrt(tau) * x, rp, ci, p1, k)
+    for g, r in zip(got, ref):
+        assert rel_l2(g, r / math.sqrt(tau)) < 1e-11
+
+
+def test_local_refinement_two_nodes_closed_form():
+    """Two connected nodes at distance d on the x axis with refinement weights
+    r = (r0, r1), a = (a0, a1): D_0 = -w_r r0 d (1 + tau d^2)^-gamma e_x
+    + alpha (a0 + a1)/2 (1 + beta / (1 + tau d^2)) d e_x."""
+    d, tau, gamma, alpha, beta, w_r = 1.3, 0.8, 2.2, 0.07, 6.0, 1.5
+    x = np.array([[0.0, 0.0], [d, 0.0]])
+    rp, ci = csr_of(2, [(0, 1)])
+    r = np.array([2.0, 0.5])
+    a = np.array([3.0, 1.0])
+    p = ot.Params(alpha=alpha, beta=beta, gamma=gamma, rep_weight=w_r, tau=tau)
+    _, fa, disp = ot.forces(x, rp, ci, p, 0, rep_w=r, att_w=a)
+    rep0 = -d * (1 + tau * d * d) ** (-gamma)
+    att0 = alpha * 2.0 * (1 + beta / (1 + tau * d * d)) * d
+    assert disp[0, 0] == pytest.approx(w_r * 2.0 * rep0 + att0, rel=1e-14)
+    assert disp[1, 0] == pytest.approx(-w_r * 0.5 * rep0 - att0, rel=1e-14)
+    assert disp[0, 1] == 0.0 and disp[1, 1] == 0.0
+    # symmetric edge weights keep Newton's third law for the attraction
+    assert fa[0, 0] == pytest.approx(-fa[1, 0], rel=1e-15)
