@@ -78,18 +78,22 @@ typedef struct tfdp_params {
     int32_t k_mode;      /* 0: exact O(n^2) repulsion; 1, 2, 3: fixed k; -1: k schedule */
     int32_t total_iters; /* T of the k schedule and the cooling, >= 1 */
     float t0;            /* initial step cap; <= 0 selects max(1, sqrt(n)/10) */
+    float tau;           /* length scale of both t-forces, > 0, default 1: (1 + tau d^2) in
+                            place of (1 + d^2) (the generalised t-force of Sec. 3.2, Eq.3; the
+                            paper's model has tau = 1) */
 } tfdp_params;
 
 typedef struct tfdp_layout tfdp_layout; /* opaque handle (host memory) */
 
 /* Fill *p with the defaults: alpha 0.1, beta 8, gamma 2 (Sec. 3.3),
- * rep_weight 1, n_int 64, k_mode -1, total_iters 300, t0 0 (automatic). */
+ * rep_weight 1, n_int 64, k_mode -1, total_iters 300, t0 0 (automatic),
+ * tau 1. */
 void tfdp_params_default(tfdp_params* p);
 
 /* Host-only check of parameters and sizes; touches no device.
  * TFDP_ERR_INVALID_ARG: p NULL, n < 1, nnz < 0, gamma <= 1 (Eq.10), alpha,
  * beta or rep_weight negative or not finite, n_int < 1, k_mode outside
- * {-1,0,1,2,3}, total_iters < 1, t0 not finite.
+ * {-1,0,1,2,3}, total_iters < 1, t0 not finite, tau not finite or <= 0.
  * TFDP_ERR_UNSUPPORTED: N_int * k_max > 1024 (FFT length above 2048), where
  * k_max is k_mode for k_mode 1 or 2 and 3 otherwise.
  * Returns TFDP_OK with a warning in tfdp_last_error() when
@@ -153,6 +157,19 @@ tfdp_status tfdp_layout_forces(tfdp_layout* h, const float* d_pos_in, int32_t k,
  * later work (one stream, or synchronised). Positions and the counter are
  * kept. Takes effect for work enqueued afterwards. */
 tfdp_status tfdp_layout_set_params(tfdp_layout* h, const tfdp_params* p);
+
+/* Local refinement (Sec. 5): per-node weights that make chosen nodes pull
+ * their neighbours closer and push the others away.
+ *   d_rep_w  float32[n] (device) or NULL: node i's repulsion enters its
+ *            motion as rep_weight * d_rep_w[i] * F^r_i
+ *   d_att_w  float32[n] (device) or NULL: the attraction term of edge (i, j)
+ *            is scaled by (d_att_w[i] + d_att_w[j]) / 2 (the same for both
+ *            ends, so the attraction stays symmetric)
+ * NULL restores weight 1. The arrays stay owned by the caller and are read
+ * by every later step and forces call until replaced; values should be
+ * finite and >= 0 (not checked). tfdp_layout_forces reports F^r unweighted,
+ * F^a and D weighted. Takes effect for work enqueued afterwards. */
+tfdp_status tfdp_layout_set_node_weights(tfdp_layout* h, const float* d_rep_w, const float* d_att_w);
 
 /* Read / set the iteration counter t (checkpoint and resume: positions plus t
  * are the whole state). */

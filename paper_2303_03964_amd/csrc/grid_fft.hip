@@ -232,7 +232,8 @@ static void allow_big_lds(Kern k) {
 // K, minus its odd part the row spectrum of H_x divided by i.
 // bid < max_chunks: chunk block; otherwise lb = logical kernel-row block.
 template <int K, int LOGL>
-__device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float gamma, int nw, int bid, int lb) {
+__device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float gamma, float tau, int nw, int bid,
+                                            int lb) {
     extern __shared__ float4 smem4[];
     const int M = g.m;
     const int lane = threadIdx.x & 63;
@@ -316,7 +317,7 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
         if (f < RBK && r < L) {
             const int bt = signed_offset(r, M, L), at = signed_offset(a, M, L);
             if (bt != INT_MIN && at != INT_MIN) {
-                const double d2 = s * s * ((double)at * at + (double)bt * bt);
+                const double d2 = (double)tau * (s * s * ((double)at * at + (double)bt * bt));
                 const double kk = (gamma == 2.0f) ? 1.0 / ((1.0 + d2) * (1.0 + d2)) : pow(1.0 + d2, -(double)gamma);
                 v = make_float2((float)kk, (float)(kk * s * (double)at));
             }
@@ -338,14 +339,14 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
 }
 
 template <int K, int LOGL>
-__global__ __launch_bounds__(512) void k_spread(Bufs b, Geom g, float gamma, int nw, int nkb) {
+__global__ __launch_bounds__(512) void k_spread(Bufs b, Geom g, float gamma, float tau, int nw, int nkb) {
     const int bid = blockIdx.x;
     int lb = -1;
     if (bid >= b.max_chunks) {
         lb = xcd_pair_block(bid - b.max_chunks, nkb);
         if (lb < 0) return;
     }
-    spread_body<K, LOGL>(b, g, gamma, nw, bid, lb);
+    spread_body<K, LOGL>(b, g, gamma, tau, nw, bid, lb);
 }
 
 // Batched: map entry {member, block}; blocks past the member's max_chunks
@@ -354,7 +355,7 @@ template <int K, int LOGL>
 __global__ __launch_bounds__(512) void kb_spread(const Member* __restrict__ mem, const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
-    spread_body<K, LOGL>(m.b, m.g, m.a.gamma, m.nw, e.y, e.y - m.b.max_chunks);
+    spread_body<K, LOGL>(m.b, m.g, m.a.gamma, m.a.tau, m.nw, e.y, e.y - m.b.max_chunks);
 }
 
 Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
@@ -371,12 +372,12 @@ Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
 }
 
 template <int K, int LOGL>
-static void launch_spread_t(const Bufs& b, const Geom& g, float gamma, hipStream_t s) {
+static void launch_spread_t(const Bufs& b, const Geom& g, float gamma, float tau, hipStream_t s) {
     static_assert(RowTile<LOGL>::RBK == 8, "spread_dims assumes 8 kernel rows per block");
     int nw, nkb;
     const Dims d = spread_dims(b, g, &nw, &nkb);
     hipLaunchKernelGGL((k_spread<K, LOGL>), dim3(b.max_chunks + xcd_pair_grid(nkb)), dim3(d.block), d.lds, s, b, g,
-                       gamma, nw, nkb);
+                       gamma, tau, nw, nkb);
 }
 
 template <int K, int LOGL>
@@ -408,22 +409,22 @@ void launch_b_spread(int k, int logL, int nw, const Member* mem, const int2* map
 }
 
 template <int K>
-static void launch_spread_k(const Bufs& b, const Geom& g, float gamma, hipStream_t s) {
+static void launch_spread_k(const Bufs& b, const Geom& g, float gamma, float tau, hipStream_t s) {
     switch (g.logL) {
-        case 6: launch_spread_t<K, 6>(b, g, gamma, s); break;
-        case 7: launch_spread_t<K, 7>(b, g, gamma, s); break;
-        case 8: launch_spread_t<K, 8>(b, g, gamma, s); break;
-        case 9: launch_spread_t<K, 9>(b, g, gamma, s); break;
-        case 10: launch_spread_t<K, 10>(b, g, gamma, s); break;
-        default: launch_spread_t<K, 11>(b, g, gamma, s); break;
+        case 6: launch_spread_t<K, 6>(b, g, gamma, tau, s); break;
+        case 7: launch_spread_t<K, 7>(b, g, gamma, tau, s); break;
+        case 8: launch_spread_t<K, 8>(b, g, gamma, tau, s); break;
+        case 9: launch_spread_t<K, 9>(b, g, gamma, tau, s); break;
+        case 10: launch_spread_t<K, 10>(b, g, gamma, tau, s); break;
+        default: launch_spread_t<K, 11>(b, g, gamma, tau, s); break;
     }
 }
 
-void launch_spread(const Bufs& b, const Geom& g, float gamma, hipStream_t s) {
+void launch_spread(const Bufs& b, const Geom& g, float gamma, float tau, hipStream_t s) {
     switch (g.k) {
-        case 1: launch_spread_k<1>(b, g, gamma, s); break;
-        case 2: launch_spread_k<2>(b, g, gamma, s); break;
-        default: launch_spread_k<3>(b, g, gamma, s); break;
+        case 1: launch_spread_k<1>(b, g, gamma, tau, s); break;
+        case 2: launch_spread_k<2>(b, g, gamma, tau, s); break;
+        default: launch_spread_k<3>(b, g, gamma, tau, s); break;
     }
 }
 

@@ -90,11 +90,13 @@ __device__ __forceinline__ void wave_segmented_sum(float& x, float& y, int key, 
     seg_step_lane(x, y, key, lane, lane >= 32 ? 31 : lane);
 }
 
-// Attraction term of one CSR entry: (1 + beta / (1 + d^2)) (x_i - x_j).
-__device__ __forceinline__ void edge_term(float px, float py, float2 q, float beta, float& ax, float& ay) {
+// Attraction term of one CSR entry: (1 + beta / (1 + tau d^2)) (x_i - x_j)
+// (tau = 1: Eq.6; other tau: the generalised t-force of Eq.3).
+__device__ __forceinline__ void edge_term(float px, float py, float2 q, float beta, float tau, float& ax,
+                                          float& ay) {
     const float dx = px - q.x;
     const float dy = py - q.y;
-    const float f = 1.f + beta / (1.f + (dx * dx + dy * dy));
+    const float f = 1.f + beta / (1.f + tau * (dx * dx + dy * dy));
     ax = f * dx;
     ay = f * dy;
 }
@@ -108,8 +110,10 @@ __device__ __forceinline__ void node_output(int i, float2 p, float frx, float fr
                                             float& ymin, float& xmax, float& ymax) {
     const float fax = -a.alpha * sax;
     const float fay = -a.alpha * say;
-    const float dxt = a.rep_weight * frx + fax;
-    const float dyt = a.rep_weight * fry + fay;
+    // local refinement (Sec. 5): node i's repulsion scaled by rep_w[i]
+    const float wr = a.rep_w ? a.rep_weight * a.rep_w[i] : a.rep_weight;
+    const float dxt = wr * frx + fax;
+    const float dyt = wr * fry + fay;
     if (pos_out == nullptr) {
         if (f_rep) f_rep[i] = make_float2(frx, fry);
         if (f_att) f_att[i] = make_float2(fax, fay);
@@ -146,6 +150,7 @@ __device__ __forceinline__ void edges_body(const float2* __restrict__ pos, float
     __shared__ float accy[kThreads];
     __shared__ float hred[2][kThreads / 64];
     __shared__ float2 pown[kThreads];
+    __shared__ float aown[kThreads];
     const int* __restrict__ row_ptr = es.rp;
     const int* __restrict__ col_idx = es.col;
     const int w = threadIdx.x >> 6;
@@ -165,6 +170,8 @@ __device__ __forceinline__ void edges_body(const float2* __restrict__ pos, float
         const int row = s0.x;
         const int e1 = row_ptr[row + 1];
         const float2 pr = pos[row];
+        const float* __restrict__ aw = a.att_w;
+        const float ai = aw ? aw[row] : 0.f;
         float sx = 0.f, sy = 0.f;
         for (int e = row_ptr[row] + threadIdx.x; e < e1; e += 4 * kThreads) {
             // past the row's end the row itself stands in: its term is zero
@@ -175,12 +182,17 @@ __device__ __forceinline__ void edges_body(const float2* __restrict__ pos, float
             float2 q[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) q[u] = pos[c[u]];
+            float wgt[4] = {1.f, 1.f, 1.f, 1.f};
+            if (aw) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) wgt[u] = 0.5f * (ai + aw[c[u]]);
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 float ax, ay;
-                edge_term(pr.x, pr.y, q[u], a.beta, ax, ay);
-                sx += ax;
-                sy += ay;
+                edge_term(pr.x, pr.y, q[u], a.beta, a.tau, ax, ay);
+                sx += wgt[u] * ax;
+                sy += wgt[u] * ay;
             }
         }
         for (int off = 32; off > 0; off >>= 1) {
@@ -208,6 +220,9 @@ __device__ __forceinline__ void edges_body(const float2* __restrict__ pos, float
             float2* pw = reinterpret_cast<float2*>(pown) + w * 64;
             const float2 po = lane < nr ? pos[r0 + lane] : make_float2(0.f, 0.f);
             pw[lane] = po;
+            const float* __restrict__ aw = a.att_w;
+            float* awn = aown + w * 64;
+            if (aw) awn[lane] = lane < nr ? aw[r0 + lane] : 0.f;
             const int eb = row_ptr[r0];
             const int ee = row_ptr[r0 + nr];
             float* ax_w = accx + w * 64;
@@ -225,6 +240,12 @@ __device__ __forceinline__ void edges_body(const float2* __restrict__ pos, float
             float2 q[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) q[r] = pos[ent[r] & 0x3ffffffu];
+            // local refinement weights of the neighbours (Sec. 5), when set
+            float aj[R];
+            if (aw) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) aj[r] = aw[ent[r] & 0x3ffffffu];
+            }
             // per round: terms of 64 consecutive entries, summed per row by
             // a segmented wave sum; the last lane of each row's run adds the
             // run's sum to the row (one lane per row and round, so plain LDS
@@ -235,7 +256,14 @@ __device__ __forceinline__ void edges_body(const float2* __restrict__ pos, float
                 const bool valid = eb + r * 64 + lane < ee;
                 const int key = valid ? (int)(ent[r] >> 26) : 127;
                 float ax = 0.f, ay = 0.f;
-                if (valid) edge_term(pw[key].x, pw[key].y, q[r], a.beta, ax, ay);
+                if (valid) {
+                    edge_term(pw[key].x, pw[key].y, q[r], a.beta, a.tau, ax, ay);
+                    if (aw) {
+                        const float wgt = 0.5f * (awn[key] + aj[r]);
+                        ax *= wgt;
+                        ay *= wgt;
+                    }
+                }
                 wave_segmented_sum(ax, ay, key, lane);
                 const int knext = __shfl_down(key, 1);
                 if (valid && (lane == 63 || knext != key)) {
@@ -353,6 +381,7 @@ __device__ __forceinline__ void brute_body(const float2* __restrict__ pos, int n
     const bool active = i < n;
     const float2 p = active ? pos[i] : make_float2(0.f, 0.f);
     const bool g2 = a.gamma == 2.0f;
+    const float tau = a.tau;
     float frx = 0.f, fry = 0.f;
     for (int base = 0; base < n; base += kThreads) {
         const int j = base + threadIdx.x;
@@ -363,7 +392,7 @@ __device__ __forceinline__ void brute_body(const float2* __restrict__ pos, int n
             const float2 q = tile[jj];
             const float dx = p.x - q.x;
             const float dy = p.y - q.y;
-            const float u = 1.f + (dx * dx + dy * dy);
+            const float u = 1.f + tau * (dx * dx + dy * dy);
             float kk;
             if (g2) {
                 const float r = 1.f / u;
@@ -380,11 +409,14 @@ __device__ __forceinline__ void brute_body(const float2* __restrict__ pos, int n
     if (active) {
         float sax = 0.f, say = 0.f;
         const int e1 = row_ptr[i + 1];
+        const float* __restrict__ aw = a.att_w;
         for (int e = row_ptr[i]; e < e1; ++e) {
+            const int j = col_idx[e] & 0x3ffffff;
             float ax, ay;
-            edge_term(p.x, p.y, pos[col_idx[e] & 0x3ffffff], a.beta, ax, ay);
-            sax += ax;
-            say += ay;
+            edge_term(p.x, p.y, pos[j], a.beta, tau, ax, ay);
+            const float wgt = aw ? 0.5f * (aw[i] + aw[j]) : 1.f;
+            sax += wgt * ax;
+            say += wgt * ay;
         }
         node_output(i, p, frx, fry, sax, say, a, t, st, pos_out, f_rep, f_att, f_tot, xmin, ymin, xmax, ymax);
     }

@@ -184,7 +184,7 @@ void enqueue_grid(tfdp_layout* h, const float2* pos, const Bufs& b, const Geom& 
     { PhaseTimer pt(h, PH_BIN_COUNT, s); launch_bin_count(pos, b, set, s); }
     { PhaseTimer pt(h, PH_BIN_SCAN, s); launch_bin_scan(b, set ^ 1, s); }
     { PhaseTimer pt(h, PH_BIN_SCATTER, s); launch_bin_scatter(pos, b, s); }
-    { PhaseTimer pt(h, PH_SPREAD, s); launch_spread(b, g, h->p.gamma, s); }
+    { PhaseTimer pt(h, PH_SPREAD, s); launch_spread(b, g, h->p.gamma, h->p.tau, s); }
     { PhaseTimer pt(h, PH_ROWFFT, s); launch_rowfft(b, g, s); }
     { PhaseTimer pt(h, PH_COLCONV, s); launch_colconv(b, g, s); }
     { PhaseTimer pt(h, PH_ROWIFFT, s); launch_rowifft(b, g, s); }
@@ -336,6 +336,7 @@ void tfdp_params_default(tfdp_params* p) {
     p->k_mode = -1;
     p->total_iters = 300;
     p->t0 = 0.0f;
+    p->tau = 1.0f;
 }
 
 tfdp_status tfdp_params_validate(const tfdp_params* p, int32_t n, int64_t nnz) {
@@ -354,6 +355,10 @@ tfdp_status tfdp_params_validate(const tfdp_params* p, int32_t n, int64_t nnz) {
     }
     if (!finite_f(p->gamma) || !(p->gamma > 1.0f)) {
         set_msg("gamma must be > 1 (Eq.10)");
+        return TFDP_ERR_INVALID_ARG;
+    }
+    if (!finite_f(p->tau) || !(p->tau > 0.f)) {
+        set_msg("tau must be finite and > 0 (Eq.3)");
         return TFDP_ERR_INVALID_ARG;
     }
     if (!finite_f(p->alpha) || p->alpha < 0.f || !finite_f(p->beta) || p->beta < 0.f ||
@@ -574,6 +579,19 @@ tfdp_status tfdp_layout_set_params(tfdp_layout* h, const tfdp_params* p) {
         h->tw_pending = true;
     }
     h->p = *p;
+    h->version += 1;
+    drop_graphs(h);
+    return TFDP_OK;
+}
+
+tfdp_status tfdp_layout_set_node_weights(tfdp_layout* h, const float* d_rep_w, const float* d_att_w) {
+    if (!h) {
+        set_msg("invalid handle");
+        return TFDP_ERR_INVALID_ARG;
+    }
+    set_msg("");
+    h->rep_w = d_rep_w;
+    h->att_w = d_att_w;
     h->version += 1;
     drop_graphs(h);
     return TFDP_OK;

@@ -88,6 +88,8 @@ struct tfdp_layout {
     unsigned int version;
     long long slice_nodes;  // column-slice width fixed at init
     bool tw_pending;        // twiddle tables to (re)compute before the next launch
+    const float* rep_w;     // local-refinement weights (caller's device arrays) or null
+    const float* att_w;
 };
 
 namespace tfdp {
@@ -104,6 +106,9 @@ inline ModelArgs model_args(const tfdp_layout* h) {
     a.rep_weight = h->p.rep_weight;
     a.t0 = h->p.t0 > 0.f ? h->p.t0 : std::fmax(1.0f, (float)(std::sqrt((double)h->n) / 10.0));
     a.total_iters = h->p.total_iters;
+    a.tau = h->p.tau;
+    a.rep_w = h->rep_w;
+    a.att_w = h->att_w;
     return a;
 }
 

@@ -81,6 +81,9 @@ struct ModelArgs {
     float alpha, beta, gamma, rep_weight;
     float t0;
     int total_iters;
+    float tau;             // length scale of the t-forces (Eq.3), 1 in the paper's model
+    const float* rep_w;    // per-node repulsion weights (local refinement, Sec. 5) or null
+    const float* att_w;    // per-node attraction weights or null
 };
 
 // One graph of a batched launch: the arguments of its plain launches for one
@@ -112,7 +115,7 @@ void launch_box_reduce(const float2* pos, int n, DevState* st, int set, hipStrea
 void launch_bin_count(const float2* pos, const Bufs& b, int set, hipStream_t s);
 void launch_bin_scan(const Bufs& b, int reset_set, hipStream_t s);
 void launch_bin_scatter(const float2* pos, const Bufs& b, hipStream_t s);
-void launch_spread(const Bufs& b, const Geom& g, float gamma, hipStream_t s);
+void launch_spread(const Bufs& b, const Geom& g, float gamma, float tau, hipStream_t s);
 void launch_rowfft(const Bufs& b, const Geom& g, hipStream_t s);
 void launch_colconv(const Bufs& b, const Geom& g, hipStream_t s);
 void launch_rowifft(const Bufs& b, const Geom& g, hipStream_t s);

@@ -39,6 +39,7 @@ class TfdpParams(ctypes.Structure):
         ("k_mode", c_int32),
         ("total_iters", c_int32),
         ("t0", c_float),
+        ("tau", c_float),
     ]
 
     def as_dict(self):
@@ -61,6 +62,7 @@ _SIGS = {
     "tfdp_layout_step": (c_int32, [c_void_p, c_int32, c_void_p]),
     "tfdp_layout_forces": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "tfdp_layout_set_params": (c_int32, [c_void_p, POINTER(TfdpParams)]),
+    "tfdp_layout_set_node_weights": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "tfdp_layout_get_iter": (c_int32, [c_void_p, POINTER(c_int32)]),
     "tfdp_layout_set_iter": (c_int32, [c_void_p, c_int32]),
     "tfdp_layout_sync_status": (c_int32, [c_void_p, c_void_p]),
@@ -163,6 +165,10 @@ def tfdp_layout_forces(h, pos_in, k, f_rep=None, f_att=None, f_tot=None, stream=
 
 def tfdp_layout_set_params(h, params):
     return _check(load_library().tfdp_layout_set_params(h, ctypes.byref(params)))
+
+
+def tfdp_layout_set_node_weights(h, rep_w=None, att_w=None):
+    return _check(load_library().tfdp_layout_set_node_weights(h, _ptr(rep_w), _ptr(att_w)))
 
 
 def tfdp_layout_get_iter(h) -> int:
@@ -295,6 +301,17 @@ class Layout:
     def set_params(self, params: TfdpParams):
         tfdp_layout_set_params(self.handle, params)
         self.params = params
+
+    def set_node_weights(self, rep_w=None, att_w=None):
+        """Local-refinement weights (float32 [n] device tensors or None);
+        kept referenced here while the handle uses them."""
+        dev = self.pos.device
+        self.rep_w = None if rep_w is None else torch.as_tensor(rep_w, dtype=torch.float32).to(dev).contiguous()
+        self.att_w = None if att_w is None else torch.as_tensor(att_w, dtype=torch.float32).to(dev).contiguous()
+        for w in (self.rep_w, self.att_w):
+            if w is not None and w.numel() != self.n:
+                raise ValueError("weights must have n entries")
+        tfdp_layout_set_node_weights(self.handle, self.rep_w, self.att_w)
 
     @property
     def iteration(self):

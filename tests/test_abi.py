@@ -25,7 +25,7 @@ def test_exports_every_header_function():
 def test_defaults_match_paper():
     p = T.tfdp_params_default()
     assert p.alpha == pytest.approx(0.1) and p.beta == 8.0 and p.gamma == 2.0
-    assert p.rep_weight == 1.0 and p.k_mode == -1 and p.t0 == 0.0
+    assert p.rep_weight == 1.0 and p.k_mode == -1 and p.t0 == 0.0 and p.tau == 1.0
 
 
 @pytest.mark.parametrize("field,value,code", [
@@ -34,6 +34,7 @@ def test_defaults_match_paper():
     ("rep_weight", -2.0, INVALID), ("n_int", 0, INVALID), ("n_int", 1025, INVALID),
     ("k_mode", 4, INVALID), ("k_mode", -2, INVALID), ("total_iters", 0, INVALID),
     ("t0", float("inf"), INVALID), ("n_int", 400, UNSUPPORTED),
+    ("tau", 0.0, INVALID), ("tau", -1.0, INVALID), ("tau", float("nan"), INVALID),
 ])
 def test_validate_rejects(field, value, code):
     p = T.tfdp_params_default(**{field: value})
@@ -103,6 +104,7 @@ def test_null_handle_calls():
     assert lib.tfdp_layout_sync_status(None, None) == INVALID
     assert lib.tfdp_layout_set_profiling(None, 1) == INVALID
     assert lib.tfdp_layout_set_graphs(None, 1) == INVALID
+    assert lib.tfdp_layout_set_node_weights(None, None, None) == INVALID
     lib.tfdp_layout_destroy(None)
 
 
@@ -112,8 +114,27 @@ def test_phase_names():
     assert T.tfdp_phase_name(-1) == "" and T.tfdp_phase_name(999) == ""
 
 
-def test_params_struct_layout():
-    assert ctypes.sizeof(TfdpParams) == 32
+def test_params_struct_layout(tmp_path):
+    """The ctypes mirror has the C struct's size and field offsets (compiled
+    from include/tfdp.h with the host C compiler)."""
+    import os
+    import subprocess
+    assert ctypes.sizeof(TfdpParams) == 36
+    fields = [name for name, _ in TfdpParams._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"tfdp.h\"\nint main(void) {\n"
+                   '  printf("%zu", sizeof(tfdp_params));\n'
+                   + "".join(f'  printf(" %zu", offsetof(tfdp_params, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = tmp_path / "layout"
+    r = subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(root, "include"),
+                        "-I", "/opt/rocm/include", str(src), "-o", str(exe)], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("no host C compiler for the HIP headers: " + r.stderr[-200:])
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(TfdpParams)
+    assert vals[1:] == [getattr(TfdpParams, f).offset for f in fields]
 
 
 def test_batch_host_bookkeeping():

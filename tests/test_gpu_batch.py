@@ -163,3 +163,41 @@ def test_batch_many_uneven_graphs(T, stream):
         g, pos = sg.sbm_batch_member(i)
         members.append((i, autotune.n_int_for_size(g.n), {}))
     run_case(T, stream, [30], total=30, members=members)
+
+
+def test_batch_with_tau_and_refinement_weights(T, stream):
+    """Members with tau != 1 and local-refinement weights, bit-identical to
+    their plain steps (weights and tau reach the batched kernels through the
+    member descriptors)."""
+    import torch
+    with torch.cuda.stream(stream):
+        gs = graphs([0, 1, 3])
+        rng = np.random.default_rng(4)
+        lays = []
+        for q, (g, pos) in enumerate(gs):
+            extra = {"tau": [0.5, 1.0, 2.0][q], "gamma": 2.3}
+            a, b = pair(T, g, pos, 32, 40, extra)
+            if q != 1:
+                rw = torch.as_tensor(rng.uniform(0.5, 2.0, g.n).astype(np.float32))
+                aw = torch.as_tensor(rng.uniform(0.5, 2.0, g.n).astype(np.float32))
+                a.set_node_weights(rw, aw)
+                b.set_node_weights(rw, aw)
+            lays.append((a, b))
+        B = T.Batch(4)
+        for a, _ in lays:
+            B.add(a)
+        B.step(17)
+        for _, b in lays:
+            b.step(17)
+        # weights changed between calls reach the batch
+        w2 = torch.full((lays[1][0].n,), 1.7)
+        lays[1][0].set_node_weights(None, w2)
+        lays[1][1].set_node_weights(None, w2)
+        B.step(23)
+        for _, b in lays:
+            b.step(23)
+        torch.cuda.synchronize()
+        for a, b in lays:
+            assert a.iteration == b.iteration == 40
+            assert torch.equal(a.pos, b.pos)
+        B.close()

@@ -447,3 +447,72 @@ def test_grid_change_keeps_state(T):
     assert rel_l2(fr.cpu().numpy(), ot.repulsion_ibfft_stable(x, 2.0, 96, 3)) <= TOL
     a.close()
     b.close()
+
+
+# ------------------------------------------------------------------ generalised t-force and local refinement
+
+def hub_graph(n=6000, hub_deg=1500, seed=3):
+    """Random graph plus one node of degree hub_deg (a row of the edge pass's
+    heavy path) and a few medium hubs."""
+    rng = np.random.default_rng(seed)
+    e = [(0, j) for j in range(1, hub_deg + 1)]
+    e += [(1, j) for j in range(2000, 2600)]
+    u = rng.integers(0, n, size=4 * n)
+    v = rng.integers(0, n, size=4 * n)
+    e += list(zip(u.tolist(), v.tolist()))
+    return sg.csr_from_edges(n, np.array(e, dtype=np.int64))
+
+
+@pytest.mark.parametrize("tau", [0.35, 2.5])
+@pytest.mark.parametrize("k", [0, 1, 3])
+def test_generalised_tforce_tau(T, tau, k):
+    g = hub_graph()
+    pos = sg.uniform_positions(g.n, 5, -30, 30)
+    n_int = 48
+    say(f"case tau={tau} k={k}")
+    lay = make_layout(T, g, pos, n_int=n_int, tau=tau, gamma=2.5)
+    got = gpu_forces(lay, pos, k)
+    x = pos.astype(np.float64)
+    fr = ot.repulsion_exact(x, 2.5, tau=tau) if k == 0 else ot.repulsion_ibfft_stable(x, 2.5, n_int, k, tau=tau)
+    fa = ot.attraction(x, g.row_ptr, g.col_idx, 0.1, 8.0, tau=tau)
+    errs = [rel_l2(got[0], fr), rel_l2(got[1], fa), rel_l2(got[2], fr + fa)]
+    say(f"  rel L2 rep/att/tot = {errs}")
+    assert max(errs) <= TOL
+    lay.close()
+
+
+@pytest.mark.parametrize("k", [0, 2])
+def test_local_refinement_weights(T, k):
+    import torch
+    g = hub_graph()
+    pos = sg.uniform_positions(g.n, 6, -30, 30)
+    rng = np.random.default_rng(12)
+    rep_w = rng.uniform(0.5, 3.0, size=g.n).astype(np.float32)
+    att_w = rng.uniform(0.2, 4.0, size=g.n).astype(np.float32)
+    p = ot.Params(alpha=0.05, beta=6.0, gamma=2.0, rep_weight=1.5, n_int=48, tau=0.7)
+    lay = make_layout(T, g, pos, n_int=48, alpha=0.05, beta=6.0, rep_weight=1.5, tau=0.7)
+    lay.set_node_weights(torch.as_tensor(rep_w), torch.as_tensor(att_w))
+    got = gpu_forces(lay, pos, k)
+    want = ot.forces(pos.astype(np.float64), g.row_ptr, g.col_idx, p, k,
+                     rep_w=rep_w.astype(np.float64), att_w=att_w.astype(np.float64))
+    errs = [rel_l2(a, b) for a, b in zip(got, want)]
+    say(f"weighted k={k}: rel L2 rep/att/tot = {errs}")
+    assert max(errs) <= TOL
+    # one capped step with weights and tau against the oracle's move
+    lay.iteration = 0
+    lay.set_params(T.tfdp_params_default(n_int=48, alpha=0.05, beta=6.0, rep_weight=1.5, tau=0.7, k_mode=k,
+                                         total_iters=10))
+    lay.pos.copy_(torch.as_tensor(pos))
+    lay.step(1)
+    torch.cuda.synchronize()
+    q = ot.Params(alpha=0.05, beta=6.0, gamma=2.0, rep_weight=1.5, n_int=48, tau=0.7, k_mode=k, total_iters=10)
+    x1 = ot.capped_move(pos.astype(np.float64), want[2], ot.step_cap(0, 10, ot.default_t0(g.n)))
+    move = rel_l2(lay.pos.cpu().numpy() - pos, x1 - pos)
+    say(f"  step move rel L2 = {move}")
+    assert move <= TOL
+    # weights cleared: back to the unweighted model
+    lay.set_node_weights(None, None)
+    got2 = gpu_forces(lay, pos, k)
+    want2 = ot.forces(pos.astype(np.float64), g.row_ptr, g.col_idx, q, k)
+    assert rel_l2(got2[2], want2[2]) <= TOL
+    lay.close()
