@@ -24,6 +24,10 @@ HIP_FLAGS = [
     f"--offload-arch={ARCH}",
     # keep the compiler from emitting packed FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse multiply-adds only inside one source expression: the same code
+    # then rounds the same way in every kernel that inlines it (the batched
+    # kernels reproduce the per-graph ones bit for bit)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-result",
 ]
 
