@@ -74,7 +74,11 @@ typedef struct tfdp_params {
     float beta;          /* weight of the attractive t-force (Eq.6), default 8 */
     float gamma;         /* repulsive t-force exponent (Eq.5), default 2; must be > 1 (Eq.10) */
     float rep_weight;    /* multiplier of the repulsion, default 1 (Sec. 5, global refinement) */
-    int32_t n_int;       /* intervals per box side N_int (Sec. 3.4), 1..1024 */
+    int32_t n_int;       /* intervals per box side N_int (Sec. 3.4), 1..1024; 0: automatic, chosen
+                            every 10 iterations (at counters that are multiples of 10) as
+                            max(50, ceil(W)) for the box side W of the current layout, the rule the
+                            paper cites for t-SNE (Sec. 3.4, "Choices of k"), capped at 1024 / k_max;
+                            the workspace is then sized for the cap */
     int32_t k_mode;      /* 0: exact O(n^2) repulsion; 1, 2, 3: fixed k; -1: k schedule */
     int32_t total_iters; /* T of the k schedule and the cooling, >= 1 */
     float t0;            /* initial step cap; <= 0 selects max(1, sqrt(n)/10) */
@@ -92,7 +96,7 @@ void tfdp_params_default(tfdp_params* p);
 
 /* Host-only check of parameters and sizes; touches no device.
  * TFDP_ERR_INVALID_ARG: p NULL, n < 1, nnz < 0, gamma <= 1 (Eq.10), alpha,
- * beta or rep_weight negative or not finite, n_int < 1, k_mode outside
+ * beta or rep_weight negative or not finite, n_int < 0, k_mode outside
  * {-1,0,1,2,3}, total_iters < 1, t0 not finite, tau not finite or <= 0.
  * TFDP_ERR_UNSUPPORTED: N_int * k_max > 1024 (FFT length above 2048), where
  * k_max is k_mode for k_mode 1 or 2 and 3 otherwise.
@@ -157,6 +161,10 @@ tfdp_status tfdp_layout_forces(tfdp_layout* h, const float* d_pos_in, int32_t k,
  * later work (one stream, or synchronised). Positions and the counter are
  * kept. Takes effect for work enqueued afterwards. */
 tfdp_status tfdp_layout_set_params(tfdp_layout* h, const tfdp_params* p);
+
+/* The handle's current parameters (with the automatic grid: the grid in
+ * use as n_int). */
+tfdp_status tfdp_layout_get_params(const tfdp_layout* h, tfdp_params* out);
 
 /* Local refinement (Sec. 5): per-node weights that make chosen nodes pull
  * their neighbours closer and push the others away.
@@ -230,8 +238,9 @@ typedef struct tfdp_batch tfdp_batch; /* opaque handle (host memory) */
 tfdp_status tfdp_batch_create(tfdp_batch** out, int32_t capacity);
 /* Add / remove a member (host bookkeeping; the device tables are rebuilt at
  * the next step). TFDP_ERR_INVALID_ARG: NULL, already a member (add) or not
- * a member (remove). TFDP_ERR_UNSUPPORTED: batch full, or a handle whose
- * edge pass is split into column slices. */
+ * a member (remove). TFDP_ERR_UNSUPPORTED: batch full, a handle whose edge
+ * pass is split into column slices, or one with the automatic grid
+ * (n_int = 0). */
 tfdp_status tfdp_batch_add(tfdp_batch* b, tfdp_layout* h);
 tfdp_status tfdp_batch_remove(tfdp_batch* b, tfdp_layout* h);
 /* Number of members (0 for NULL). */

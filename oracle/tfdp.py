@@ -362,6 +362,19 @@ class Params:
         self.tau = float(tau)
 
 
+AUTO_GRID_MIN = 50
+AUTO_GRID_CHUNK = 10
+
+
+def auto_n_int(pos, cap):
+    """Automatic grid: one interval per unit of layout length, at least 50,
+    N_int = max(50, ceil(W)) for the side W of the square box (the rule of
+    Linderman et al. that Sec. 3.4 cites for t-SNE), capped at `cap`; chosen
+    every AUTO_GRID_CHUNK iterations (reading of this implementation)."""
+    w = square_box(pos)[2]
+    return int(min(cap, max(AUTO_GRID_MIN, math.ceil(w))))
+
+
 def k_for_iteration(t, total):
     """Dynamic k of Sec. 3.4: 1 for the first 90% of the iterations, 2 for
     the next 5%, 3 for the rest (boundaries rounded down)."""
@@ -421,7 +434,14 @@ def layout(pos0, row_ptr, col_idx, params, iters=None, t_start=0,
     total = params.total_iters
     t0 = params.t0 if params.t0 > 0 else default_t0(n)
     iters = total - t_start if iters is None else iters
+    auto = params.n_int == 0
+    if auto:
+        params = Params(**{**params.__dict__})
+        kmax = params.k_mode if params.k_mode in (1, 2) else 3
+        params.n_int = auto_n_int(x, 1024 // kmax)
     for t in range(t_start, t_start + iters):
+        if auto and t % AUTO_GRID_CHUNK == 0:
+            params.n_int = auto_n_int(x, 1024 // kmax)
         k = params.k_mode if params.k_mode >= 0 else k_for_iteration(t, total)
         _, _, disp = forces(x, row_ptr, col_idx, params, k, rep_w, att_w)
         x = capped_move(x, disp, step_cap(t, total, t0))

@@ -23,6 +23,7 @@ from .tfdp import (  # noqa: F401
     tfdp_layout_destroy,
     tfdp_layout_forces,
     tfdp_layout_get_iter,
+    tfdp_layout_get_params,
     tfdp_layout_init,
     tfdp_layout_phase_times,
     tfdp_layout_set_iter,

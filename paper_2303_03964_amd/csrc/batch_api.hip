@@ -386,6 +386,10 @@ tfdp_status tfdp_batch_add(tfdp_batch* b, tfdp_layout* h) {
         set_msg("batched stepping needs a single edge-pass column slice");
         return TFDP_ERR_UNSUPPORTED;
     }
+    if (h->auto_grid) {
+        set_msg("batched stepping needs a fixed grid (n_int > 0)");
+        return TFDP_ERR_UNSUPPORTED;
+    }
     b->mem.push_back(h);
     b->seen.push_back(0);
     b->geo.push_back(make_int2(0, 0));

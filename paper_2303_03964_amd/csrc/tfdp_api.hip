@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/tfdp.h: parameter validation,
 // workspace layout, the per-iteration launch sequence and profiling.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -108,6 +109,15 @@ Layout carve(void* base, int n, long long nnz, const tfdp_params* p, long long s
 }
 
 bool finite_f(float v) { return std::isfinite(v); }
+
+// Automatic grid (n_int = 0): the largest grid the workspace holds for the
+// k range of the parameters, and the parameters the workspace is sized for.
+int auto_grid_cap(const tfdp_params* p) { return (kMaxL / 2) / k_workspace(p); }
+tfdp_params sizing_params(const tfdp_params* p) {
+    tfdp_params q = *p;
+    if (q.n_int == 0) q.n_int = auto_grid_cap(p);
+    return q;
+}
 
 // Edge-pass schedule: rows with more than kGroupEdges entries get a block
 // each (slot 0 = {row, -1}); the other rows are cut, in order, into wave
@@ -320,6 +330,67 @@ hipGraphExec_t pair_graph(tfdp_layout* h, int k, int parity, int orient, const M
 }
 
 
+// New parameters; a new grid re-lays the grid arrays inside the same
+// workspace (TFDP_ERR_WORKSPACE if they do not fit).
+tfdp_status relay_grid(tfdp_layout* h, const tfdp_params& q) {
+    if (q.n_int != h->p.n_int || k_workspace(&q) != h->k_ws) {
+        size_t need = 0;
+        Layout nl = carve(h->ws, h->n, h->nnz, &q, h->slice_nodes, &need);
+        if (need > h->ws_bytes) {
+            set_msg("workspace too small for this n_int / k_mode: need " + std::to_string(need) + " bytes");
+            return TFDP_ERR_WORKSPACE;
+        }
+        for (int s = 0; s < kMaxSlices; ++s) nl.slice[s] = h->lay.slice[s];
+        h->lay = nl;
+        h->k_ws = k_workspace(&q);
+        h->tw_pending = true;
+    }
+    h->p = q;
+    h->version += 1;
+    drop_graphs(h);
+    return TFDP_OK;
+}
+
+float host_dec_ord(unsigned int u) {
+    const unsigned int v = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+    float f;
+    std::memcpy(&f, &v, sizeof(f));
+    return f;
+}
+
+// Automatic grid: intervals per side = max(kAutoGridMin, ceil(W)) for the
+// box side W of the current positions (one interval per unit of layout
+// length), capped by the workspace. Reads the box extremes back to the host.
+tfdp_status choose_auto_grid(tfdp_layout* h, hipStream_t s) {
+    DevState* st = h->lay.b.st;
+    const int set = h->t & 1;
+    launch_box_begin(st, h->t, s);
+    launch_box_reduce(reinterpret_cast<const float2*>(h->pos), h->n, st, set, s);
+    unsigned int mm[kBoxSlots][32];
+    tfdp_status r = check_hip(hipMemcpyAsync(mm, st->mm[set], sizeof(mm), hipMemcpyDeviceToHost, s),
+                              "hipMemcpyAsync");
+    if (r == TFDP_OK) r = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (r != TFDP_OK) return r;
+    unsigned int a0 = 0xffffffffu, a1 = 0xffffffffu, a2 = 0u, a3 = 0u;
+    for (int i = 0; i < kBoxSlots; ++i) {
+        a0 = std::min(a0, mm[i][0]);
+        a1 = std::min(a1, mm[i][1]);
+        a2 = std::max(a2, mm[i][2]);
+        a3 = std::max(a3, mm[i][3]);
+    }
+    double w = 1.0;
+    if (a0 != 0xffffffffu) {
+        w = std::max((double)host_dec_ord(a2) - (double)host_dec_ord(a0),
+                     (double)host_dec_ord(a3) - (double)host_dec_ord(a1));
+        if (!(w > 0.0)) w = 1.0;
+    }
+    const int cap = auto_grid_cap(&h->p);
+    const double want = std::max((double)kAutoGridMin, std::ceil(w));
+    tfdp_params q = h->p;
+    q.n_int = (int)std::min((double)cap, want);
+    return relay_grid(h, q);
+}
+
 }  // namespace
 
 extern "C" {
@@ -366,8 +437,8 @@ tfdp_status tfdp_params_validate(const tfdp_params* p, int32_t n, int64_t nnz) {
         set_msg("alpha, beta and rep_weight must be finite and >= 0");
         return TFDP_ERR_INVALID_ARG;
     }
-    if (p->n_int < 1 || p->n_int > kMaxNInt) {
-        set_msg("n_int must be in [1, 1024]");
+    if (p->n_int < 0 || p->n_int > kMaxNInt) {
+        set_msg("n_int must be 0 (automatic) or in [1, 1024]");
         return TFDP_ERR_INVALID_ARG;
     }
     if (p->k_mode < -1 || p->k_mode > 3) {
@@ -398,7 +469,8 @@ tfdp_status tfdp_params_validate(const tfdp_params* p, int32_t n, int64_t nnz) {
 size_t tfdp_workspace_size(int32_t n, int64_t nnz, const tfdp_params* p) {
     if (tfdp_params_validate(p, n, nnz) != TFDP_OK) return 0;
     size_t bytes = 0;
-    carve(nullptr, n, nnz, p, slice_nodes(), &bytes);
+    const tfdp_params q = sizing_params(p);
+    carve(nullptr, n, nnz, &q, slice_nodes(), &bytes);
     return bytes;
 }
 
@@ -419,7 +491,8 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
     }
     size_t need = 0;
     const long long sn = slice_nodes();
-    carve(nullptr, n, nnz, p, sn, &need);
+    const tfdp_params sizing = sizing_params(p);
+    carve(nullptr, n, nnz, &sizing, sn, &need);
     if (!d_ws || ws_bytes < need) {
         set_msg("workspace too small: need " + std::to_string(need) + " bytes");
         return TFDP_ERR_WORKSPACE;
@@ -441,6 +514,8 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
     h->ws = d_ws;
     h->ws_bytes = ws_bytes;
     h->p = *p;
+    h->auto_grid = p->n_int == 0;
+    if (h->auto_grid) h->p.n_int = std::min(kAutoGridMin, auto_grid_cap(p));
     h->k_ws = k_workspace(p);
     h->t = 0;
     h->prof = false;
@@ -450,7 +525,7 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
     h->ev_stream = nullptr;
     size_t bytes = 0;
     h->slice_nodes = sn;
-    h->lay = carve(d_ws, n, nnz, p, sn, &bytes);
+    h->lay = carve(d_ws, n, nnz, &h->p, sn, &bytes);
 
     DevState* dst = h->lay.b.st;
     static const bool attrs = (init_kernel_attributes(), true);
@@ -479,6 +554,8 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
     return TFDP_OK;
 }
 
+static tfdp_status step_fixed_grid(tfdp_layout* h, int32_t iters, hipStream_t s);
+
 tfdp_status tfdp_layout_step(tfdp_layout* h, int32_t iters, hipStream_t s) {
     if (!h || iters < 0) {
         set_msg("invalid handle or iteration count");
@@ -486,6 +563,21 @@ tfdp_status tfdp_layout_step(tfdp_layout* h, int32_t iters, hipStream_t s) {
     }
     set_msg("");
     if (iters == 0) return TFDP_OK;
+    if (!h->auto_grid) return step_fixed_grid(h, iters, s);
+    for (int done = 0; done < iters;) {
+        const int c = std::min(kAutoGridChunk - h->t % kAutoGridChunk, iters - done);
+        if (h->t % kAutoGridChunk == 0) {  // chosen at fixed counters: independent of how calls split
+            tfdp_status st = choose_auto_grid(h, s);
+            if (st != TFDP_OK) return st;
+        }
+        tfdp_status st = step_fixed_grid(h, c, s);
+        if (st != TFDP_OK) return st;
+        done += c;
+    }
+    return TFDP_OK;
+}
+
+static tfdp_status step_fixed_grid(tfdp_layout* h, int32_t iters, hipStream_t s) {
     const ModelArgs a = model_args(h);
     float2* cur = reinterpret_cast<float2*>(h->pos);
     float2* alt = h->lay.pos_alt;
@@ -565,22 +657,31 @@ tfdp_status tfdp_layout_set_params(tfdp_layout* h, const tfdp_params* p) {
     }
     tfdp_status st = tfdp_params_validate(p, h->n, h->nnz);
     if (st != TFDP_OK) return st;
-    if (p->n_int != h->p.n_int || k_workspace(p) != h->k_ws) {
-        // new grid: re-lay the grid arrays inside the same workspace
+    tfdp_params q = *p;
+    const bool automatic = p->n_int == 0;
+    if (automatic) {
+        // the workspace must hold the largest automatic grid
         size_t need = 0;
-        Layout nl = carve(h->ws, h->n, h->nnz, p, h->slice_nodes, &need);
+        const tfdp_params sizing = sizing_params(p);
+        carve(nullptr, h->n, h->nnz, &sizing, h->slice_nodes, &need);
         if (need > h->ws_bytes) {
-            set_msg("workspace too small for this n_int / k_mode: need " + std::to_string(need) + " bytes");
+            set_msg("workspace too small for the automatic grid: need " + std::to_string(need) + " bytes");
             return TFDP_ERR_WORKSPACE;
         }
-        for (int s = 0; s < kMaxSlices; ++s) nl.slice[s] = h->lay.slice[s];
-        h->lay = nl;
-        h->k_ws = k_workspace(p);
-        h->tw_pending = true;
+        q.n_int = h->auto_grid ? std::min(h->p.n_int, auto_grid_cap(p)) : std::min(kAutoGridMin, auto_grid_cap(p));
     }
-    h->p = *p;
-    h->version += 1;
-    drop_graphs(h);
+    st = relay_grid(h, q);
+    if (st != TFDP_OK) return st;
+    h->auto_grid = automatic;
+    return TFDP_OK;
+}
+
+tfdp_status tfdp_layout_get_params(const tfdp_layout* h, tfdp_params* out) {
+    if (!h || !out) {
+        set_msg("invalid handle or pointer");
+        return TFDP_ERR_INVALID_ARG;
+    }
+    *out = h->p;
     return TFDP_OK;
 }
 

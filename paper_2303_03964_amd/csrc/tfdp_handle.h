@@ -90,6 +90,7 @@ struct tfdp_layout {
     bool tw_pending;        // twiddle tables to (re)compute before the next launch
     const float* rep_w;     // local-refinement weights (caller's device arrays) or null
     const float* att_w;
+    bool auto_grid;         // n_int chosen from the box every kAutoGridChunk iterations
 };
 
 namespace tfdp {

@@ -63,6 +63,7 @@ _SIGS = {
     "tfdp_layout_forces": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "tfdp_layout_set_params": (c_int32, [c_void_p, POINTER(TfdpParams)]),
     "tfdp_layout_set_node_weights": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "tfdp_layout_get_params": (c_int32, [c_void_p, POINTER(TfdpParams)]),
     "tfdp_layout_get_iter": (c_int32, [c_void_p, POINTER(c_int32)]),
     "tfdp_layout_set_iter": (c_int32, [c_void_p, c_int32]),
     "tfdp_layout_sync_status": (c_int32, [c_void_p, c_void_p]),
@@ -169,6 +170,12 @@ def tfdp_layout_set_params(h, params):
 
 def tfdp_layout_set_node_weights(h, rep_w=None, att_w=None):
     return _check(load_library().tfdp_layout_set_node_weights(h, _ptr(rep_w), _ptr(att_w)))
+
+
+def tfdp_layout_get_params(h) -> TfdpParams:
+    p = TfdpParams()
+    _check(load_library().tfdp_layout_get_params(h, ctypes.byref(p)))
+    return p
 
 
 def tfdp_layout_get_iter(h) -> int:

@@ -31,7 +31,7 @@ def test_defaults_match_paper():
 @pytest.mark.parametrize("field,value,code", [
     ("gamma", 1.0, INVALID), ("gamma", 0.5, INVALID), ("gamma", float("nan"), INVALID),
     ("alpha", -0.1, INVALID), ("alpha", float("inf"), INVALID), ("beta", -1.0, INVALID),
-    ("rep_weight", -2.0, INVALID), ("n_int", 0, INVALID), ("n_int", 1025, INVALID),
+    ("rep_weight", -2.0, INVALID), ("n_int", -1, INVALID), ("n_int", 1025, INVALID),
     ("k_mode", 4, INVALID), ("k_mode", -2, INVALID), ("total_iters", 0, INVALID),
     ("t0", float("inf"), INVALID), ("n_int", 400, UNSUPPORTED),
     ("tau", 0.0, INVALID), ("tau", -1.0, INVALID), ("tau", float("nan"), INVALID),
@@ -53,6 +53,10 @@ def test_validate_sizes_and_limits():
     assert T.tfdp_params_validate(T.tfdp_params_default(n_int=1024, k_mode=1), 10, 0) == OK
     assert T.tfdp_params_validate(T.tfdp_params_default(n_int=341), 10, 0) == OK
     assert T.tfdp_params_validate(T.tfdp_params_default(n_int=342), 10, 0) == UNSUPPORTED
+    # automatic grid: valid, workspace sized for the largest grid of the k range
+    auto = T.tfdp_params_default(n_int=0)
+    assert T.tfdp_params_validate(auto, 10, 0) == OK
+    assert T.tfdp_workspace_size(1000, 0, auto) == T.tfdp_workspace_size(1000, 0, T.tfdp_params_default(n_int=341))
 
 
 def test_contact_condition_is_a_warning():
@@ -105,6 +109,7 @@ def test_null_handle_calls():
     assert lib.tfdp_layout_set_profiling(None, 1) == INVALID
     assert lib.tfdp_layout_set_graphs(None, 1) == INVALID
     assert lib.tfdp_layout_set_node_weights(None, None, None) == INVALID
+    assert lib.tfdp_layout_get_params(None, None) == INVALID
     lib.tfdp_layout_destroy(None)
 
 

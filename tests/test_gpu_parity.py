@@ -516,3 +516,36 @@ def test_local_refinement_weights(T, k):
     want2 = ot.forces(pos.astype(np.float64), g.row_ptr, g.col_idx, q, k)
     assert rel_l2(got2[2], want2[2]) <= TOL
     lay.close()
+
+
+def test_automatic_grid(T):
+    """n_int = 0: every 10 iterations the grid becomes max(50, ceil(W)) for
+    the box of the current positions; the choice does not depend on how the
+    iterations are split into calls; forces on the chosen grid match the
+    oracle."""
+    import torch
+    from oracle.tfdp import auto_n_int
+    w = sg.sbm_1k()
+    g = w.graph
+    a = make_layout(T, g, w.pos0, n_int=0, total_iters=300)
+    b = make_layout(T, g, w.pos0, n_int=0, total_iters=300)
+    assert T.tfdp_layout_get_params(a.handle).n_int == 50
+    for chunk in range(4):
+        want = auto_n_int(a.pos.cpu().numpy().astype(np.float64), 341)
+        a.step(10)
+        torch.cuda.synchronize()
+        got = T.tfdp_layout_get_params(a.handle).n_int
+        say(f"chunk {chunk}: grid {got} (box rule {want})")
+        assert got == want
+    for c in (7, 11, 4, 18):
+        b.step(c)
+    torch.cuda.synchronize()
+    assert a.iteration == b.iteration == 40
+    assert torch.equal(a.pos, b.pos)
+    ni = T.tfdp_layout_get_params(a.handle).n_int
+    pos = a.pos.cpu().numpy()
+    check_forces = oracle_forces(g, pos, 3, ni)
+    got = gpu_forces(a, pos, 3)
+    assert rel_l2(got[2], check_forces[2]) <= TOL
+    a.close()
+    b.close()

@@ -530,3 +530,13 @@ def test_local_refinement_two_nodes_closed_form():
     assert disp[0, 1] == 0.0 and disp[1, 1] == 0.0
     # symmetric edge weights keep Newton's third law for the attraction
     assert fa[0, 0] == pytest.approx(-fa[1, 0], rel=1e-15)
+
+
+def test_auto_grid_rule():
+    """max(50, ceil(W)) intervals per side, W = side of the square box."""
+    x = np.array([[0.0, 0.0], [37.2, 5.0]])
+    assert ot.auto_n_int(x, 341) == 50
+    x = np.array([[-60.0, 0.0], [60.3, 1.0]])
+    assert ot.auto_n_int(x, 341) == 121
+    assert ot.auto_n_int(x, 100) == 100
+    assert ot.auto_n_int(np.zeros((3, 2)), 341) == 50  # coincident: W = 1
