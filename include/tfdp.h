@@ -213,6 +213,28 @@ const char* tfdp_phase_name(int32_t phase);
 tfdp_status tfdp_layout_phase_times(tfdp_layout* h, double* total_ms, int64_t* launches,
                                     int32_t nphases);
 
+/* ---- Layout quality (Sec. 4, "Metrics") ----
+ *
+ * Stress error estimated from a sample of source nodes:
+ *   SE = mean over pairs (s, v), v != s, v reachable from s, of
+ *        (c ||x_s - x_v|| / D(s, v) - 1)^2
+ * with D the hop distance and c = sum(||x_s - x_v|| / D) / sum((||x_s - x_v|| / D)^2)
+ * the optimal uniform scale of the layout. Hop distances come from one
+ * multi-source BFS on the device (up to 254 levels; farther nodes count as
+ * unreachable).
+ *   n, nnz, d_row_ptr, d_col_idx  symmetric CSR (device, as for tfdp_layout_init;
+ *               checked on the device first: TFDP_ERR_INVALID_ARG if invalid)
+ *   d_pos       float32[n][2] positions (device)
+ *   d_sources   int32[nsrc] source nodes in [0, n) (device), 1 <= nsrc <= 64
+ *   d_work      device scratch of work_bytes >= tfdp_stress_workspace_size(n, nsrc)
+ *   se          result (host); NaN when no pair is reachable
+ *   levels      BFS levels run (host, may be NULL)
+ * Synchronises `stream`. */
+size_t tfdp_stress_workspace_size(int32_t n, int32_t nsrc);
+tfdp_status tfdp_stress_sampled(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
+                                const float* d_pos, const int32_t* d_sources, int32_t nsrc, void* d_work,
+                                size_t work_bytes, double* se, int32_t* levels, hipStream_t stream);
+
 /* ---- Batched stepping ----
  *
  * A batch steps many layout handles (graphs of any sizes, each with its own

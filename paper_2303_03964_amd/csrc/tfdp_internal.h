@@ -198,6 +198,13 @@ void launch_b_advance(int* tcall, int slots, int iters, hipStream_t s);
 void launch_b_brute(const Member* mem, const int2* map, int blocks, const int2* tick_map, int members, int j,
                     hipStream_t s);
 
+// ---- layout quality (metrics.hip) ----
+size_t stress_workspace_bytes(int n, int nsrc);
+// 0, -1 (invalid CSR) or the HIP error; *se = sampled stress error,
+// *levels = BFS levels run
+int stress_sampled(int n, long long nnz, const int* row_ptr, const int* col_idx, const float2* pos, const int* src,
+                   int nsrc, void* work, double* se, int* levels, hipStream_t s);
+
 // ---- device helpers used by several translation units ----
 
 // Order-preserving map float -> uint (min/max of floats via integer atomics).

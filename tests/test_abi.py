@@ -162,3 +162,20 @@ def test_batch_host_bookkeeping():
     assert lib.tfdp_batch_set_graphs(b, 0) == OK and lib.tfdp_batch_set_graphs(None, 1) == INVALID
     lib.tfdp_batch_destroy(b)
     lib.tfdp_batch_destroy(None)
+
+
+def test_stress_metric_host_checks():
+    lib = T.load_library()
+    assert T.tfdp_stress_workspace_size(0, 4) == 0
+    assert T.tfdp_stress_workspace_size(10, 0) == 0 and T.tfdp_stress_workspace_size(10, 65) == 0
+    assert T.tfdp_stress_workspace_size(1000, 64) > 64 * 1000
+    se = ctypes.c_double()
+    fake = ctypes.c_void_p(0x100000)
+    assert lib.tfdp_stress_sampled(10, 4, fake, fake, fake, fake, 0, fake, 1 << 20, ctypes.byref(se), None,
+                                   None) == INVALID
+    assert lib.tfdp_stress_sampled(10, 4, None, fake, fake, fake, 4, fake, 1 << 20, ctypes.byref(se), None,
+                                   None) == INVALID
+    assert lib.tfdp_stress_sampled(10, 4, fake, fake, fake, fake, 4, None, 1 << 20, ctypes.byref(se), None,
+                                   None) == WORKSPACE
+    assert lib.tfdp_stress_sampled(10, 4, fake, fake, fake, fake, 4, fake, 16, ctypes.byref(se), None,
+                                   None) == WORKSPACE

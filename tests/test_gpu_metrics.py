@@ -1,0 +1,75 @@
+"""Sampled stress error on the device (Sec. 4, "Metrics") against the FP64
+oracle's metric with the same sources: multi-source BFS hop distances and
+the optimal-scale stress over (source, node) pairs."""
+import sys
+
+import numpy as np
+import pytest
+
+import synthgraphs as sg
+from oracle import metrics as om
+from tests._lib import ensure_built
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ensure_built()
+    import paper_2303_03964_amd as lib
+    lib.load_library()
+    return lib
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_se(T, g, pos, sources):
+    import torch
+    rp = torch.as_tensor(g.row_ptr, dtype=torch.int32).cuda()
+    ci = torch.as_tensor(g.col_idx, dtype=torch.int32).cuda()
+    p = torch.as_tensor(pos, dtype=torch.float32).cuda()
+    src = torch.as_tensor(np.asarray(sources), dtype=torch.int32).cuda()
+    return T.tfdp_stress_sampled(rp, ci, p, src)
+
+
+@pytest.mark.parametrize("case", ["sbm_1k", "two_components", "mesh_100k"])
+def test_sampled_stress_matches_oracle(T, case):
+    rng = np.random.default_rng(3)
+    if case == "sbm_1k":
+        w = sg.sbm_1k()
+        g, pos = w.graph, sg.uniform_positions(w.graph.n, 4, -20, 20)
+        src = rng.choice(g.n, 64, replace=False)
+    elif case == "two_components":
+        a = sg.sbm([150, 150], 0.05, 0.01, 5)
+        b = sg.sbm([100, 100], 0.05, 0.01, 6)
+        e = np.concatenate([a.edges(), b.edges() + a.n])
+        g = sg.csr_from_edges(a.n + b.n, e)
+        pos = sg.uniform_positions(g.n, 7, -10, 10)
+        src = rng.choice(g.n, 17, replace=False)
+    else:
+        w = sg.mesh_100k()
+        g, pos = w.graph, sg.uniform_positions(w.graph.n, 8, -300, 300)
+        src = rng.choice(g.n, 64, replace=False)
+    se, levels = gpu_se(T, g, pos, src)
+    want = om.stress_error(pos.astype(np.float64), g.row_ptr, g.col_idx, sources=src)
+    d = om.graph_distances(g.n, g.row_ptr, g.col_idx, src)
+    ecc = int(np.nanmax(np.where(np.isfinite(d), d, np.nan)))
+    say(f"{case}: n={g.n} SE gpu {se:.12f} oracle {want:.12f} levels {levels} (max distance {ecc})")
+    assert abs(se - want) <= 1e-9 * abs(want)
+    assert levels == ecc + 1
+
+
+def test_invalid_csr_is_rejected(T):
+    import torch
+    rp = torch.tensor([0, 1, 2], dtype=torch.int32).cuda()
+    ci = torch.tensor([1, 5], dtype=torch.int32).cuda()  # column out of range
+    p = torch.zeros((2, 2), dtype=torch.float32).cuda()
+    src = torch.tensor([0], dtype=torch.int32).cuda()
+    with pytest.raises(T.TfdpError):
+        T.tfdp_stress_sampled(rp, ci, p, src)
