@@ -369,12 +369,13 @@ def main():
         ph_rest = T.tfdp_layout_phase_times(lay.handle)
     T.tfdp_layout_set_profiling(lay.handle, 0)
     torch.cuda.synchronize()
-    # quality of the final layout: stress error from 64 seeded sources (BFS
-    # and sums on the device)
+    # quality of the final layout: stress error and neighbourhood preservation
+    # over 64 seeded sources (BFS, sums and the radix select on the device)
     t_q = time.perf_counter()
     src = torch.as_tensor(np.random.default_rng(20230307).choice(g.n, 64, replace=False), dtype=torch.int32).to(dev)
-    se, levels = T.tfdp_stress_sampled(lay.row_ptr, lay.col_idx, lay.pos, src)
-    quality = {"se_sampled": se, "sources": 64, "bfs_levels": levels, "seconds": time.perf_counter() - t_q}
+    se, nps, levels = T.tfdp_quality_sampled(lay.row_ptr, lay.col_idx, lay.pos, src)
+    quality = {"se_sampled": se, "np1_sampled": nps[0], "np2_sampled": nps[1], "sources": 64,
+               "bfs_levels": levels, "seconds": round(time.perf_counter() - t_q, 4)}
 
     gm_ms, gm_n = ph1["gather_update"]
     avg_ms = gm_ms / max(gm_n, 1)

@@ -225,8 +225,10 @@ tfdp_status tfdp_layout_phase_times(tfdp_layout* h, double* total_ms, int64_t* l
  *   n, nnz, d_row_ptr, d_col_idx  symmetric CSR (device, as for tfdp_layout_init;
  *               checked on the device first: TFDP_ERR_INVALID_ARG if invalid)
  *   d_pos       float32[n][2] positions (device)
- *   d_sources   int32[nsrc] source nodes in [0, n) (device), 1 <= nsrc <= 64
- *   d_work      device scratch of work_bytes >= tfdp_stress_workspace_size(n, nsrc)
+ *   d_sources   int32[nsrc] source nodes in [0, n) (device), 1 <= nsrc <= 64;
+ *               checked on the device: TFDP_ERR_INVALID_ARG otherwise
+ *   d_work      device scratch of work_bytes >= tfdp_stress_workspace_size(n, nsrc),
+ *               256-byte aligned (TFDP_ERR_WORKSPACE otherwise)
  *   se          result (host); NaN when no pair is reachable
  *   levels      BFS levels run (host, may be NULL)
  * Synchronises `stream`. */
@@ -234,6 +236,19 @@ size_t tfdp_stress_workspace_size(int32_t n, int32_t nsrc);
 tfdp_status tfdp_stress_sampled(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
                                 const float* d_pos, const int32_t* d_sources, int32_t nsrc, void* d_work,
                                 size_t work_bytes, double* se, int32_t* levels, hipStream_t stream);
+/* Stress error as above plus neighbourhood preservation over the same
+ * sources (Sec. 4, "Metrics"): for r = 1, 2 and each source s with a
+ * non-empty graph ring N_G(s, r) = {v : 1 <= D(s, v) <= r} of k_s nodes, the
+ * Jaccard index of that ring and the k_s nearest layout neighbours of s
+ * (s excluded; equal distances, compared as float64 squared distances, go
+ * to the lower node index); NP_r = the mean of those indices. The k_s-th
+ * nearest node is found by an exact radix select on the device.
+ *   np          double[2] result (host): NP_1, NP_2; NaN where no source
+ *               has a non-empty ring
+ * Other arguments, workspace size and errors as for tfdp_stress_sampled. */
+tfdp_status tfdp_quality_sampled(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
+                                 const float* d_pos, const int32_t* d_sources, int32_t nsrc, void* d_work,
+                                 size_t work_bytes, double* se, double* np, int32_t* levels, hipStream_t stream);
 
 /* ---- Batched stepping ----
  *

@@ -37,6 +37,7 @@ from .tfdp import (  # noqa: F401
     tfdp_params_validate,
     tfdp_phase_count,
     tfdp_phase_name,
+    tfdp_quality_sampled,
     tfdp_stress_sampled,
     tfdp_stress_workspace_size,
     tfdp_workspace_size,

@@ -1,10 +1,12 @@
-// Layout quality on the device (Sec. 4, "Metrics"): the stress error SE
-// estimated from a sample of source nodes. Hop distances from up to 64
+// Layout quality on the device (Sec. 4, "Metrics"): the stress error SE and
+// the neighbourhood preservation NP_1, NP_2 estimated from a sample of
+// source nodes. Hop distances from up to 64
 // sources come from one multi-source BFS with a 64-bit source mask per node
 // (a level per launch, pulled from the neighbours' frontier masks); the
 // stress sums over all (source, node) pairs at finite distance are reduced
 // per block in float64 and added on the host in block order.
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "tfdp_internal.h"
@@ -12,6 +14,12 @@
 namespace tfdp {
 
 constexpr int kMetricThreads = 256;
+
+// Sources outside [0, n) mark the check flag (read with the CSR check).
+__global__ void k_src_check(const int* __restrict__ src, int nsrc, int n, int* bad) {
+    const int q = threadIdx.x;
+    if (q < nsrc && (src[q] < 0 || src[q] >= n)) *bad = 2;
+}
 
 // visited = frontier = the mask of the sources at each node; distances of
 // the sources to themselves 0, all others unreached (255).
@@ -104,6 +112,11 @@ __global__ __launch_bounds__(kMetricThreads) void k_stress_sums(int n, const flo
 
 constexpr int kStressBlocks = 1024;
 
+// neighbourhood preservation over the BFS distances (below)
+int np_sampled(int n, const float2* pos, const int* src, int nsrc, const unsigned char* dist, void* extra,
+               double* np, hipStream_t s);
+size_t np_extra_bytes(int nsrc);
+
 size_t stress_workspace_bytes(int n, int nsrc) {
     size_t b = 0;
     auto take = [&](size_t bytes) { b = (b + 255) & ~(size_t)255; b += bytes; };
@@ -114,13 +127,15 @@ size_t stress_workspace_bytes(int n, int nsrc) {
     take((size_t)nsrc * n);       // distances
     take(sizeof(int));            // changed flag
     take((size_t)kStressBlocks * 3 * sizeof(double));
+    take(np_extra_bytes(nsrc));
     return (b + 255) & ~(size_t)255;
 }
 
-// Returns 0 on success, -1 for an invalid CSR, else the HIP error; fills SE
-// (NaN without pairs).
+// Returns 0 on success, -1 for an invalid CSR, -2 for a source outside
+// [0, n), else the HIP error; fills SE
+// (NaN without pairs) and, when np is not NULL, NP_1 and NP_2.
 int stress_sampled(int n, long long nnz, const int* row_ptr, const int* col_idx, const float2* pos, const int* src,
-                   int nsrc, void* work, double* se, int* levels, hipStream_t s) {
+                   int nsrc, void* work, double* se, double* np, int* levels, hipStream_t s) {
     char* base = static_cast<char*>(work);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -135,11 +150,13 @@ int stress_sampled(int n, long long nnz, const int* row_ptr, const int* col_idx,
         hipError_t e = hipMemsetAsync(chk, 0, sizeof(DevState), s);
         if (e != hipSuccess) return (int)e;
         launch_csr_check(row_ptr, col_idx, n, nnz, chk, s);
-        int bad = 0;
-        e = hipMemcpyAsync(&bad, &chk->csr_bad, sizeof(int), hipMemcpyDeviceToHost, s);
+        hipLaunchKernelGGL(k_src_check, dim3(1), dim3(64), 0, s, src, nsrc, n, &chk->pad);
+        int bad[2] = {0, 0};  // csr_bad, pad (sources)
+        e = hipMemcpyAsync(bad, &chk->csr_bad, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return (int)e;
-        if (bad) return -1;
+        if (bad[0]) return -1;
+        if (bad[1]) return -2;
     }
     auto* visited = static_cast<unsigned long long*>(take((size_t)n * 8));
     auto* frontier = static_cast<unsigned long long*>(take((size_t)n * 8));
@@ -147,6 +164,7 @@ int stress_sampled(int n, long long nnz, const int* row_ptr, const int* col_idx,
     auto* dist = static_cast<unsigned char*>(take((size_t)nsrc * n));
     auto* changed = static_cast<int*>(take(sizeof(int)));
     auto* partial = static_cast<double*>(take((size_t)kStressBlocks * 3 * sizeof(double)));
+    void* np_extra = take(np_extra_bytes(nsrc));
     const int blocks = (n + kMetricThreads - 1) / kMetricThreads;
     hipLaunchKernelGGL(k_bfs_init, dim3(blocks), dim3(kMetricThreads), 0, s, n, src, nsrc, visited, frontier, dist);
     int level = 1;
@@ -183,6 +201,196 @@ int stress_sampled(int n, long long nnz, const int* row_ptr, const int* col_idx,
         *se = (sc * sc * sr2 - 2.0 * sc * sr + cnt) / cnt;
     } else {
         *se = std::nan("");
+    }
+    if (np) return np_sampled(n, pos, src, nsrc, dist, np_extra, np, s);
+    return 0;
+}
+
+}  // namespace tfdp
+
+namespace tfdp {
+
+// ----------------------------------------------------------------- neighbourhood preservation
+//
+// NP_r for sampled nodes s (Sec. 4, "Metrics"): the k_s = |N_G(s, r)| nearest
+// layout neighbours of s (s excluded, distance ties to the lower index)
+// against the graph ring N_G(s, r) = {v : 1 <= D(s, v) <= r} from the BFS
+// distances; NP_r = mean over sampled nodes with k_s > 0 of the Jaccard
+// index |A & B| / |A | B| = o / (2 k_s - o). The k_s-th smallest key
+// (squared distance in float64, then the node index) is found per source by
+// an exact radix select: eight 8-bit passes over the bits of the squared
+// distance, then four over the index among exact ties.
+
+constexpr int kNpBlocks = 128;
+
+__device__ __forceinline__ unsigned long long d2_key(const float2 p, const float2 q) {
+#pragma clang fp contract(off)  // the plain sum of the two rounded squares
+    const double dx = (double)p.x - (double)q.x;
+    const double dy = (double)p.y - (double)q.y;
+    return (unsigned long long)__double_as_longlong(dx * dx + dy * dy);  // >= 0: monotone as unsigned
+}
+
+// Ring sizes: count[s] += #{v : lo <= D(s, v) <= r}.
+__global__ __launch_bounds__(kMetricThreads) void k_ring_count(int n, int nsrc, const unsigned char* __restrict__ dist,
+                                                              int r, unsigned int* count) {
+    __shared__ unsigned int c[64];
+    if (threadIdx.x < 64) c[threadIdx.x] = 0;
+    __syncthreads();
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        for (int s = 0; s < nsrc; ++s) {
+            const int d = dist[(size_t)s * n + v];
+            if (d >= 1 && d <= r) atomicAdd(&c[s], 1u);
+        }
+    __syncthreads();
+    if (threadIdx.x < nsrc && c[threadIdx.x]) atomicAdd(&count[threadIdx.x], c[threadIdx.x]);
+}
+
+// One radix pass: per source, histogram of digit `shift` of the key among
+// nodes whose key matches the source's prefix on `mask`. Phase 0 keys are
+// the squared distances; phase 1 keys are node indices among nodes whose
+// squared distance equals the selected value (sel[s]).
+struct NpSel {
+    unsigned long long prefix[64];
+    unsigned long long mask[64];
+    unsigned long long dsel[64];  // phase 1: the selected squared distance
+    int active[64];
+};
+
+__global__ __launch_bounds__(kMetricThreads) void k_np_hist(int n, const float2* __restrict__ pos,
+                                                           const int* __restrict__ src, int nsrc, NpSel sel,
+                                                           int phase, int shift, unsigned int* hist) {
+    extern __shared__ unsigned int h[];  // [nsrc][256]
+    for (int i = threadIdx.x; i < nsrc * 256; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const float2 p = pos[v];
+        for (int s = 0; s < nsrc; ++s) {
+            if (!sel.active[s] || v == src[s]) continue;
+            const unsigned long long d2 = d2_key(p, pos[src[s]]);
+            unsigned long long key;
+            if (phase == 0) {
+                key = d2;
+            } else {
+                if (d2 != sel.dsel[s]) continue;
+                key = (unsigned long long)v;
+            }
+            if ((key & sel.mask[s]) != sel.prefix[s]) continue;
+            atomicAdd(&h[s * 256 + (int)((key >> shift) & 255ull)], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nsrc * 256; i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// Overlap per source: nodes both in the ring and among the k nearest
+// (key below the selected (squared distance, index) pair).
+__global__ __launch_bounds__(kMetricThreads) void k_np_overlap(int n, const float2* __restrict__ pos,
+                                                              const int* __restrict__ src, int nsrc,
+                                                              const unsigned char* __restrict__ dist, int r,
+                                                              NpSel sel, const unsigned int* __restrict__ isel,
+                                                              unsigned int* overlap) {
+    __shared__ unsigned int c[64];
+    __shared__ float2 sp[64];
+    if (threadIdx.x < 64) c[threadIdx.x] = 0;
+    if (threadIdx.x < nsrc) sp[threadIdx.x] = pos[src[threadIdx.x]];
+    __syncthreads();
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const float2 p = pos[v];
+        for (int s = 0; s < nsrc; ++s) {
+            if (!sel.active[s] || v == src[s]) continue;
+            const int d = dist[(size_t)s * n + v];
+            if (d < 1 || d > r) continue;
+            const unsigned long long d2 = d2_key(p, sp[s]);
+            if (d2 < sel.dsel[s] || (d2 == sel.dsel[s] && (unsigned int)v <= isel[s])) atomicAdd(&c[s], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nsrc && c[threadIdx.x]) atomicAdd(&overlap[threadIdx.x], c[threadIdx.x]);
+}
+
+size_t np_extra_bytes(int) { return ((size_t)64 * 256 * 4 + 256) + ((size_t)64 * 4 + 256) * 3; }
+
+// NP_r for r = 1 and 2 from the BFS distances in the stress workspace (the
+// same sources); np[0] = NP_1, np[1] = NP_2 (NaN when no source has a
+// non-empty ring).
+int np_sampled(int n, const float2* pos, const int* src, int nsrc, const unsigned char* dist, void* extra,
+               double* np, hipStream_t s) {
+    char* base = static_cast<char*>(extra);
+    unsigned int* hist = reinterpret_cast<unsigned int*>(base);
+    unsigned int* count = reinterpret_cast<unsigned int*>(base + 64 * 256 * 4 + 256);
+    unsigned int* isel_d = count + 128;
+    unsigned int* overlap = isel_d + 128;
+    for (int r = 1; r <= 2; ++r) {
+        hipError_t e = hipMemsetAsync(count, 0, 64 * 4, s);
+        if (e != hipSuccess) return (int)e;
+        hipLaunchKernelGGL(k_ring_count, dim3(kNpBlocks), dim3(kMetricThreads), 0, s, n, nsrc, dist, r, count);
+        unsigned int k[64] = {0};
+        e = hipMemcpyAsync(k, count, nsrc * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return (int)e;
+        NpSel sel;
+        std::memset(&sel, 0, sizeof(sel));
+        unsigned long long rank[64];
+        for (int q = 0; q < nsrc; ++q) {
+            sel.active[q] = k[q] > 0 ? 1 : 0;
+            rank[q] = k[q];
+        }
+        unsigned int isel[64] = {0};
+        // phase 0: squared distance bits; phase 1: index among ties
+        for (int phase = 0; phase < 2; ++phase) {
+            const int top = phase == 0 ? 56 : 24;
+            for (int shift = top; shift >= 0; shift -= 8) {
+                e = hipMemsetAsync(hist, 0, (size_t)nsrc * 256 * 4, s);
+                if (e != hipSuccess) return (int)e;
+                hipLaunchKernelGGL(k_np_hist, dim3(kNpBlocks), dim3(kMetricThreads), (size_t)nsrc * 256 * 4, s, n,
+                                   pos, src, nsrc, sel, phase, shift, hist);
+                std::vector<unsigned int> hh((size_t)nsrc * 256);
+                e = hipMemcpyAsync(hh.data(), hist, hh.size() * 4, hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                if (e != hipSuccess) return (int)e;
+                for (int q = 0; q < nsrc; ++q) {
+                    if (!sel.active[q]) continue;
+                    unsigned long long acc = 0;
+                    int dgt = 0;
+                    for (; dgt < 256; ++dgt) {
+                        const unsigned long long c = hh[(size_t)q * 256 + dgt];
+                        if (acc + c >= rank[q]) break;
+                        acc += c;
+                    }
+                    if (dgt > 255) dgt = 255;  // not reached: rank <= candidates
+                    rank[q] -= acc;
+                    sel.prefix[q] |= (unsigned long long)dgt << shift;
+                    sel.mask[q] |= 255ull << shift;
+                }
+            }
+            if (phase == 0) {
+                for (int q = 0; q < nsrc; ++q) {
+                    sel.dsel[q] = sel.prefix[q];
+                    sel.prefix[q] = 0;
+                    sel.mask[q] = 0;
+                }
+            } else {
+                for (int q = 0; q < nsrc; ++q) isel[q] = (unsigned int)sel.prefix[q];
+            }
+        }
+        e = hipMemcpyAsync(isel_d, isel, nsrc * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemsetAsync(overlap, 0, 64 * 4, s);
+        if (e != hipSuccess) return (int)e;
+        hipLaunchKernelGGL(k_np_overlap, dim3(kNpBlocks), dim3(kMetricThreads), 0, s, n, pos, src, nsrc, dist, r, sel,
+                           isel_d, overlap);
+        unsigned int o[64] = {0};
+        e = hipMemcpyAsync(o, overlap, nsrc * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return (int)e;
+        double sum = 0.0;
+        int used = 0;
+        for (int q = 0; q < nsrc; ++q) {
+            if (!k[q]) continue;
+            sum += (double)o[q] / (2.0 * (double)k[q] - (double)o[q]);
+            ++used;
+        }
+        np[r - 1] = used ? sum / used : std::nan("");
     }
     return 0;
 }

@@ -771,29 +771,51 @@ size_t tfdp_stress_workspace_size(int32_t n, int32_t nsrc) {
     return stress_workspace_bytes(n, nsrc);
 }
 
-tfdp_status tfdp_stress_sampled(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
-                                const float* d_pos, const int32_t* d_sources, int32_t nsrc, void* d_work,
-                                size_t work_bytes, double* se, int32_t* levels, hipStream_t stream) {
+static tfdp_status quality_sampled(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
+                                   const float* d_pos, const int32_t* d_sources, int32_t nsrc, void* d_work,
+                                   size_t work_bytes, double* se, double* np, int32_t* levels, hipStream_t stream) {
     set_msg("");
     if (n < 1 || nnz < 0 || nsrc < 1 || nsrc > 64 || !d_row_ptr || (!d_col_idx && nnz > 0) || !d_pos ||
         !d_sources || !se) {
         set_msg("invalid sizes or pointers (1 <= nsrc <= 64)");
         return TFDP_ERR_INVALID_ARG;
     }
-    if (!d_work || work_bytes < stress_workspace_bytes(n, nsrc)) {
-        set_msg("metric workspace missing or smaller than tfdp_stress_workspace_size");
+    if (!d_work || work_bytes < stress_workspace_bytes(n, nsrc) || ((uintptr_t)d_work & 255u)) {
+        set_msg("metric workspace missing, misaligned or smaller than tfdp_stress_workspace_size");
         return TFDP_ERR_WORKSPACE;
     }
     int lv = 0;
     const int e = stress_sampled(n, nnz, d_row_ptr, d_col_idx, reinterpret_cast<const float2*>(d_pos), d_sources,
-                                 nsrc, d_work, se, &lv, stream);
+                                 nsrc, d_work, se, np, &lv, stream);
     if (levels) *levels = lv;
     if (e == -1) {
         set_msg("invalid CSR: row_ptr must start at 0, be monotone and end at nnz; columns in [0, n)");
         return TFDP_ERR_INVALID_ARG;
     }
-    if (e != 0) return check_hip((hipError_t)e, "stress");
+    if (e == -2) {
+        set_msg("a source node is outside [0, n)");
+        return TFDP_ERR_INVALID_ARG;
+    }
+    if (e != 0) return check_hip((hipError_t)e, "metrics");
     return check_hip(hipGetLastError(), "kernel launch");
+}
+
+tfdp_status tfdp_stress_sampled(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
+                                const float* d_pos, const int32_t* d_sources, int32_t nsrc, void* d_work,
+                                size_t work_bytes, double* se, int32_t* levels, hipStream_t stream) {
+    return quality_sampled(n, nnz, d_row_ptr, d_col_idx, d_pos, d_sources, nsrc, d_work, work_bytes, se, nullptr,
+                           levels, stream);
+}
+
+tfdp_status tfdp_quality_sampled(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
+                                 const float* d_pos, const int32_t* d_sources, int32_t nsrc, void* d_work,
+                                 size_t work_bytes, double* se, double* np, int32_t* levels, hipStream_t stream) {
+    if (!np) {
+        set_msg("np must point to two doubles");
+        return TFDP_ERR_INVALID_ARG;
+    }
+    return quality_sampled(n, nnz, d_row_ptr, d_col_idx, d_pos, d_sources, nsrc, d_work, work_bytes, se, np,
+                           levels, stream);
 }
 
 int32_t tfdp_phase_count(void) { return PH_COUNT; }

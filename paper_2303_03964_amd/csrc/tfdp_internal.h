@@ -200,10 +200,12 @@ void launch_b_brute(const Member* mem, const int2* map, int blocks, const int2* 
 
 // ---- layout quality (metrics.hip) ----
 size_t stress_workspace_bytes(int n, int nsrc);
-// 0, -1 (invalid CSR) or the HIP error; *se = sampled stress error,
-// *levels = BFS levels run
+// 0, -1 (invalid CSR), -2 (a source outside [0, n)) or the HIP error;
+// *se = sampled stress error,
+// np (NULL: skipped) = {NP_1, NP_2} over the same sources, *levels = BFS
+// levels run
 int stress_sampled(int n, long long nnz, const int* row_ptr, const int* col_idx, const float2* pos, const int* src,
-                   int nsrc, void* work, double* se, int* levels, hipStream_t s);
+                   int nsrc, void* work, double* se, double* np, int* levels, hipStream_t s);
 
 // ---- device helpers used by several translation units ----
 

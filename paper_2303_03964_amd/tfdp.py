@@ -77,6 +77,9 @@ _SIGS = {
     "tfdp_stress_workspace_size": (c_size_t, [c_int32, c_int32]),
     "tfdp_stress_sampled": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
                                       c_size_t, POINTER(c_double), POINTER(c_int32), c_void_p]),
+    "tfdp_quality_sampled": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
+                                       c_size_t, POINTER(c_double), POINTER(c_double), POINTER(c_int32),
+                                       c_void_p]),
     "tfdp_batch_create": (c_int32, [POINTER(c_void_p), c_int32]),
     "tfdp_batch_add": (c_int32, [c_void_p, c_void_p]),
     "tfdp_batch_remove": (c_int32, [c_void_p, c_void_p]),
@@ -231,17 +234,22 @@ def tfdp_stress_workspace_size(n, nsrc) -> int:
     return int(load_library().tfdp_stress_workspace_size(n, nsrc))
 
 
+def _metric_workspace(pos, nsrc):
+    n = int(pos.shape[0])
+    size = tfdp_stress_workspace_size(n, nsrc)
+    if size == 0:
+        raise TfdpError(-1, "invalid sizes for the metric workspace")
+    work = torch.empty(size + 256, dtype=torch.uint8, device=pos.device)
+    off = (-work.data_ptr()) % 256
+    return work[off:off + size], size
+
+
 def tfdp_stress_sampled(row_ptr, col_idx, pos, sources, stream=None):
     """Sampled stress error of the layout `pos` (device tensors: int32 CSR,
     float32 [n, 2] positions, int32 sources). Returns (SE, BFS levels)."""
     n = int(pos.shape[0])
     nsrc = int(sources.numel())
-    size = tfdp_stress_workspace_size(n, nsrc)
-    if size == 0:
-        raise TfdpError(-1, "invalid sizes for the stress workspace")
-    work = torch.empty(size + 256, dtype=torch.uint8, device=pos.device)
-    off = (-work.data_ptr()) % 256
-    work = work[off:off + size]
+    work, size = _metric_workspace(pos, nsrc)
     se = c_double()
     lv = c_int32()
     nnz = int(col_idx.numel())
@@ -249,6 +257,22 @@ def tfdp_stress_sampled(row_ptr, col_idx, pos, sources, stream=None):
                                               _ptr(sources), nsrc, _ptr(work), size, ctypes.byref(se),
                                               ctypes.byref(lv), _stream(stream)))
     return se.value, lv.value
+
+
+def tfdp_quality_sampled(row_ptr, col_idx, pos, sources, stream=None):
+    """Sampled stress error and neighbourhood preservation NP_1, NP_2 of the
+    layout `pos` over the same sources. Returns (SE, (NP_1, NP_2), BFS levels)."""
+    n = int(pos.shape[0])
+    nsrc = int(sources.numel())
+    work, size = _metric_workspace(pos, nsrc)
+    se = c_double()
+    np_ = (c_double * 2)()
+    lv = c_int32()
+    nnz = int(col_idx.numel())
+    _check(load_library().tfdp_quality_sampled(n, nnz, _ptr(row_ptr), _ptr(col_idx if nnz else None), _ptr(pos),
+                                               _ptr(sources), nsrc, _ptr(work), size, ctypes.byref(se), np_,
+                                               ctypes.byref(lv), _stream(stream)))
+    return se.value, (np_[0], np_[1]), lv.value
 
 
 def tfdp_batch_create(capacity):

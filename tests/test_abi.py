@@ -179,3 +179,17 @@ def test_stress_metric_host_checks():
                                    None) == WORKSPACE
     assert lib.tfdp_stress_sampled(10, 4, fake, fake, fake, fake, 4, fake, 16, ctypes.byref(se), None,
                                    None) == WORKSPACE
+
+
+def test_quality_metric_host_checks():
+    lib = T.load_library()
+    se = ctypes.c_double()
+    np2 = (ctypes.c_double * 2)()
+    fake = ctypes.c_void_p(0x100000)
+    # np output required; misaligned workspace rejected
+    assert lib.tfdp_quality_sampled(10, 4, fake, fake, fake, fake, 4, fake, 1 << 20, ctypes.byref(se), None, None,
+                                    None) == INVALID
+    assert lib.tfdp_quality_sampled(10, 4, fake, fake, fake, fake, 4, ctypes.c_void_p(0x100040), 1 << 20,
+                                    ctypes.byref(se), np2, None, None) == WORKSPACE
+    assert lib.tfdp_quality_sampled(10, 4, fake, fake, fake, fake, 65, fake, 1 << 20, ctypes.byref(se), np2, None,
+                                    None) == INVALID

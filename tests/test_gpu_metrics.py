@@ -73,3 +73,83 @@ def test_invalid_csr_is_rejected(T):
     src = torch.tensor([0], dtype=torch.int32).cuda()
     with pytest.raises(T.TfdpError):
         T.tfdp_stress_sampled(rp, ci, p, src)
+
+
+def gpu_quality(T, g, pos, sources):
+    import torch
+    rp = torch.as_tensor(g.row_ptr, dtype=torch.int32).cuda()
+    ci = torch.as_tensor(g.col_idx, dtype=torch.int32).cuda()
+    p = torch.as_tensor(pos, dtype=torch.float32).cuda()
+    src = torch.as_tensor(np.asarray(sources), dtype=torch.int32).cuda()
+    return T.tfdp_quality_sampled(rp, ci, p, src)
+
+
+def np_case(case):
+    rng = np.random.default_rng(11)
+    if case == "sbm_1k":
+        w = sg.sbm_1k()
+        g, pos = w.graph, sg.uniform_positions(w.graph.n, 4, -20, 20)
+        src = rng.choice(g.n, 64, replace=False)
+    elif case == "two_components_isolated":
+        # two components plus isolated nodes (empty rings), some of them sources
+        a = sg.sbm([150, 150], 0.05, 0.01, 5)
+        b = sg.sbm([100, 100], 0.05, 0.01, 6)
+        e = np.concatenate([a.edges(), b.edges() + a.n])
+        g = sg.csr_from_edges(a.n + b.n + 5, e)
+        pos = sg.uniform_positions(g.n, 7, -10, 10)
+        src = np.concatenate([rng.choice(a.n + b.n, 20, replace=False), [g.n - 1, g.n - 3]])
+    elif case == "grid_ties":
+        # the lattice's own integer coordinates (node i at column i % 316,
+        # row i // 316): rings are mostly preserved and many distances tie
+        # exactly, so the k-th nearest is often decided by the node index
+        w = sg.mesh_100k()
+        g = w.graph
+        idx = np.arange(g.n)
+        pos = np.stack([idx % 316, idx // 316], axis=1).astype(np.float32)
+        src = rng.choice(g.n, 64, replace=False)
+    elif case == "coincident":
+        # every node at one point: all distances tie
+        w = sg.sbm_1k()
+        g = w.graph
+        pos = np.full((g.n, 2), 3.25, dtype=np.float32)
+        src = rng.choice(g.n, 9, replace=False)
+    else:
+        # jittered lattice coordinates: high NP without ties
+        w = sg.mesh_100k()
+        g = w.graph
+        idx = np.arange(g.n)
+        pos = (np.stack([idx % 316, idx // 316], axis=1)
+               + sg.uniform_positions(g.n, 8, -0.3, 0.3)).astype(np.float32)
+        src = rng.choice(g.n, 33, replace=False)
+    return g, pos, src
+
+
+@pytest.mark.parametrize("case", ["sbm_1k", "two_components_isolated", "grid_ties", "coincident", "mesh_100k"])
+def test_sampled_np_matches_oracle(T, case):
+    g, pos, src = np_case(case)
+    se, nps, levels = gpu_quality(T, g, pos, src)
+    se_only, _ = gpu_se(T, g, pos, src)
+    assert se == se_only or (np.isnan(se) and np.isnan(se_only))
+    for r in (1, 2):
+        want = om.neighborhood_preservation(pos, g.row_ptr, g.col_idx, r, nodes=[int(s) for s in src])
+        say(f"{case}: n={g.n} NP_{r} gpu {nps[r - 1]:.15f} oracle {want:.15f}")
+        # the same sets on both sides: equal up to the order of the mean
+        assert abs(nps[r - 1] - want) <= 1e-12
+        if case in ("grid_ties", "mesh_100k"):
+            assert want > 0.3  # the case exercises large overlaps
+
+
+def test_np_without_rings_is_nan(T):
+    g = sg.csr_from_edges(6, np.array([[0, 1]]))
+    pos = sg.uniform_positions(6, 2, 0, 1)
+    se, nps, _ = gpu_quality(T, g, pos, [3, 4])
+    assert np.isnan(nps[0]) and np.isnan(nps[1]) and np.isnan(se)
+
+
+def test_source_out_of_range_is_rejected(T):
+    g = sg.csr_from_edges(6, np.array([[0, 1], [1, 2]]))
+    pos = sg.uniform_positions(6, 2, 0, 1)
+    with pytest.raises(T.TfdpError, match="source"):
+        gpu_quality(T, g, pos, [1, 6])
+    with pytest.raises(T.TfdpError, match="source"):
+        gpu_se(T, g, pos, [-1])
