@@ -93,6 +93,30 @@ def measured_traffic(kernel_file):
     return rec.get("hbm_bytes_per_launch")
 
 
+def gather_reference(torch, lay, stream, reps=20):
+    """Time of a plain gather of every CSR entry's neighbour position
+    (torch.index_select with the int32 column indices, 8-byte rows) on the
+    same graph and stream: a reference for the random-gather part of the
+    edge pass, which reads the same neighbours (and writes no copy)."""
+    pos = lay.pos.view(-1, 2)
+    col = lay.col_idx
+    with torch.cuda.stream(stream):
+        out = torch.empty((col.numel(), 2), dtype=pos.dtype, device=pos.device)
+        for _ in range(3):
+            torch.index_select(pos, 0, col, out=out)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            torch.index_select(pos, 0, col, out=out)
+        e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del out
+    return {"op": "torch.index_select of the nnz neighbour positions (int32 indices, 8-byte rows)",
+            "avg_ms": ms, "gathers": int(col.numel()), "gathers_per_s": col.numel() / (ms * 1e-3)}
+
+
 def cpu_baseline(w, iters):
     """The FP64 oracle (as it stands) on the same graph: `iters` iterations of
     forces + move at k = 1 from the initial positions."""
@@ -377,6 +401,7 @@ def main():
     quality = {"se_sampled": se, "np1_sampled": nps[0], "np2_sampled": nps[1], "sources": 64,
                "bfs_levels": levels, "seconds": round(time.perf_counter() - t_q, 4)}
 
+    gather_ref = gather_reference(torch, lay, stream)
     gm_ms, gm_n = ph1["gather_update"]
     avg_ms = gm_ms / max(gm_n, 1)
     m1 = w.n_int  # k = 1
@@ -422,6 +447,7 @@ def main():
             "algorithmic_bytes_per_launch": bytes_launch,
             "avg_launch_ms": avg_ms,
             "launches": gm_n,
+            "gather_reference": gather_ref,
         },
         "phase_ms_k1": phases,
         "phase_ms_k23": phases_rest,

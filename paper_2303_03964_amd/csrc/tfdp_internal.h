@@ -142,15 +142,20 @@ __device__ __forceinline__ int xcd_pair_block(int phys, int nb) {
 }
 
 // Column slices for n nodes with slices of at most slice_nodes columns, and
-// an upper bound of the edge-pass blocks of all slices together (per slice
-// at most ceil(n/4) light blocks and one block per row with more than
-// kGroupEdges entries, plus one).
+// an upper bound of the edge-pass blocks of all slices together. Per slice:
+// H heavy rows (more than kGroupEdges entries; H <= entries / 513 over all
+// slices) get a block each; a wave group ends with kGroupRows rows (at most
+// n / 64 such groups), at the last row (one), before a heavy row (at most
+// H), or when the next row's entries do not fit, in which case the group and
+// the next one hold more than kGroupEdges entries together (fewer than
+// entries / 256 such groups); four groups per block.
 inline int edge_slices(long long n, long long slice_nodes) {
     long long s = (n + slice_nodes - 1) / slice_nodes;
     return (int)(s < 1 ? 1 : (s > kMaxSlices ? kMaxSlices : s));
 }
 inline long long edge_blocks_bound(long long n, long long nnz, long long slice_nodes) {
-    return (long long)edge_slices(n, slice_nodes) * ((n + 3) / 4 + 1) + nnz / (kGroupEdges + 1) + 1;
+    return (long long)edge_slices(n, slice_nodes) * ((n / kGroupRows + 2) / 4 + 3) + nnz / (2 * kGroupEdges) +
+           2 * (nnz / (kGroupEdges + 1)) + 1;
 }
 void launch_brute(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx,
                   int n, DevState* st, const ModelArgs& a, int t,
