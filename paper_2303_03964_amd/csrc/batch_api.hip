@@ -23,7 +23,7 @@ enum BPhase { B_BIN_COUNT, B_BIN_SCAN, B_BIN_SCATTER, B_SPREAD, B_ROWFFT, B_COLC
 
 struct BLaunch {
     int phase;
-    int k, logL, nw;  // B_BRUTE: nw = offset of the tick map (one entry per member), k = members
+    int k, len, nw;  // B_BRUTE: nw = offset of the tick map (one entry per member), k = members
     size_t off;       // first map entry
     int blocks;
     size_t lds;
@@ -181,9 +181,9 @@ tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s,
     std::stable_sort(order.begin(), order.end(), bigger_first);
     std::stable_sort(brute.begin(), brute.end(), bigger_first);
     std::vector<int2> map;
-    auto emit = [&](int phase, int k, int logL, int nw, size_t lds, const std::vector<int>& who,
+    auto emit = [&](int phase, int k, int len, int nw, size_t lds, const std::vector<int>& who,
                     const std::vector<int>& blocks) {
-        BLaunch L{phase, k, logL, nw, map.size(), 0, lds};
+        BLaunch L{phase, k, len, nw, map.size(), 0, lds};
         for (size_t q = 0; q < who.size(); ++q)
             for (int j = 0; j < blocks[q]; ++j)
                 map.push_back(make_int2(entry_of(who[q], ks[who[q]] > 0 ? ks[who[q]] : 1), j));
@@ -207,7 +207,7 @@ tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s,
         emit(B_BIN_SCAN, 0, 0, 0, 0, order, bs);
         emit(B_BIN_SCATTER, 0, 0, 0, lds_s, order, bsc);
     }
-    // spreading: classes (k, logL, nw)
+    // spreading: classes (k, L, nw)
     {
         std::map<std::tuple<int, int, int>, std::vector<int>> cls;
         for (int i : order) {
@@ -215,7 +215,7 @@ tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s,
             const Geom g = make_geom(h->p.n_int, ks[i]);
             int nw, nkb;
             spread_dims(bufs_for(h, ks[i]), g, &nw, &nkb);
-            cls[std::make_tuple(ks[i], g.logL, nw)].push_back(i);
+            cls[std::make_tuple(ks[i], g.L, nw)].push_back(i);
         }
         for (auto& kv : cls) {
             std::vector<int> blocks;
@@ -234,7 +234,7 @@ tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s,
     // row FFTs, column pass, inverse rows: classes by FFT length
     {
         std::map<int, std::vector<int>> cls;
-        for (int i : order) cls[make_geom(b->mem[i]->p.n_int, ks[i]).logL].push_back(i);
+        for (int i : order) cls[make_geom(b->mem[i]->p.n_int, ks[i]).L].push_back(i);
         for (int phase : {B_ROWFFT, B_COLCONV, B_ROWIFFT})
             for (auto& kv : cls) {
                 std::vector<int> blocks;
@@ -316,10 +316,10 @@ void enqueue_iter(tfdp_batch* b, const Comp& c, int j, hipStream_t s) {
             case B_BIN_COUNT: launch_b_bin_count(mem, map, L.blocks, L.lds, b->d_t, j, s); break;
             case B_BIN_SCAN: launch_b_bin_scan(mem, map, L.blocks, b->d_t, j, s); break;
             case B_BIN_SCATTER: launch_b_bin_scatter(mem, map, L.blocks, L.lds, j, s); break;
-            case B_SPREAD: launch_b_spread(L.k, L.logL, L.nw, mem, map, L.blocks, L.lds, s); break;
-            case B_ROWFFT: launch_b_rowfft(L.logL, mem, map, L.blocks, s); break;
-            case B_COLCONV: launch_b_colconv(L.logL, mem, map, L.blocks, s); break;
-            case B_ROWIFFT: launch_b_rowifft(L.logL, mem, map, L.blocks, s); break;
+            case B_SPREAD: launch_b_spread(L.k, L.len, L.nw, mem, map, L.blocks, L.lds, s); break;
+            case B_ROWFFT: launch_b_rowfft(L.len, mem, map, L.blocks, s); break;
+            case B_COLCONV: launch_b_colconv(L.len, mem, map, L.blocks, s); break;
+            case B_ROWIFFT: launch_b_rowifft(L.len, mem, map, L.blocks, s); break;
             case B_EDGES: launch_b_edges(L.k, mem, map, L.blocks, b->d_t, j, s); break;
             default: launch_b_brute(mem, map, L.blocks, c.d_map + L.nw, L.k, j, s); break;
         }

@@ -12,8 +12,8 @@
 // to its grid node, which keeps float32 away from the cancellation of two
 // large terms.
 //
-// The linear convolution is embedded in an L x L circulant (L = power of two
-// >= 2M) and computed with 2D FFTs:
+// The linear convolution is embedded in an L x L circulant (L = the smallest
+// 2^a or 3 * 2^a >= 2M, see make_geom) and computed with 2D FFTs:
 //   spread   one block per chunk of an interval row's nodes (sorted by the
 //            binning pass): per-wave LDS copies of the row's k grid rows,
 //            summed in a fixed order, written as one partial row set
@@ -28,11 +28,12 @@
 //   rowifft  RB potential rows per block from column tiles: inverse real
 //            FFTs, (phi_1, G_x, G_y) written per grid node.
 //
-// Every FFT is a task of one wave: a Stockham autosort FFT with radix-8
-// passes (and one radix-4 or radix-2 pass), each lane holding its points in
-// registers between LDS exchanges. A task is one transform of length
-// L >= 512 or 512/L transforms of a shorter length, so every task has 512 or
-// more points and needs no block-wide barrier.
+// Every FFT is a task of one wave: a Stockham autosort FFT with a radix-3
+// pass when 3 divides L, then radix-8 passes (and one radix-4 or radix-2
+// pass), each lane holding its points in registers between LDS exchanges. A
+// task is F transforms (FftLen<L>::F: 512 or more points for L = 2^a, 1536
+// for L = 3 * 2^a, so that every pass gives each lane whole butterflies) and
+// needs no block-wide barrier.
 #include <climits>
 
 #include "tfdp_internal.h"
@@ -103,42 +104,63 @@ __device__ __forceinline__ void dft8(float2* v) {
     v[7] = csub(b[6], b[7]);
 }
 
+// 3-point DFT: X1,2 = v0 - (v1 + v2)/2 -/+ i sin(2 pi/3) (v1 - v2) (forward;
+// the signs of the i terms swap for the inverse).
+template <bool INV>
+__device__ __forceinline__ void dft3(float2* v) {
+    const float c = 0.86602540378443865f;
+    const float2 t1 = cadd(v[1], v[2]);
+    const float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+    const float2 d = csub(v[1], v[2]);
+    const float2 t3 = INV ? make_float2(-c * d.y, c * d.x) : make_float2(c * d.y, -c * d.x);
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(t2, t3);
+    v[2] = csub(t2, t3);
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dft_r(float2* v) {
     if constexpr (R == 8) dft8<INV>(v);
     else if constexpr (R == 4) dft4<INV>(v);
+    else if constexpr (R == 3) dft3<INV>(v);
     else dft2<INV>(v);
 }
 
-// One Stockham pass of radix 2^LOGR over a task of F transforms of length
-// L = 2^LOGL (F L >= 512, contiguous in LDS). 2^LOGNS: length of the
-// sub-transforms already combined. Every lane owns NITEMS/64 butterflies;
-// all reads of the wave precede its writes (LDS executes a wave's
-// operations in order), so the pass is in place.
-template <int LOGL, int LOGR, int LOGNS, bool INV>
+// Transforms per wave task for length L.
+template <int L>
+struct FftLen {
+    static constexpr bool R3 = (L % 3) == 0;
+    static constexpr int F = fft_task_ffts(L);
+    static_assert(F >= 1 && (R3 ? 1536 % L == 0 : (L & (L - 1)) == 0), "FFT length");
+};
+
+// One Stockham pass of radix R over a task of F transforms of length L
+// (contiguous in LDS); NS: length of the sub-transforms already combined.
+// Every lane owns F L / (64 R) butterflies; all reads of the wave precede its
+// writes (LDS executes a wave's operations in order), so the pass is in
+// place.
+template <int L, int R, int NS, bool INV>
 __device__ __forceinline__ void wave_pass(float2* buf, const float2* __restrict__ tw, int lane) {
-    constexpr int L = 1 << LOGL;
-    constexpr int R = 1 << LOGR;
-    constexpr int F = L < 512 ? 512 / L : 1;
-    constexpr int LOGLR = LOGL - LOGR;
-    constexpr int NITEMS = F * L / R;
+    constexpr int F = FftLen<L>::F;
+    constexpr int N = L / R;             // butterflies per transform
+    constexpr int NITEMS = F * N;
     constexpr int IPL = NITEMS / 64;
-    constexpr int TSHIFT = LOGL - LOGNS - LOGR;  // twiddle index = k r 2^TSHIFT
-    static_assert(NITEMS % 64 == 0, "task size");
+    constexpr int TSTEP = L / (NS * R);  // twiddle index = k r TSTEP
+    static_assert(NITEMS % 64 == 0 && L % (NS * R) == 0, "task size");
     float2 v[IPL][R];
 #pragma unroll
     for (int it = 0; it < IPL; ++it) {
         const int item = lane + it * 64;
-        const int f = item >> LOGLR;
-        const int j = item & ((1 << LOGLR) - 1);
-        const int k = j & ((1 << LOGNS) - 1);
-        const float2* src = buf + (f << LOGL) + j;
+        const int f = item / N;
+        const int j = item % N;
+        const int k = j % NS;
+        const float2* src = buf + f * L + j;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[it][r] = src[r << LOGLR];
-        if (LOGNS > 0) {
+        for (int r = 0; r < R; ++r) v[it][r] = src[r * N];
+        if (NS > 1) {
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                float2 w = tw[(k * r) << TSHIFT];
+                float2 w = tw[k * r * TSTEP];
                 if (INV) w.y = -w.y;
                 v[it][r] = cmul(v[it][r], w);
             }
@@ -149,39 +171,58 @@ __device__ __forceinline__ void wave_pass(float2* buf, const float2* __restrict_
 #pragma unroll
     for (int it = 0; it < IPL; ++it) {
         const int item = lane + it * 64;
-        const int f = item >> LOGLR;
-        const int j = item & ((1 << LOGLR) - 1);
-        const int k = j & ((1 << LOGNS) - 1);
-        float2* dst = buf + (f << LOGL) + ((j >> LOGNS) << (LOGNS + LOGR)) + k;
+        const int f = item / N;
+        const int j = item % N;
+        const int k = j % NS;
+        float2* dst = buf + f * L + (j / NS) * (NS * R) + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) dst[r << LOGNS] = v[it][r];
+        for (int r = 0; r < R; ++r) dst[r * NS] = v[it][r];
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int LOGL, bool INV, int LOGNS = 0>
+template <int L, bool INV, int NS = 1>
 __device__ __forceinline__ void wave_fft_passes(float2* buf, const float2* __restrict__ tw, int lane) {
-    constexpr int REM = LOGL - LOGNS;
-    if constexpr (REM >= 3) {
-        wave_pass<LOGL, 3, LOGNS, INV>(buf, tw, lane);
-        wave_fft_passes<LOGL, INV, LOGNS + 3>(buf, tw, lane);
-    } else if constexpr (REM == 2) {
-        wave_pass<LOGL, 2, LOGNS, INV>(buf, tw, lane);
-    } else if constexpr (REM == 1) {
-        wave_pass<LOGL, 1, LOGNS, INV>(buf, tw, lane);
+    if constexpr (NS == 1 && FftLen<L>::R3) {
+        wave_pass<L, 3, 1, INV>(buf, tw, lane);
+        wave_fft_passes<L, INV, 3>(buf, tw, lane);
+    } else {
+        constexpr int REM = L / NS;  // a power of two
+        if constexpr (REM >= 8) {
+            wave_pass<L, 8, NS, INV>(buf, tw, lane);
+            wave_fft_passes<L, INV, NS * 8>(buf, tw, lane);
+        } else if constexpr (REM == 4) {
+            wave_pass<L, 4, NS, INV>(buf, tw, lane);
+        } else if constexpr (REM == 2) {
+            wave_pass<L, 2, NS, INV>(buf, tw, lane);
+        }
     }
 }
 
-// FFT task of one wave: F = max(1, 512/L) contiguous transforms of length
-// L = 2^LOGL; tw[j] = exp(-2 pi i j / L), j < L. Unnormalised; INV uses the
-// conjugate roots.
-template <int LOGL, bool INV>
+// FFT task of one wave: F contiguous transforms of length L; tw[j] =
+// exp(-2 pi i j / L), j < L. Unnormalised; INV uses the conjugate roots.
+template <int L, bool INV>
 __device__ __forceinline__ void wave_fft(float2* buf, const float2* __restrict__ tw, int lane) {
-    wave_fft_passes<LOGL, INV, 0>(buf, tw, lane);
+    wave_fft_passes<L, INV, 1>(buf, tw, lane);
 }
 
-template <int LOGL>
-constexpr int task_ffts() { return (1 << LOGL) < 512 ? 512 / (1 << LOGL) : 1; }
+template <int L>
+constexpr int task_ffts() { return FftLen<L>::F; }
+
+// Every FFT length make_geom can choose: 2^a (64 .. 2048) and 3 * 2^a
+// (384, 768, 1536).
+#define TFDP_L_SWITCH(len, CALL)        \
+    switch (len) {                      \
+        case 64: CALL(64); break;       \
+        case 128: CALL(128); break;     \
+        case 256: CALL(256); break;     \
+        case 384: CALL(384); break;     \
+        case 512: CALL(512); break;     \
+        case 768: CALL(768); break;     \
+        case 1024: CALL(1024); break;   \
+        case 1536: CALL(1536); break;   \
+        default: CALL(2048); break;     \
+    }
 
 __global__ void k_twiddles(float2* tw, int L) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -204,14 +245,14 @@ __device__ __forceinline__ int signed_offset(int r, int M, int L) {
 // RBK kernel rows make RBK transforms. Column tiles of RB (RBK) consecutive
 // rows are stored with one RB * 8-byte write per column; pairs of logical
 // blocks share an XCD so that a line is filled from fewer L2s.
-template <int LOGL>
+template <int L>
 struct RowTile {
     // few rows per block at small L so that a 256 x 256 grid still makes
     // 128 blocks (measured: RB 8 -> 2 took the k = 1 row passes at N_int 256
     // from 17.5 + 11.2 us to 10.3 + 8.5 us)
-    static constexpr int RB = LOGL <= 9 ? 2 : 4;
+    static constexpr int RB = L <= 512 ? 2 : 4;
     static constexpr int RBK = 8;
-    static constexpr int THREADS = LOGL <= 9 ? 256 : 512;
+    static constexpr int THREADS = L <= 512 ? 256 : 512;
 };
 
 // Allow dynamic LDS beyond 64 KB (gfx950 has 160 KB per workgroup); once per kernel.
@@ -231,7 +272,7 @@ static void allow_big_lds(Kern k) {
 // K(a, b) + i H_x(a, b); the result is real, its even part the row spectrum of
 // K, minus its odd part the row spectrum of H_x divided by i.
 // bid < max_chunks: chunk block; otherwise lb = logical kernel-row block.
-template <int K, int LOGL>
+template <int K, int L>
 __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float gamma, float tau, int nw, int bid,
                                             int lb) {
     extern __shared__ float4 smem4[];
@@ -300,10 +341,9 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
         for (int i = threadIdx.x; i < per; i += blockDim.x) out[i] = acc[i];
         return;
     }
-    constexpr int L = 1 << LOGL;
-    constexpr int F = task_ffts<LOGL>();
+    constexpr int F = task_ffts<L>();
     constexpr int TL = F * L;
-    constexpr int RBK = RowTile<LOGL>::RBK;
+    constexpr int RBK = RowTile<L>::RBK;
     constexpr int NKT = (RBK + F - 1) / F;
     float2* z = reinterpret_cast<float2*>(smem4);
     const int H = g.H;
@@ -311,7 +351,7 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
     const Box bx = b.st->box;
     const double s = bx.h / (double)K;
     for (int i = threadIdx.x; i < NKT * TL; i += blockDim.x) {
-        const int f = i >> LOGL, a = i & (L - 1);
+        const int f = i / L, a = i % L;
         const int r = r0 + f;
         float2 v = make_float2(0.f, 0.f);
         if (f < RBK && r < L) {
@@ -325,7 +365,7 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
         z[i] = v;
     }
     __syncthreads();
-    for (int tk = w; tk < NKT; tk += nw) wave_fft<LOGL, false>(z + tk * TL, b.tw, lane);
+    for (int tk = w; tk < NKT; tk += nw) wave_fft<L, false>(z + tk * TL, b.tw, lane);
     __syncthreads();
     for (int i = threadIdx.x; i < H * RBK; i += blockDim.x) {
         const int f = i % RBK, u = i / RBK;
@@ -333,12 +373,12 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
         if (r >= L) continue;
         const float2* zr = z + f * L;
         const float a = zr[u].x;
-        const float c = zr[(L - u) & (L - 1)].x;
+        const float c = zr[u == 0 ? 0 : L - u].x;
         b.kcol[(size_t)u * L + r] = make_float2(0.5f * (a + c), -0.5f * (a - c));
     }
 }
 
-template <int K, int LOGL>
+template <int K, int L>
 __global__ __launch_bounds__(512) void k_spread(Bufs b, Geom g, float gamma, float tau, int nw, int nkb) {
     const int bid = blockIdx.x;
     int lb = -1;
@@ -346,22 +386,22 @@ __global__ __launch_bounds__(512) void k_spread(Bufs b, Geom g, float gamma, flo
         lb = xcd_pair_block(bid - b.max_chunks, nkb);
         if (lb < 0) return;
     }
-    spread_body<K, LOGL>(b, g, gamma, tau, nw, bid, lb);
+    spread_body<K, L>(b, g, gamma, tau, nw, bid, lb);
 }
 
 // Batched: map entry {member, block}; blocks past the member's max_chunks
 // are its logical kernel-row blocks.
-template <int K, int LOGL>
+template <int K, int L>
 __global__ __launch_bounds__(512) void kb_spread(const Member* __restrict__ mem, const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
-    spread_body<K, LOGL>(m.b, m.g, m.a.gamma, m.a.tau, m.nw, e.y, e.y - m.b.max_chunks);
+    spread_body<K, L>(m.b, m.g, m.a.gamma, m.a.tau, m.nw, e.y, e.y - m.b.max_chunks);
 }
 
 Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
     const size_t per = (size_t)g.k * g.m * 3 * sizeof(unsigned long long);  // <= 74 KB (M <= 1023)
     const int nw = 8;
-    const int F = g.L < 512 ? 512 / g.L : 1;
+    const int F = fft_task_ffts(g.L);
     const int RBK = 8;
     const size_t kern = (size_t)((RBK + F - 1) / F) * F * g.L * sizeof(float2);
     const size_t lds = per > kern ? per : kern;
@@ -371,53 +411,43 @@ Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
     return Dims{b.max_chunks + nkb, nw * 64, lds};
 }
 
-template <int K, int LOGL>
+template <int K, int L>
 static void launch_spread_t(const Bufs& b, const Geom& g, float gamma, float tau, hipStream_t s) {
-    static_assert(RowTile<LOGL>::RBK == 8, "spread_dims assumes 8 kernel rows per block");
+    static_assert(RowTile<L>::RBK == 8, "spread_dims assumes 8 kernel rows per block");
     int nw, nkb;
     const Dims d = spread_dims(b, g, &nw, &nkb);
-    hipLaunchKernelGGL((k_spread<K, LOGL>), dim3(b.max_chunks + xcd_pair_grid(nkb)), dim3(d.block), d.lds, s, b, g,
+    hipLaunchKernelGGL((k_spread<K, L>), dim3(b.max_chunks + xcd_pair_grid(nkb)), dim3(d.block), d.lds, s, b, g,
                        gamma, tau, nw, nkb);
 }
 
-template <int K, int LOGL>
+template <int K, int L>
 static void launch_b_spread_t(const Member* mem, const int2* map, int blocks, int nw, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((kb_spread<K, LOGL>), dim3(blocks), dim3(nw * 64), lds, s, mem, map);
+    hipLaunchKernelGGL((kb_spread<K, L>), dim3(blocks), dim3(nw * 64), lds, s, mem, map);
 }
 
 template <int K>
-static void launch_b_spread_k(int logL, int nw, const Member* mem, const int2* map, int blocks, size_t lds,
+static void launch_b_spread_k(int len, int nw, const Member* mem, const int2* map, int blocks, size_t lds,
                               hipStream_t s) {
-    switch (logL) {
-        case 6: launch_b_spread_t<K, 6>(mem, map, blocks, nw, lds, s); break;
-        case 7: launch_b_spread_t<K, 7>(mem, map, blocks, nw, lds, s); break;
-        case 8: launch_b_spread_t<K, 8>(mem, map, blocks, nw, lds, s); break;
-        case 9: launch_b_spread_t<K, 9>(mem, map, blocks, nw, lds, s); break;
-        case 10: launch_b_spread_t<K, 10>(mem, map, blocks, nw, lds, s); break;
-        default: launch_b_spread_t<K, 11>(mem, map, blocks, nw, lds, s); break;
-    }
+#define TFDP_C(LL) launch_b_spread_t<K, LL>(mem, map, blocks, nw, lds, s)
+    TFDP_L_SWITCH(len, TFDP_C)
+#undef TFDP_C
 }
 
-void launch_b_spread(int k, int logL, int nw, const Member* mem, const int2* map, int blocks, size_t lds,
+void launch_b_spread(int k, int len, int nw, const Member* mem, const int2* map, int blocks, size_t lds,
                      hipStream_t s) {
     if (blocks <= 0) return;
     switch (k) {
-        case 1: launch_b_spread_k<1>(logL, nw, mem, map, blocks, lds, s); break;
-        case 2: launch_b_spread_k<2>(logL, nw, mem, map, blocks, lds, s); break;
-        default: launch_b_spread_k<3>(logL, nw, mem, map, blocks, lds, s); break;
+        case 1: launch_b_spread_k<1>(len, nw, mem, map, blocks, lds, s); break;
+        case 2: launch_b_spread_k<2>(len, nw, mem, map, blocks, lds, s); break;
+        default: launch_b_spread_k<3>(len, nw, mem, map, blocks, lds, s); break;
     }
 }
 
 template <int K>
 static void launch_spread_k(const Bufs& b, const Geom& g, float gamma, float tau, hipStream_t s) {
-    switch (g.logL) {
-        case 6: launch_spread_t<K, 6>(b, g, gamma, tau, s); break;
-        case 7: launch_spread_t<K, 7>(b, g, gamma, tau, s); break;
-        case 8: launch_spread_t<K, 8>(b, g, gamma, tau, s); break;
-        case 9: launch_spread_t<K, 9>(b, g, gamma, tau, s); break;
-        case 10: launch_spread_t<K, 10>(b, g, gamma, tau, s); break;
-        default: launch_spread_t<K, 11>(b, g, gamma, tau, s); break;
-    }
+#define TFDP_C(LL) launch_spread_t<K, LL>(b, g, gamma, tau, s)
+    TFDP_L_SWITCH(g.L, TFDP_C)
+#undef TFDP_C
 }
 
 void launch_spread(const Bufs& b, const Geom& g, float gamma, float tau, hipStream_t s) {
@@ -432,13 +462,12 @@ void launch_spread(const Bufs& b, const Geom& g, float gamma, float tau, hipStre
 
 // RB grid rows per (logical) block. Transforms of row pair q:
 // 3q = q1 + i qdx (row 2q), 3q+1 = qdy(2q) + i qdy(2q+1), 3q+2 = q1 + i qdx (row 2q+1).
-template <int LOGL>
+template <int L>
 __device__ __forceinline__ void rowfft_body(const Bufs& b, const Geom& g, int lb) {
     extern __shared__ float2 z[];
-    constexpr int L = 1 << LOGL;
-    constexpr int F = task_ffts<LOGL>();
+    constexpr int F = task_ffts<L>();
     constexpr int TL = F * L;
-    constexpr int RB = RowTile<LOGL>::RB;
+    constexpr int RB = RowTile<L>::RB;
     constexpr int NQT = (3 * RB / 2 + F - 1) / F;
     const int M = g.m, H = g.H, K = g.k;
     const int lane = threadIdx.x & 63;
@@ -472,7 +501,7 @@ __device__ __forceinline__ void rowfft_body(const Bufs& b, const Geom& g, int lb
         reinterpret_cast<float*>(z + (3 * q + 1) * L + x)[r & 1] = sy;
     }
     __syncthreads();
-    for (int tk = w; tk < NQT; tk += nwav) wave_fft<LOGL, false>(z + tk * TL, b.tw, lane);
+    for (int tk = w; tk < NQT; tk += nwav) wave_fft<L, false>(z + tk * TL, b.tw, lane);
     __syncthreads();
     // unpack with Z(u) and Z(L-u); r fastest so each column gets RB consecutive rows
     for (int i = threadIdx.x; i < 3 * H * RB; i += blockDim.x) {
@@ -481,7 +510,7 @@ __device__ __forceinline__ void rowfft_body(const Bufs& b, const Geom& g, int lb
         const int y = y0 + r;
         if (y >= M) continue;
         const int q = r >> 1, odd = r & 1;
-        const int um = (L - u) & (L - 1);
+        const int um = u == 0 ? 0 : L - u;
         float2 v;
         if (ch < 2) {
             const float2* zr = z + (3 * q + (odd ? 2 : 0)) * L;
@@ -499,47 +528,42 @@ __device__ __forceinline__ void rowfft_body(const Bufs& b, const Geom& g, int lb
     }
 }
 
-template <int LOGL>
-__global__ __launch_bounds__(RowTile<LOGL>::THREADS) void k_rowfft(Bufs b, Geom g, int nqb) {
+template <int L>
+__global__ __launch_bounds__(RowTile<L>::THREADS) void k_rowfft(Bufs b, Geom g, int nqb) {
     const int lb = xcd_pair_block(blockIdx.x, nqb);
     if (lb < 0) return;
-    rowfft_body<LOGL>(b, g, lb);
+    rowfft_body<L>(b, g, lb);
 }
 
-template <int LOGL>
-__global__ __launch_bounds__(RowTile<LOGL>::THREADS) void kb_rowfft(const Member* __restrict__ mem,
+template <int L>
+__global__ __launch_bounds__(RowTile<L>::THREADS) void kb_rowfft(const Member* __restrict__ mem,
                                                                      const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
-    rowfft_body<LOGL>(m.b, m.g, e.y);
+    rowfft_body<L>(m.b, m.g, e.y);
 }
 
-template <int LOGL>
+template <int L>
 static Dims rowfft_dims_t(const Geom& g, int* nqb) {
-    constexpr int F = task_ffts<LOGL>();
-    constexpr int TL = F * (1 << LOGL);
-    constexpr int RB = RowTile<LOGL>::RB;
+    constexpr int F = task_ffts<L>();
+    constexpr int TL = F * L;
+    constexpr int RB = RowTile<L>::RB;
     constexpr int NQT = (3 * RB / 2 + F - 1) / F;
     *nqb = (g.m + RB - 1) / RB;
-    return Dims{*nqb, RowTile<LOGL>::THREADS, (size_t)NQT * TL * sizeof(float2)};
+    return Dims{*nqb, RowTile<L>::THREADS, (size_t)NQT * TL * sizeof(float2)};
 }
 
-template <int LOGL>
+template <int L>
 static void launch_rowfft_t(const Bufs& b, const Geom& g, hipStream_t s) {
     int nqb;
-    const Dims d = rowfft_dims_t<LOGL>(g, &nqb);
-    hipLaunchKernelGGL(k_rowfft<LOGL>, dim3(xcd_pair_grid(nqb)), dim3(d.block), d.lds, s, b, g, nqb);
+    const Dims d = rowfft_dims_t<L>(g, &nqb);
+    hipLaunchKernelGGL(k_rowfft<L>, dim3(xcd_pair_grid(nqb)), dim3(d.block), d.lds, s, b, g, nqb);
 }
 
 void launch_rowfft(const Bufs& b, const Geom& g, hipStream_t s) {
-    switch (g.logL) {
-        case 6: launch_rowfft_t<6>(b, g, s); break;
-        case 7: launch_rowfft_t<7>(b, g, s); break;
-        case 8: launch_rowfft_t<8>(b, g, s); break;
-        case 9: launch_rowfft_t<9>(b, g, s); break;
-        case 10: launch_rowfft_t<10>(b, g, s); break;
-        default: launch_rowfft_t<11>(b, g, s); break;
-    }
+#define TFDP_C(LL) launch_rowfft_t<LL>(b, g, s)
+    TFDP_L_SWITCH(g.L, TFDP_C)
+#undef TFDP_C
 }
 
 // ----------------------------------------------------------------- column pass
@@ -550,12 +574,10 @@ void launch_rowfft(const Bufs& b, const Geom& g, hipStream_t s) {
 //   Q1, Qdx, Qdy            (charge row spectra, rows y < M)
 // then phi_1 = K^ Q1, G_x = H_x^ Q1 - K^ Qdx, G_y = H_y^ Q1 - K^ Qdy (scaled by
 // 1/L^2) and three inverse column FFTs; rows y < M stored column-major.
-template <int LOGL>
+template <int L>
 __device__ __forceinline__ void colconv_body(const Bufs& b, const Geom& g, int bid) {
     extern __shared__ float2 sm2[];
-    constexpr int L = 1 << LOGL;
-    constexpr int logL = LOGL;
-    constexpr int F = task_ffts<LOGL>();
+    constexpr int F = task_ffts<L>();
     constexpr int TL = F * L;
     const int M = g.m, H = g.H;
     const int lane = threadIdx.x & 63;
@@ -566,7 +588,7 @@ __device__ __forceinline__ void colconv_body(const Bufs& b, const Geom& g, int b
     const float inv = 1.f / ((float)L * (float)L);
     // task c (0..4) of transform f covers column u0 + f
     for (int i = threadIdx.x; i < TL; i += blockDim.x) {
-        const int f = i >> logL, r = i & (L - 1);
+        const int f = i / L, r = i % L;
         const int u = u0 + f;
         float2 kr = make_float2(0.f, 0.f);
         if (u < H) kr = b.kcol[(size_t)u * L + r];
@@ -581,7 +603,7 @@ __device__ __forceinline__ void colconv_body(const Bufs& b, const Geom& g, int b
         }
     }
     __syncthreads();
-    if (w < 5) wave_fft<LOGL, false>(sm2 + w * TL, b.tw, lane);
+    if (w < 5) wave_fft<L, false>(sm2 + w * TL, b.tw, lane);
     __syncthreads();
     for (int i = threadIdx.x; i < TL; i += blockDim.x) {
         const float kk = sm2[i].x * inv;
@@ -593,7 +615,7 @@ __device__ __forceinline__ void colconv_body(const Bufs& b, const Geom& g, int b
         sm2[4 * TL + i] = make_float2(-h2 * q1.y - kk * qy.x, h2 * q1.x - kk * qy.y);
     }
     __syncthreads();
-    if (w < 3) wave_fft<LOGL, true>(sm2 + (2 + w) * TL, b.tw, lane);
+    if (w < 3) wave_fft<L, true>(sm2 + (2 + w) * TL, b.tw, lane);
     __syncthreads();
     for (int i = threadIdx.x; i < 3 * F * M; i += blockDim.x) {
         const int ch = i / (F * M), rem = i % (F * M);
@@ -603,39 +625,33 @@ __device__ __forceinline__ void colconv_body(const Bufs& b, const Geom& g, int b
     }
 }
 
-template <int LOGL>
+template <int L>
 __global__ __launch_bounds__(512) void k_colconv(Bufs b, Geom g) {
-    colconv_body<LOGL>(b, g, blockIdx.x);
+    colconv_body<L>(b, g, blockIdx.x);
 }
 
-template <int LOGL>
+template <int L>
 __global__ __launch_bounds__(512) void kb_colconv(const Member* __restrict__ mem, const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
-    colconv_body<LOGL>(m.b, m.g, e.y);
+    colconv_body<L>(m.b, m.g, e.y);
 }
 
 Dims colconv_dims(const Geom& g) {
-    const int F = g.L < 512 ? 512 / g.L : 1;
+    const int F = fft_task_ffts(g.L);
     return Dims{(g.H + F - 1) / F, 512, (size_t)5 * F * g.L * sizeof(float2)};
 }
 
-template <int LOGL>
+template <int L>
 static void launch_colconv_t(const Bufs& b, const Geom& g, hipStream_t s) {
-    static_assert(task_ffts<LOGL>() == ((1 << LOGL) < 512 ? 512 / (1 << LOGL) : 1), "colconv_dims");
     const Dims d = colconv_dims(g);
-    hipLaunchKernelGGL(k_colconv<LOGL>, dim3(d.grid), dim3(d.block), d.lds, s, b, g);
+    hipLaunchKernelGGL(k_colconv<L>, dim3(d.grid), dim3(d.block), d.lds, s, b, g);
 }
 
 void launch_colconv(const Bufs& b, const Geom& g, hipStream_t s) {
-    switch (g.logL) {
-        case 6: launch_colconv_t<6>(b, g, s); break;
-        case 7: launch_colconv_t<7>(b, g, s); break;
-        case 8: launch_colconv_t<8>(b, g, s); break;
-        case 9: launch_colconv_t<9>(b, g, s); break;
-        case 10: launch_colconv_t<10>(b, g, s); break;
-        default: launch_colconv_t<11>(b, g, s); break;
-    }
+#define TFDP_C(LL) launch_colconv_t<LL>(b, g, s)
+    TFDP_L_SWITCH(g.L, TFDP_C)
+#undef TFDP_C
 }
 
 // ----------------------------------------------------------------- inverse rows
@@ -643,13 +659,12 @@ void launch_colconv(const Bufs& b, const Geom& g, hipStream_t s) {
 // RB potential rows per block, read as column tiles. Transforms: row r holds
 // phi_1 + i G_x (task area r), row pair q holds G_y(2q) + i G_y(2q+1)
 // (area RB + q); the spectra of real rows are extended by Hermitian symmetry.
-template <int LOGL>
+template <int L>
 __device__ __forceinline__ void rowifft_body(const Bufs& b, const Geom& g, int lb) {
     extern __shared__ float2 z[];
-    constexpr int L = 1 << LOGL;
-    constexpr int F = task_ffts<LOGL>();
+    constexpr int F = task_ffts<L>();
     constexpr int TL = F * L;
-    constexpr int RB = RowTile<LOGL>::RB;
+    constexpr int RB = RowTile<L>::RB;
     constexpr int NT = (3 * RB / 2 + F - 1) / F;
     const int M = g.m, H = g.H;
     const int lane = threadIdx.x & 63;
@@ -680,7 +695,7 @@ __device__ __forceinline__ void rowifft_body(const Bufs& b, const Geom& g, int l
         z[(RB + q) * L + u] = make_float2(p[2][0].x - p[2][1].y, p[2][0].y + p[2][1].x);
     }
     __syncthreads();
-    for (int tk = w; tk < NT; tk += nwav) wave_fft<LOGL, true>(z + tk * TL, b.tw, lane);
+    for (int tk = w; tk < NT; tk += nwav) wave_fft<L, true>(z + tk * TL, b.tw, lane);
     __syncthreads();
     for (int i = threadIdx.x; i < RB * M; i += blockDim.x) {
         const int r = i / M, x = i % M;
@@ -693,63 +708,48 @@ __device__ __forceinline__ void rowifft_body(const Bufs& b, const Geom& g, int l
     }
 }
 
-template <int LOGL>
-__global__ __launch_bounds__(RowTile<LOGL>::THREADS) void k_rowifft(Bufs b, Geom g, int nrb) {
+template <int L>
+__global__ __launch_bounds__(RowTile<L>::THREADS) void k_rowifft(Bufs b, Geom g, int nrb) {
     const int lb = xcd_pair_block(blockIdx.x, nrb);
     if (lb < 0) return;
-    rowifft_body<LOGL>(b, g, lb);
+    rowifft_body<L>(b, g, lb);
 }
 
-template <int LOGL>
-__global__ __launch_bounds__(RowTile<LOGL>::THREADS) void kb_rowifft(const Member* __restrict__ mem,
+template <int L>
+__global__ __launch_bounds__(RowTile<L>::THREADS) void kb_rowifft(const Member* __restrict__ mem,
                                                                       const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
-    rowifft_body<LOGL>(m.b, m.g, e.y);
+    rowifft_body<L>(m.b, m.g, e.y);
 }
 
-template <int LOGL>
+template <int L>
 static Dims rowifft_dims_t(const Geom& g, int* nrb) {
-    constexpr int F = task_ffts<LOGL>();
-    constexpr int TL = F * (1 << LOGL);
-    constexpr int RB = RowTile<LOGL>::RB;
+    constexpr int F = task_ffts<L>();
+    constexpr int TL = F * L;
+    constexpr int RB = RowTile<L>::RB;
     constexpr int NT = (3 * RB / 2 + F - 1) / F;
     *nrb = (g.m + RB - 1) / RB;
-    return Dims{*nrb, RowTile<LOGL>::THREADS, (size_t)NT * TL * sizeof(float2)};
+    return Dims{*nrb, RowTile<L>::THREADS, (size_t)NT * TL * sizeof(float2)};
 }
 
-template <int LOGL>
+template <int L>
 static void launch_rowifft_t(const Bufs& b, const Geom& g, hipStream_t s) {
     int nrb;
-    const Dims d = rowifft_dims_t<LOGL>(g, &nrb);
-    hipLaunchKernelGGL(k_rowifft<LOGL>, dim3(xcd_pair_grid(nrb)), dim3(d.block), d.lds, s, b, g, nrb);
+    const Dims d = rowifft_dims_t<L>(g, &nrb);
+    hipLaunchKernelGGL(k_rowifft<L>, dim3(xcd_pair_grid(nrb)), dim3(d.block), d.lds, s, b, g, nrb);
 }
 
 void launch_rowifft(const Bufs& b, const Geom& g, hipStream_t s) {
-    switch (g.logL) {
-        case 6: launch_rowifft_t<6>(b, g, s); break;
-        case 7: launch_rowifft_t<7>(b, g, s); break;
-        case 8: launch_rowifft_t<8>(b, g, s); break;
-        case 9: launch_rowifft_t<9>(b, g, s); break;
-        case 10: launch_rowifft_t<10>(b, g, s); break;
-        default: launch_rowifft_t<11>(b, g, s); break;
-    }
+#define TFDP_C(LL) launch_rowifft_t<LL>(b, g, s)
+    TFDP_L_SWITCH(g.L, TFDP_C)
+#undef TFDP_C
 }
-
-#define TFDP_LOGL_SWITCH(logL, CALL)        \
-    switch (logL) {                            \
-        case 6: CALL(6); break;                \
-        case 7: CALL(7); break;                \
-        case 8: CALL(8); break;                \
-        case 9: CALL(9); break;                \
-        case 10: CALL(10); break;              \
-        default: CALL(11); break;              \
-    }
 
 Dims rowfft_dims(const Geom& g, int* nqb) {
     Dims d{};
 #define TFDP_D(LG) d = rowfft_dims_t<LG>(g, nqb)
-    TFDP_LOGL_SWITCH(g.logL, TFDP_D)
+    TFDP_L_SWITCH(g.L, TFDP_D)
 #undef TFDP_D
     return d;
 }
@@ -757,66 +757,71 @@ Dims rowfft_dims(const Geom& g, int* nqb) {
 Dims rowifft_dims(const Geom& g, int* nrb) {
     Dims d{};
 #define TFDP_D(LG) d = rowifft_dims_t<LG>(g, nrb)
-    TFDP_LOGL_SWITCH(g.logL, TFDP_D)
+    TFDP_L_SWITCH(g.L, TFDP_D)
 #undef TFDP_D
     return d;
 }
 
-void launch_b_rowfft(int logL, const Member* mem, const int2* map, int blocks, hipStream_t s) {
+void launch_b_rowfft(int len, const Member* mem, const int2* map, int blocks, hipStream_t s) {
     if (blocks <= 0) return;
-    const Geom g{1, 1, 1 << logL, logL, (1 << logL) / 2 + 1, 1};
+    const Geom g{1, 1, len, len / 2 + 1, 1};
     int nqb;
     const Dims d = rowfft_dims(g, &nqb);
 #define TFDP_L(LG) hipLaunchKernelGGL(kb_rowfft<LG>, dim3(blocks), dim3(d.block), d.lds, s, mem, map)
-    TFDP_LOGL_SWITCH(logL, TFDP_L)
+    TFDP_L_SWITCH(len, TFDP_L)
 #undef TFDP_L
 }
 
-void launch_b_colconv(int logL, const Member* mem, const int2* map, int blocks, hipStream_t s) {
+void launch_b_colconv(int len, const Member* mem, const int2* map, int blocks, hipStream_t s) {
     if (blocks <= 0) return;
-    const Geom g{1, 1, 1 << logL, logL, (1 << logL) / 2 + 1, 1};
+    const Geom g{1, 1, len, len / 2 + 1, 1};
     const Dims d = colconv_dims(g);
 #define TFDP_L(LG) hipLaunchKernelGGL(kb_colconv<LG>, dim3(blocks), dim3(d.block), d.lds, s, mem, map)
-    TFDP_LOGL_SWITCH(logL, TFDP_L)
+    TFDP_L_SWITCH(len, TFDP_L)
 #undef TFDP_L
 }
 
-void launch_b_rowifft(int logL, const Member* mem, const int2* map, int blocks, hipStream_t s) {
+void launch_b_rowifft(int len, const Member* mem, const int2* map, int blocks, hipStream_t s) {
     if (blocks <= 0) return;
-    const Geom g{1, 1, 1 << logL, logL, (1 << logL) / 2 + 1, 1};
+    const Geom g{1, 1, len, len / 2 + 1, 1};
     int nrb;
     const Dims d = rowifft_dims(g, &nrb);
 #define TFDP_L(LG) hipLaunchKernelGGL(kb_rowifft<LG>, dim3(blocks), dim3(d.block), d.lds, s, mem, map)
-    TFDP_LOGL_SWITCH(logL, TFDP_L)
+    TFDP_L_SWITCH(len, TFDP_L)
 #undef TFDP_L
 }
 
 // Large-LDS attribute for every kernel instantiation that can exceed 64 KB
 // (called once at set-up, so that no attribute call happens during stream
 // capture).
-template <int LOGL>
+template <int L>
 static void allow_big_lds_all_l() {
-    allow_big_lds(k_spread<1, LOGL>);
-    allow_big_lds(k_spread<2, LOGL>);
-    allow_big_lds(k_spread<3, LOGL>);
-    allow_big_lds(k_rowfft<LOGL>);
-    allow_big_lds(k_colconv<LOGL>);
-    allow_big_lds(k_rowifft<LOGL>);
-    allow_big_lds(kb_spread<1, LOGL>);
-    allow_big_lds(kb_spread<2, LOGL>);
-    allow_big_lds(kb_spread<3, LOGL>);
-    allow_big_lds(kb_rowfft<LOGL>);
-    allow_big_lds(kb_colconv<LOGL>);
-    allow_big_lds(kb_rowifft<LOGL>);
+    allow_big_lds(k_spread<1, L>);
+    allow_big_lds(k_spread<2, L>);
+    allow_big_lds(k_spread<3, L>);
+    allow_big_lds(k_rowfft<L>);
+    allow_big_lds(k_colconv<L>);
+    allow_big_lds(k_rowifft<L>);
+    allow_big_lds(kb_spread<1, L>);
+    allow_big_lds(kb_spread<2, L>);
+    allow_big_lds(kb_spread<3, L>);
+    allow_big_lds(kb_rowfft<L>);
+    allow_big_lds(kb_colconv<L>);
+    allow_big_lds(kb_rowifft<L>);
 }
 
 void init_kernel_attributes() {
-    allow_big_lds_all_l<6>();
-    allow_big_lds_all_l<7>();
-    allow_big_lds_all_l<8>();
-    allow_big_lds_all_l<9>();
-    allow_big_lds_all_l<10>();
-    allow_big_lds_all_l<11>();
+#define TFDP_A(LL) allow_big_lds_all_l<LL>()
+    TFDP_A(64);
+    TFDP_A(128);
+    TFDP_A(256);
+    TFDP_A(384);
+    TFDP_A(512);
+    TFDP_A(768);
+    TFDP_A(1024);
+    TFDP_A(1536);
+    TFDP_A(2048);
+#undef TFDP_A
 }
 
 }  // namespace tfdp

@@ -20,19 +20,20 @@ tfdp_status check_hip(hipError_t e, const char* what);
 
 inline int k_workspace(const tfdp_params* p) { return (p->k_mode == 1 || p->k_mode == 2) ? p->k_mode : 3; }
 
+// FFT length: the smallest 2^a >= max(64, 2M), or 3 * 2^(a-2) when that is
+// still >= 2M and one of the radix-3 lengths 384, 768, 1536 (any L >= 2M - 1
+// gives the same linear convolution; the circulant is zero in the gap).
 inline Geom make_geom(int n_int, int k) {
     Geom g;
     g.k = k;
     g.m = n_int * k;
-    int L = 64, logL = 6;
-    while (L < 2 * g.m) {
-        L <<= 1;
-        ++logL;
-    }
+    int L = 64;
+    while (L < 2 * g.m) L <<= 1;
+    const int l3 = 3 * (L / 4);
+    if (l3 >= 2 * g.m && (l3 == 384 || l3 == 768 || l3 == 1536)) L = l3;
     g.L = L;
-    g.logL = logL;
     g.H = L / 2 + 1;
-    g.cw = L >= 512 ? 1 : 512 / L;  // transforms per FFT task
+    g.cw = fft_task_ffts(L);  // transforms per FFT task
     return g;
 }
 

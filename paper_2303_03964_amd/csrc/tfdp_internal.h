@@ -43,11 +43,15 @@ struct DevState {
 struct Geom {
     int k;      // interpolation nodes per interval per axis
     int m;      // grid nodes per side, N_int * k
-    int L;      // FFT length per side (power of two, >= 2M, >= 64)
-    int logL;
+    int L;      // FFT length per side (2^a or 3 * 2^a, >= 2M, >= 64)
     int H;      // L/2 + 1 stored spectrum columns
     int cw;     // spectrum columns per block of the column pass
 };
+
+// Transforms per FFT task (one wave) of length L: 512 or more points for
+// L = 2^a, 1536 for L = 3 * 2^a (every pass then gives each of the 64 lanes
+// whole butterflies).
+__host__ __device__ constexpr int fft_task_ffts(int L) { return L % 3 == 0 ? 1536 / L : (L < 512 ? 512 / L : 1); }
 
 // Workspace views used by the kernels.
 struct Bufs {
@@ -189,11 +193,11 @@ void launch_b_bin_count(const Member* mem, const int2* map, int blocks, size_t l
                         hipStream_t s);
 void launch_b_bin_scan(const Member* mem, const int2* map, int blocks, const int* tcall, int j, hipStream_t s);
 void launch_b_bin_scatter(const Member* mem, const int2* map, int blocks, size_t lds, int j, hipStream_t s);
-void launch_b_spread(int k, int logL, int nw, const Member* mem, const int2* map, int blocks, size_t lds,
+void launch_b_spread(int k, int len, int nw, const Member* mem, const int2* map, int blocks, size_t lds,
                      hipStream_t s);
-void launch_b_rowfft(int logL, const Member* mem, const int2* map, int blocks, hipStream_t s);
-void launch_b_colconv(int logL, const Member* mem, const int2* map, int blocks, hipStream_t s);
-void launch_b_rowifft(int logL, const Member* mem, const int2* map, int blocks, hipStream_t s);
+void launch_b_rowfft(int len, const Member* mem, const int2* map, int blocks, hipStream_t s);
+void launch_b_colconv(int len, const Member* mem, const int2* map, int blocks, hipStream_t s);
+void launch_b_rowifft(int len, const Member* mem, const int2* map, int blocks, hipStream_t s);
 void launch_b_edges(int k, const Member* mem, const int2* map, int blocks, const int* tcall, int j,
                     hipStream_t s);
 void launch_b_copy(const Member* mem, const int2* map, int blocks, hipStream_t s);
