@@ -265,7 +265,7 @@ tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s,
     // exact method: one launch for all such members, then their counters
     if (!brute.empty()) {
         std::vector<int> blocks;
-        for (int i : brute) blocks.push_back((b->mem[i]->n + kThreads - 1) / kThreads);
+        for (int i : brute) blocks.push_back((b->mem[i]->n + kBruteRows - 1) / kBruteRows);
         const size_t tick = map.size();
         for (int i : brute) map.push_back(make_int2(entry_of(i, 1), 0));
         emit(B_BRUTE, (int)brute.size(), 0, (int)tick, 0, brute, blocks);

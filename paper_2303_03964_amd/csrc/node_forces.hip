@@ -367,17 +367,53 @@ void launch_edges(const float2* pos, float2* pos_out, const EdgeSlice& es, int m
     }
 }
 
-// Exact repulsion: F_i = sum_j K_ij (x_i - x_j), K_ij = (1 + d_ij^2)^-gamma
-// (Eq.11; the j = i term is zero), positions streamed through LDS tiles;
-// attraction by a per-thread row loop (used for small graphs).
+// Exact repulsion: F_i = sum_j K_ij (x_i - x_j), K_ij = (1 + tau d_ij^2)^-gamma
+// (Eq.11; the j = i term is zero), positions streamed through 256-position
+// LDS tiles; attraction by a per-lane row loop (used for small graphs).
+// A block holds kBruteRows = 64 rows, one per lane; its four waves sum
+// interleaved quarters of every tile (8 positions per LDS batch) and wave 0
+// adds the four sums in a fixed order, then finishes its rows.
 // Columns are read through the 26-bit column mask, so the packed edge-pass
 // entries (column | row-in-group << 26) serve as well as a plain CSR.
+template <bool G2>
+__device__ __forceinline__ void brute_term(float2 p, float2 q, float tau, float gamma, float& frx, float& fry) {
+    const float dx = p.x - q.x;
+    const float dy = p.y - q.y;
+    const float u = 1.f + tau * (dx * dx + dy * dy);
+    float kk;
+    if constexpr (G2) {
+        const float r = __builtin_amdgcn_rcpf(u);  // u >= 1: hardware reciprocal, <= 1 ulp
+        kk = r * r;
+    } else {
+        kk = powf(u, -gamma);
+    }
+    frx += kk * dx;
+    fry += kk * dy;
+}
+
+template <bool G2>
+__device__ __forceinline__ void brute_tile(const float2* tile, int j0, int j1, float2 p, float tau, float gamma,
+                                           float& frx, float& fry) {
+    int jj = j0;
+    for (; jj + 8 <= j1; jj += 8) {
+        float2 q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] = tile[jj + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) brute_term<G2>(p, q[u], tau, gamma, frx, fry);
+    }
+    for (; jj < j1; ++jj) brute_term<G2>(p, tile[jj], tau, gamma, frx, fry);
+}
+
 __device__ __forceinline__ void brute_body(const float2* __restrict__ pos, int n, float2* __restrict__ pos_out,
                                            const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
                                            DevState* st, const ModelArgs& a, int t, float2* f_rep, float2* f_att,
                                            float2* f_tot, int bid) {
     __shared__ float2 tile[kThreads];
-    const int i = bid * blockDim.x + threadIdx.x;
+    __shared__ float2 part[kThreads / 64 - 1][64];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int i = bid * kBruteRows + lane;
     const bool active = i < n;
     const float2 p = active ? pos[i] : make_float2(0.f, 0.f);
     const bool g2 = a.gamma == 2.0f;
@@ -388,38 +424,33 @@ __device__ __forceinline__ void brute_body(const float2* __restrict__ pos, int n
         tile[threadIdx.x] = j < n ? pos[j] : make_float2(0.f, 0.f);
         __syncthreads();
         const int cnt = min(kThreads, n - base);
-        for (int jj = 0; jj < cnt; ++jj) {
-            const float2 q = tile[jj];
-            const float dx = p.x - q.x;
-            const float dy = p.y - q.y;
-            const float u = 1.f + tau * (dx * dx + dy * dy);
-            float kk;
-            if (g2) {
-                const float r = 1.f / u;
-                kk = r * r;
-            } else {
-                kk = powf(u, -a.gamma);
-            }
-            frx += kk * dx;
-            fry += kk * dy;
-        }
+        const int j0 = w * 64;
+        const int j1 = min(j0 + 64, cnt);
+        if (g2)
+            brute_tile<true>(tile, j0, j1, p, tau, a.gamma, frx, fry);
+        else
+            brute_tile<false>(tile, j0, j1, p, tau, a.gamma, frx, fry);
         __syncthreads();
     }
+    if (w > 0) part[w - 1][lane] = make_float2(frx, fry);
+    __syncthreads();
+    if (w != 0 || !active) return;
+    const float2 s1 = part[0][lane], s2 = part[1][lane], s3 = part[2][lane];
+    frx = (frx + s1.x) + (s2.x + s3.x);
+    fry = (fry + s1.y) + (s2.y + s3.y);
     float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
-    if (active) {
-        float sax = 0.f, say = 0.f;
-        const int e1 = row_ptr[i + 1];
-        const float* __restrict__ aw = a.att_w;
-        for (int e = row_ptr[i]; e < e1; ++e) {
-            const int j = col_idx[e] & 0x3ffffff;
-            float ax, ay;
-            edge_term(p.x, p.y, pos[j], a.beta, tau, ax, ay);
-            const float wgt = aw ? 0.5f * (aw[i] + aw[j]) : 1.f;
-            sax += wgt * ax;
-            say += wgt * ay;
-        }
-        node_output(i, p, frx, fry, sax, say, a, t, st, pos_out, f_rep, f_att, f_tot, xmin, ymin, xmax, ymax);
+    float sax = 0.f, say = 0.f;
+    const int e1 = row_ptr[i + 1];
+    const float* __restrict__ aw = a.att_w;
+    for (int e = row_ptr[i]; e < e1; ++e) {
+        const int j = col_idx[e] & 0x3ffffff;
+        float ax, ay;
+        edge_term(p.x, p.y, pos[j], a.beta, tau, ax, ay);
+        const float wgt = aw ? 0.5f * (aw[i] + aw[j]) : 1.f;
+        sax += wgt * ax;
+        say += wgt * ay;
     }
+    node_output(i, p, frx, fry, sax, say, a, t, st, pos_out, f_rep, f_att, f_tot, xmin, ymin, xmax, ymax);
 }
 
 __global__ __launch_bounds__(kThreads) void k_brute(const float2* __restrict__ pos, int n,
@@ -460,7 +491,7 @@ void launch_b_brute(const Member* mem, const int2* map, int blocks, const int2* 
 void launch_brute(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx, int n,
                   DevState* st, const ModelArgs& a, int t, float2* f_rep, float2* f_att, float2* f_tot,
                   hipStream_t s) {
-    const int blocks = (n + kThreads - 1) / kThreads;
+    const int blocks = (n + kBruteRows - 1) / kBruteRows;
     hipLaunchKernelGGL(k_brute, dim3(blocks), dim3(kThreads), 0, s, pos, n, pos_out, row_ptr, col_idx,
                        st, a, t, f_rep, f_att, f_tot);
 }
