@@ -255,11 +255,15 @@ struct RowTile {
     static constexpr int THREADS = L <= 512 ? 256 : 512;
 };
 
-// Allow dynamic LDS beyond 64 KB (gfx950 has 160 KB per workgroup); once per kernel.
+// Allow dynamic LDS beyond 64 KB (gfx950 has 160 KB per workgroup, static
+// and dynamic together); once per kernel.
 template <class Kern>
 static void allow_big_lds(Kern k) {
+    hipFuncAttributes fa;
+    int stat = 0;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k)) == hipSuccess) stat = (int)fa.sharedSizeBytes;
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
+                              160 * 1024 - stat);
 }
 
 // ----------------------------------------------------------------- spread + kernel rows
