@@ -52,9 +52,10 @@ EXACT_MAX_N = 1024  # at most this many nodes: the exact O(n^2) method
 
 
 def fft_rounded(n_int: int, slack: float = 1.25) -> int:
-    """The FFT length per side is the power of two >= 2 N_int k: a grid just
-    above a power of two doubles the FFT length of every pass. Round N_int
-    down to that power of two when it exceeds it by at most `slack`."""
+    """The FFT length per side is the smallest 2^a (or 3 * 2^a for 384, 768,
+    1536) >= 2 N_int k: a grid just above a power of two takes a longer FFT
+    in every pass. Round N_int down to that power of two when it exceeds it
+    by at most `slack`."""
     p = 1 << max(0, (n_int - 1).bit_length() - 1)  # largest power of two < n_int
     return p if p >= 8 and n_int <= slack * p else n_int
 
@@ -119,10 +120,15 @@ EXACT_PER_FFT_LENGTH = 12
 
 
 def fft_length(n_int: int, k: int) -> int:
+    """FFT length per side the library uses for N_int and k: the smallest
+    power of two >= max(64, 2 N_int k), or three quarters of it when that is
+    still >= 2 N_int k and one of the radix-3 lengths 384, 768, 1536."""
+    m2 = 2 * n_int * k
     L = 64
-    while L < 2 * n_int * k:
+    while L < m2:
         L *= 2
-    return L
+    l3 = 3 * L // 4
+    return l3 if l3 >= m2 and l3 in (384, 768, 1536) else L
 
 
 def final_choice(n: int, width: float, tol: float = 1e-3, consts=None):

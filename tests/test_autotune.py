@@ -63,6 +63,11 @@ def test_final_choice_prefers_exact_when_cheaper():
     k_mode, ni = autotune.final_choice(1_000_000, 300.0)
     assert k_mode == -1 and ni == autotune.MAX_N_INT_K3
     assert autotune.fft_length(64, 1) == 128 and autotune.fft_length(341, 3) == 2048
+    # radix-3 lengths where 3 * 2^a >= 2M is shorter than the power of two
+    assert [autotune.fft_length(n, 3) for n in (64, 128, 256, 300)] == [384, 768, 1536, 2048]
+    assert autotune.fft_length(192, 1) == 384 and autotune.fft_length(200, 1) == 512
+    lengths = {autotune.fft_length(n, k) for k in (1, 2, 3) for n in range(1, 342)}
+    assert lengths == {64, 128, 256, 384, 512, 768, 1024, 1536, 2048}
 
 
 def test_start_params():

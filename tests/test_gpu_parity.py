@@ -159,32 +159,16 @@ def test_coincident_nodes_and_empty_graph(T):
     lay.close()
 
 
-def fft_length(n_int, k):
-    """FFT length per side the library picks: the smallest power of two
-    >= max(64, 2M), or three quarters of it when that is still >= 2M and one
-    of the radix-3 lengths 384, 768, 1536 (M = n_int k)."""
-    m2 = 2 * n_int * k
-    L = 64
-    while L < m2:
-        L *= 2
-    l3 = 3 * L // 4
-    return l3 if l3 >= m2 and l3 in (384, 768, 1536) else L
-
-
 @pytest.mark.parametrize("k,n_int", [(1, 32), (1, 64), (1, 128), (1, 192), (1, 256), (1, 341), (2, 96), (2, 192),
                                      (2, 256), (3, 256), (3, 300)])
 def test_every_fft_length(T, k, n_int):
     # each FFT length (2^a and 3 * 2^a) on a ragged uniform graph
-    L = fft_length(n_int, k)
+    from paper_2303_03964_amd import autotune
+    L = autotune.fft_length(n_int, k)
     say(f"k={k} n_int={n_int}: L={L}")
     g = sg.sbm([3000, 2011], 0.002, 0.0005, 71)
     pos = sg.uniform_positions(g.n, 72, -30.0, 30.0)
     check(T, g, pos, k, n_int)
-
-
-def test_fft_length_rule_covers_every_length():
-    lengths = {fft_length(n, k) for k in (1, 2, 3) for n in range(1, 342)}
-    assert lengths == {64, 128, 256, 384, 512, 768, 1024, 1536, 2048}
 
 
 def test_two_nodes_pair(T):
