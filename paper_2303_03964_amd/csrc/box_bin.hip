@@ -6,7 +6,7 @@
 // the spreading pass can accumulate every row of the grid in LDS without
 // global atomics:
 //   bin_count   per block of kBinChunk nodes: LDS histogram of interval rows
-//   bin_scan    per interval row: exclusive scan of the per-block counts
+//   bin_scan    exclusive scan of the per-block counts of every row
 //   bin_scatter per block: slots inside the block's part of each row by
 //               LDS atomics, positions written to their slot
 #include "tfdp_internal.h"
@@ -150,15 +150,31 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* lds /* kThreads/
     return base + x - v;
 }
 
-// One block per interval row: exclusive scan of its per-block counts in
-// place, total into bucket_cnt.
-// Block 0 also resets slot set `reset_set` for the coming update and
-// advances the iteration counter.
+// Exclusive scan of every interval row's per-block counts in place, totals
+// into bucket_cnt: one block per row, or, for graphs of at most
+// kSerialScanBlocks binning blocks, one block for all rows with a row per
+// thread (bin_scan_dims). Block 0 also resets slot set `reset_set` for the
+// coming update and advances the iteration counter.
+constexpr int kSerialScanBlocks = 32;
+
 __device__ __forceinline__ void bin_scan_body(const Bufs& b, int reset_set, int c) {
     __shared__ int lds[kThreads / 64 + 1];
     if (c == 0) {
         if (threadIdx.x < kBoxSlots) reset_slot(b.st, reset_set, threadIdx.x);
         if (threadIdx.x == 0) b.st->t += 1;
+    }
+    if (b.nblk <= kSerialScanBlocks) {
+        for (int r = threadIdx.x; r < b.n_int; r += blockDim.x) {
+            int* row = b.blkcnt + (size_t)r * b.nblk;
+            int carry = 0;
+            for (int i = 0; i < b.nblk; ++i) {
+                const int v = row[i];
+                row[i] = carry;
+                carry += v;
+            }
+            b.bucket_cnt[r] = carry;
+        }
+        return;
     }
     int* row = b.blkcnt + (size_t)c * b.nblk;
     int carry = 0;
@@ -241,7 +257,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restri
 }
 
 Dims bin_count_dims(const Bufs& b) { return Dims{b.nblk, kThreads, (size_t)b.n_int * sizeof(int)}; }
-Dims bin_scan_dims(const Bufs& b) { return Dims{b.n_int, kThreads, 0}; }
+Dims bin_scan_dims(const Bufs& b) { return Dims{b.nblk <= kSerialScanBlocks ? 1 : b.n_int, kThreads, 0}; }
 Dims bin_scatter_dims(const Bufs& b) {
     return Dims{b.nblk, kThreads, (size_t)(2 * b.n_int + kThreads / 64 + 1) * sizeof(int)};
 }
