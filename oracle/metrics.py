@@ -81,12 +81,24 @@ def ring_neighbours(n, row_ptr, col_idx, r):
     return out
 
 
+def sampled_rings(n, row_ptr, col_idx, r, nodes):
+    """N_G(i, r) for the listed nodes only, from their hop distances (the
+    same sets as ring_neighbours, without a search from every node)."""
+    d = graph_distances(n, row_ptr, col_idx, list(nodes))
+    return {int(i): set(int(v) for v in np.nonzero((d[q] >= 1) & (d[q] <= r))[0]) for q, i in enumerate(nodes)}
+
+
 def neighborhood_preservation(pos, row_ptr, col_idx, r, nodes=None):
-    """NP_r (Sec. 4, Metrics). Brute-force layout distances per node."""
+    """NP_r (Sec. 4, Metrics). Brute-force layout distances per node; with
+    ``nodes`` the mean over those nodes (sampled estimate)."""
     x = np.asarray(pos, dtype=np.float64)
     n = x.shape[0]
-    rings = ring_neighbours(n, row_ptr, col_idx, r)
-    sel = range(n) if nodes is None else nodes
+    if nodes is None:
+        rings = ring_neighbours(n, row_ptr, col_idx, r)
+        sel = range(n)
+    else:
+        sel = [int(i) for i in nodes]
+        rings = sampled_rings(n, row_ptr, col_idx, r, sel)
     vals = []
     idx = np.arange(n)
     for i in sel:

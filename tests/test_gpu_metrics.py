@@ -153,3 +153,30 @@ def test_source_out_of_range_is_rejected(T):
         gpu_quality(T, g, pos, [1, 6])
     with pytest.raises(T.TfdpError, match="source"):
         gpu_se(T, g, pos, [-1])
+
+
+def test_quality_1m_bench_configuration(T):
+    """SE, NP_1 and NP_2 on the 1M-node Chung-Lu graph after 40 layout
+    iterations, from the first 16 of the 64 seeded sources bench.py uses
+    (the oracle's distances and sorts over 1M nodes take seconds per
+    source), against the oracle metrics over the same sources."""
+    import torch
+    w = sg.chung_lu_1m()
+    g = w.graph
+    p = T.tfdp_params_default(n_int=w.n_int, total_iters=w.iters)
+    lay = T.Layout(g.row_ptr, g.col_idx, w.pos0, p)
+    lay.step(40)
+    torch.cuda.synchronize()
+    pos = lay.pos.cpu().numpy()
+    src = np.random.default_rng(20230307).choice(g.n, 64, replace=False)[:16]
+    se, nps, levels = T.tfdp_quality_sampled(lay.row_ptr, lay.col_idx, lay.pos,
+                                             torch.as_tensor(src, dtype=torch.int32).cuda())
+    say(f"1M: device metrics done (SE {se:.6f}); oracle SE ...")
+    want = om.stress_error(pos.astype(np.float64), g.row_ptr, g.col_idx, sources=src)
+    say(f"1M: SE gpu {se:.12f} oracle {want:.12f}, BFS levels {levels}")
+    assert abs(se - want) <= 1e-9 * abs(want)
+    for r in (1, 2):
+        want = om.neighborhood_preservation(pos, g.row_ptr, g.col_idx, r, nodes=[int(s) for s in src])
+        say(f"1M: NP_{r} gpu {nps[r - 1]:.15f} oracle {want:.15f}")
+        assert abs(nps[r - 1] - want) <= 1e-12
+    lay.close()

@@ -449,6 +449,41 @@ def test_np_known_case():
     # nodes 2,3,4: ring {0}, 1-NN {0} -> 1; node 5: ring {1}, 1-NN {1} -> 1
     assert abs(np1 - (1 + 1 / 3 + 1 + 1 + 1 + 1) / 6) < 1e-15
     assert om.relative_error(0.9, 1.0) == pytest.approx(-0.1)
+    # sampled: the mean over the listed nodes only (node 1 alone: 1/3)
+    assert abs(om.neighborhood_preservation(x, rp, ci, 1, nodes=[1]) - 1 / 3) < 1e-15
+    assert abs(om.neighborhood_preservation(x, rp, ci, 1, nodes=[0, 1]) - (1 + 1 / 3) / 2) < 1e-15
+
+
+def test_sampled_rings_equal_searched_rings():
+    # rings from hop distances (sampled NP) against the explicit search from
+    # every node, on a graph with several components and isolated nodes
+    rng = np.random.default_rng(73)
+    n = 300
+    edges = set()
+    while len(edges) < 420:
+        u, v = rng.integers(0, 260, 2)
+        if u != v:
+            edges.add((min(u, v), max(u, v)))
+    rp, ci = csr_of(n, sorted(edges))
+    nodes = list(rng.choice(n, 40, replace=False))
+    for r in (1, 2, 3):
+        full = om.ring_neighbours(n, rp, ci, r)
+        samp = om.sampled_rings(n, rp, ci, r, nodes)
+        assert all(samp[int(i)] == full[int(i)] for i in nodes)
+    x = rng.normal(size=(n, 2))
+    for r in (1, 2):
+        a = om.neighborhood_preservation(x, rp, ci, r, nodes=nodes)
+        full = om.ring_neighbours(n, rp, ci, r)
+        vals = []
+        for i in nodes:
+            ng = full[int(i)]
+            if not ng:
+                continue
+            d2 = ((x - x[i]) ** 2).sum(1)
+            d2[i] = np.inf
+            nl = set(np.lexsort((np.arange(n), d2))[: len(ng)].tolist())
+            vals.append(len(ng & nl) / len(ng | nl))
+        assert abs(a - np.mean(vals)) < 1e-15
 
 
 # --------------------------------------------------------------- generalised t-force and local refinement
