@@ -195,10 +195,11 @@ void tfdp_layout_destroy(tfdp_layout* h);
 /* Thread-local text for the last failure or warning ("" if none). */
 const char* tfdp_last_error(void);
 
-/* Launch iteration pairs of one k as captured HIP graphs (default on; a
- * graph per k, parity and buffer orientation is captured on first use on
- * the step's stream and dropped by tfdp_layout_set_params). Off: every
- * kernel is launched directly. Profiling (below) always launches directly. */
+/* Launch groups of eight (else two) iterations of one k as captured HIP
+ * graphs (default on; a graph per group size, k, parity and buffer
+ * orientation is captured on first use on the step's stream and dropped by
+ * tfdp_layout_set_params). Off: every kernel is launched directly.
+ * Profiling (below) always launches directly. */
 tfdp_status tfdp_layout_set_graphs(tfdp_layout* h, int32_t enable);
 
 /* Per-phase timing with HIP events recorded on the launch stream around the
@@ -256,10 +257,11 @@ tfdp_status tfdp_quality_sampled(int32_t n, int64_t nnz, const int32_t* d_row_pt
  * parameters, grid and iteration counter) together: every phase of an
  * iteration is one launch per class of graphs that share the kernel shape
  * (k, FFT length, spreading block), whose blocks each work on one graph, and
- * iteration pairs are captured as HIP graphs. Each member's positions and
- * counter after tfdp_batch_step(b, iters) are bit-identical to those after
- * tfdp_layout_step(h, iters) on that handle alone: the blocks of a batched
- * launch run the same kernel code on the same data partition.
+ * groups of eight (else two) iterations are captured as HIP graphs. Each
+ * member's positions and counter after tfdp_batch_step(b, iters) are
+ * bit-identical to those after tfdp_layout_step(h, iters) on that handle
+ * alone: the blocks of a batched launch run the same kernel code on the same
+ * data partition.
  *
  * The batch references the handles (it does not own them): remove a handle
  * before destroying it. A handle may be in at most one batch at a time and
@@ -288,8 +290,8 @@ int32_t tfdp_batch_count(const tfdp_batch* b);
  * or counter changes since the last call cost one stream synchronisation.
  * Asynchronous failures are reported per member by tfdp_layout_sync_status. */
 tfdp_status tfdp_batch_step(tfdp_batch* b, int32_t iters, hipStream_t stream);
-/* Capture iteration pairs as HIP graphs (default on; the stream must then
- * not be the legacy default stream). */
+/* Capture groups of iterations as HIP graphs (default on; the stream must
+ * then not be the legacy default stream). */
 tfdp_status tfdp_batch_set_graphs(tfdp_batch* b, int32_t enable);
 /* Free the batch and its device tables (the members stay valid). */
 void tfdp_batch_destroy(tfdp_batch* b);

@@ -4,8 +4,8 @@
 // block shape) whose blocks are listed in a device map {member entry, block};
 // each block runs the plain kernel's body for that graph and block, so the
 // result of every graph is bit-identical to tfdp_layout_step on it alone.
-// Iteration pairs of one composition (the k of every member) are captured as
-// HIP graphs.
+// Groups of eight (else two) iterations of one composition (the k of every
+// member) are captured as HIP graphs.
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -34,7 +34,9 @@ struct Comp {
     std::vector<int> ks;            // k per slot (0: exact method)
     std::vector<BLaunch> launches;  // one iteration, in dependency order
     int2* d_map = nullptr;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // pairs starting at an even / odd j
+    // captured groups of 2 and kGraphIters iterations starting at an even /
+    // odd j: [2 * (size == kGraphIters) + parity of j]
+    hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
     unsigned long long last_use = 0;
 };
 
@@ -326,12 +328,13 @@ void enqueue_iter(tfdp_batch* b, const Comp& c, int j, hipStream_t s) {
     }
 }
 
-hipGraphExec_t pair_graph(tfdp_batch* b, Comp& c, int jpar, hipStream_t s) {
-    hipGraphExec_t& ex = c.gexec[jpar];
+// Graph of `iters` (2 or kGraphIters) iterations of composition c starting
+// at a j of parity jpar (the kernels use j only through its parity).
+hipGraphExec_t group_graph(tfdp_batch* b, Comp& c, int iters, int jpar, hipStream_t s) {
+    hipGraphExec_t& ex = c.gexec[2 * (iters == 2 ? 0 : 1) + jpar];
     if (ex) return ex;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
-    enqueue_iter(b, c, jpar, s);
-    enqueue_iter(b, c, jpar + 1, s);
+    for (int i = 0; i < iters; ++i) enqueue_iter(b, c, jpar + i, s);
     hipGraph_t graph = nullptr;
     if (hipStreamEndCapture(s, &graph) != hipSuccess || !graph) return nullptr;
     if (hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
@@ -474,19 +477,27 @@ tfdp_status tfdp_batch_step(tfdp_batch* b, int32_t iters, hipStream_t s) {
         for (int i = 0; i < nm; ++i) ks[i] = k_at(b->mem[i]->p, b->mem[i]->t + j);
         Comp* c = get_comp(b, ks, s, &st);
         if (!c) return st;
-        bool pair_same = j + 1 < iters;
-        if (pair_same)
+        // a captured group when every member keeps its k over the next G
+        // iterations (the schedule never lowers k: the last one decides)
+        auto same_k_through = [&](int last) {
+            if (last >= iters) return false;
             for (int i = 0; i < nm; ++i)
-                if (k_at(b->mem[i]->p, b->mem[i]->t + j + 1) != ks[i]) {
-                    pair_same = false;
-                    break;
-                }
-        if (b->graphs && pair_same) {
-            hipGraphExec_t ex = pair_graph(b, *c, j & 1, s);
+                if (k_at(b->mem[i]->p, b->mem[i]->t + last) != ks[i]) return false;
+            return true;
+        };
+        int G = 0;
+        if (b->graphs) {
+            if (same_k_through(j + kGraphIters - 1))
+                G = kGraphIters;
+            else if (same_k_through(j + 1))
+                G = 2;
+        }
+        if (G > 0) {
+            hipGraphExec_t ex = group_graph(b, *c, G, j & 1, s);
             if (ex) {
                 st = check_hip(hipGraphLaunch(ex, s), "hipGraphLaunch");
                 if (st != TFDP_OK) return st;
-                j += 2;
+                j += G;
                 continue;
             }
             (void)hipGetLastError();

@@ -286,13 +286,14 @@ void enqueue_edges(tfdp_layout* h, const float2* pos, float2* pos_out, const Buf
 }
 
 void drop_graphs(tfdp_layout* h) {
-    for (int k = 0; k < 4; ++k)
-        for (int p = 0; p < 2; ++p)
-            for (int o = 0; o < 2; ++o)
-                if (h->gexec[k][p][o]) {
-                    (void)hipGraphExecDestroy(h->gexec[k][p][o]);
-                    h->gexec[k][p][o] = nullptr;
-                }
+    for (int z = 0; z < 2; ++z)
+        for (int k = 0; k < 4; ++k)
+            for (int p = 0; p < 2; ++p)
+                for (int o = 0; o < 2; ++o)
+                    if (h->gexec[z][k][p][o]) {
+                        (void)hipGraphExecDestroy(h->gexec[z][k][p][o]);
+                        h->gexec[z][k][p][o] = nullptr;
+                    }
 }
 
 // One interpolated iteration (k >= 1) from cur to alt; `set` = t & 1 selects
@@ -306,11 +307,14 @@ void enqueue_iteration(tfdp_layout* h, int k, int set, const float2* cur, float2
     enqueue_edges(h, cur, alt, b, g, a, set ^ 1, nullptr, nullptr, nullptr, s);
 }
 
-// Graph of two consecutive iterations at k starting with slot set `parity`
-// and positions in the caller's buffer (orient 0) or the second buffer
-// (orient 1); captured on first use.
-hipGraphExec_t pair_graph(tfdp_layout* h, int k, int parity, int orient, const ModelArgs& a, hipStream_t s) {
-    hipGraphExec_t& ex = h->gexec[k][parity][orient];
+// Graph of `iters` (2 or kGraphIters, even) consecutive iterations at k
+// starting with slot set `parity` and positions in the caller's buffer
+// (orient 0) or the second buffer (orient 1), which they end in again;
+// captured on first use. Longer groups spread the cost of a graph launch
+// (a gap of several microseconds on the device) over more iterations.
+hipGraphExec_t group_graph(tfdp_layout* h, int iters, int k, int parity, int orient, const ModelArgs& a,
+                           hipStream_t s) {
+    hipGraphExec_t& ex = h->gexec[iters == 2 ? 0 : 1][k][parity][orient];
     if (ex) return ex;
     float2* A = reinterpret_cast<float2*>(h->pos);
     float2* B = h->lay.pos_alt;
@@ -320,8 +324,12 @@ hipGraphExec_t pair_graph(tfdp_layout* h, int k, int parity, int orient, const M
         B = t;
     }
     if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
-    enqueue_iteration(h, k, parity, A, B, a, s);
-    enqueue_iteration(h, k, parity ^ 1, B, A, a, s);
+    for (int i = 0; i < iters; ++i) {
+        enqueue_iteration(h, k, (parity + i) & 1, A, B, a, s);
+        float2* t = A;
+        A = B;
+        B = t;
+    }
     hipGraph_t graph = nullptr;
     if (hipStreamEndCapture(s, &graph) != hipSuccess || !graph) return nullptr;
     if (hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
@@ -586,15 +594,24 @@ static tfdp_status step_fixed_grid(tfdp_layout* h, int32_t iters, hipStream_t s)
     const bool use_graphs = h->graphs && !h->prof;
     for (int it = 0; it < iters;) {
         const int k = k_at(h->p, h->t);
-        if (use_graphs && k > 0 && it + 1 < iters && k_at(h->p, h->t + 1) == k) {
+        // a captured group when the next G iterations share k (the schedule
+        // never lowers k, so checking the last one suffices)
+        int G = 0;
+        if (use_graphs && k > 0) {
+            if (it + kGraphIters <= iters && k_at(h->p, h->t + kGraphIters - 1) == k)
+                G = kGraphIters;
+            else if (it + 2 <= iters && k_at(h->p, h->t + 1) == k)
+                G = 2;
+        }
+        if (G > 0) {
             const int orient = cur == reinterpret_cast<float2*>(h->pos) ? 0 : 1;
-            hipGraphExec_t ex = pair_graph(h, k, h->t & 1, orient, a, s);
+            hipGraphExec_t ex = group_graph(h, G, k, h->t & 1, orient, a, s);
             if (ex) {
                 tfdp_status st = check_hip(hipGraphLaunch(ex, s), "hipGraphLaunch");
                 if (st != TFDP_OK) return st;
-                h->t += 2;
-                it += 2;
-                continue;  // two swaps: cur and alt keep their roles
+                h->t += G;
+                it += G;
+                continue;  // an even number of swaps: cur and alt keep their roles
             }
             (void)hipGetLastError();
         }

@@ -76,9 +76,10 @@ struct tfdp_layout {
     int k_ws;
     int t;
     tfdp::Layout lay;
-    // captured iteration pairs: [k][parity of t at the start][orientation]
+    // captured groups of iterations: [group size: 2 or kGraphIters][k]
+    // [parity of t at the start][orientation]
     bool graphs;
-    hipGraphExec_t gexec[4][2][2];
+    hipGraphExec_t gexec[2][4][2][2];
     // profiling
     bool prof;
     std::vector<hipEvent_t> ev_pool;

@@ -16,6 +16,7 @@ constexpr int kMaxNInt = 1024;       // largest number of intervals per side
 constexpr int kGroupEdges = 512;     // CSR entries of one wave group of the edge pass
 constexpr int kSliceNodesDefault = 1 << 24;  // column slice width of the edge pass (nodes)
 constexpr int kMaxSlices = 64;
+constexpr int kGraphIters = 8;             // iterations per captured graph (even; pairs for the rest)
 constexpr int kGroupRows = 64;       // rows of one wave group of the edge pass
 constexpr int kBruteRows = 64;       // rows per block of the exact repulsion (one per lane)
 constexpr int kAutoGridMin = 50;     // automatic grid: at least this many intervals per side
