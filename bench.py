@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--workload", default="chung_lu_1m", choices=["chung_lu_1m", "mesh_100k", "sbm_1k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations (0: about 15 s of work)")
-    ap.add_argument("--repeats", type=int, default=1, help="timed repeats; value is the median")
+    ap.add_argument("--repeats", type=int, default=5, help="timed repeats of the K steps; value is the median")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload section")
     ap.add_argument("--batch-graphs", type=int, default=512)
