@@ -209,6 +209,15 @@ __device__ __forceinline__ void wave_fft(float2* buf, const float2* __restrict__
 template <int L>
 constexpr int task_ffts() { return FftLen<L>::F; }
 
+// The block's copy of the twiddle table in LDS (after its transform area):
+// the passes then read their twiddles at LDS latency instead of from L2.
+// The caller synchronises the block before the first transform.
+template <int L>
+__device__ __forceinline__ const float2* stage_twiddles(float2* lds, const float2* __restrict__ tw) {
+    for (int i = threadIdx.x; i < L; i += blockDim.x) lds[i] = tw[i];
+    return lds;
+}
+
 // Every FFT length make_geom can choose: 2^a (64 .. 2048) and 3 * 2^a
 // (384, 768, 1536).
 #define TFDP_L_SWITCH(len, CALL)        \
@@ -368,8 +377,9 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
         }
         z[i] = v;
     }
+    const float2* tws = stage_twiddles<L>(z + NKT * TL, b.tw);
     __syncthreads();
-    for (int tk = w; tk < NKT; tk += nw) wave_fft<L, false>(z + tk * TL, b.tw, lane);
+    for (int tk = w; tk < NKT; tk += nw) wave_fft<L, false>(z + tk * TL, tws, lane);
     __syncthreads();
     for (int i = threadIdx.x; i < H * RBK; i += blockDim.x) {
         const int f = i % RBK, u = i / RBK;
@@ -407,7 +417,7 @@ Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
     const int nw = 8;
     const int F = fft_task_ffts(g.L);
     const int RBK = 8;
-    const size_t kern = (size_t)((RBK + F - 1) / F) * F * g.L * sizeof(float2);
+    const size_t kern = ((size_t)((RBK + F - 1) / F) * F * g.L + g.L) * sizeof(float2);  // + twiddles
     const size_t lds = per > kern ? per : kern;
     const int nkb = (g.L + RBK - 1) / RBK;
     *nw_out = nw;
@@ -504,8 +514,9 @@ __device__ __forceinline__ void rowfft_body(const Bufs& b, const Geom& g, int lb
         z[(3 * q + ((r & 1) ? 2 : 0)) * L + x] = make_float2(s1, sx);
         reinterpret_cast<float*>(z + (3 * q + 1) * L + x)[r & 1] = sy;
     }
+    const float2* tws = stage_twiddles<L>(z + NQT * TL, b.tw);
     __syncthreads();
-    for (int tk = w; tk < NQT; tk += nwav) wave_fft<L, false>(z + tk * TL, b.tw, lane);
+    for (int tk = w; tk < NQT; tk += nwav) wave_fft<L, false>(z + tk * TL, tws, lane);
     __syncthreads();
     // unpack with Z(u) and Z(L-u); r fastest so each column gets RB consecutive rows
     for (int i = threadIdx.x; i < 3 * H * RB; i += blockDim.x) {
@@ -554,7 +565,7 @@ static Dims rowfft_dims_t(const Geom& g, int* nqb) {
     constexpr int RB = RowTile<L>::RB;
     constexpr int NQT = (3 * RB / 2 + F - 1) / F;
     *nqb = (g.m + RB - 1) / RB;
-    return Dims{*nqb, RowTile<L>::THREADS, (size_t)NQT * TL * sizeof(float2)};
+    return Dims{*nqb, RowTile<L>::THREADS, (size_t)(NQT * TL + L) * sizeof(float2)};
 }
 
 template <int L>
@@ -606,8 +617,9 @@ __device__ __forceinline__ void colconv_body(const Bufs& b, const Geom& g, int b
             sm2[(2 + ch) * TL + i] = v;
         }
     }
+    const float2* tws = stage_twiddles<L>(sm2 + 5 * TL, b.tw);
     __syncthreads();
-    if (w < 5) wave_fft<L, false>(sm2 + w * TL, b.tw, lane);
+    if (w < 5) wave_fft<L, false>(sm2 + w * TL, tws, lane);
     __syncthreads();
     for (int i = threadIdx.x; i < TL; i += blockDim.x) {
         const float kk = sm2[i].x * inv;
@@ -619,7 +631,7 @@ __device__ __forceinline__ void colconv_body(const Bufs& b, const Geom& g, int b
         sm2[4 * TL + i] = make_float2(-h2 * q1.y - kk * qy.x, h2 * q1.x - kk * qy.y);
     }
     __syncthreads();
-    if (w < 3) wave_fft<L, true>(sm2 + (2 + w) * TL, b.tw, lane);
+    if (w < 3) wave_fft<L, true>(sm2 + (2 + w) * TL, tws, lane);
     __syncthreads();
     for (int i = threadIdx.x; i < 3 * F * M; i += blockDim.x) {
         const int ch = i / (F * M), rem = i % (F * M);
@@ -643,7 +655,7 @@ __global__ __launch_bounds__(512) void kb_colconv(const Member* __restrict__ mem
 
 Dims colconv_dims(const Geom& g) {
     const int F = fft_task_ffts(g.L);
-    return Dims{(g.H + F - 1) / F, 512, (size_t)5 * F * g.L * sizeof(float2)};
+    return Dims{(g.H + F - 1) / F, 512, ((size_t)5 * F * g.L + g.L) * sizeof(float2)};
 }
 
 template <int L>
@@ -698,8 +710,9 @@ __device__ __forceinline__ void rowifft_body(const Bufs& b, const Geom& g, int l
             z[(2 * q + o) * L + u] = make_float2(p[0][o].x - p[1][o].y, p[0][o].y + p[1][o].x);
         z[(RB + q) * L + u] = make_float2(p[2][0].x - p[2][1].y, p[2][0].y + p[2][1].x);
     }
+    const float2* tws = stage_twiddles<L>(z + NT * TL, b.tw);
     __syncthreads();
-    for (int tk = w; tk < NT; tk += nwav) wave_fft<L, true>(z + tk * TL, b.tw, lane);
+    for (int tk = w; tk < NT; tk += nwav) wave_fft<L, true>(z + tk * TL, tws, lane);
     __syncthreads();
     for (int i = threadIdx.x; i < RB * M; i += blockDim.x) {
         const int r = i / M, x = i % M;
@@ -734,7 +747,7 @@ static Dims rowifft_dims_t(const Geom& g, int* nrb) {
     constexpr int RB = RowTile<L>::RB;
     constexpr int NT = (3 * RB / 2 + F - 1) / F;
     *nrb = (g.m + RB - 1) / RB;
-    return Dims{*nrb, RowTile<L>::THREADS, (size_t)NT * TL * sizeof(float2)};
+    return Dims{*nrb, RowTile<L>::THREADS, (size_t)(NT * TL + L) * sizeof(float2)};
 }
 
 template <int L>
