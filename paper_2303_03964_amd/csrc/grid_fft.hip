@@ -414,7 +414,11 @@ __global__ __launch_bounds__(512) void kb_spread(const Member* __restrict__ mem,
 
 Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
     const size_t per = (size_t)g.k * g.m * 3 * sizeof(unsigned long long);  // <= 74 KB (M <= 1023)
-    const int nw = 8;
+    // waves per block: graphs of a few ten thousand nodes have rows of tens
+    // to hundreds of nodes, which four waves spread as fast as eight, and
+    // half the threads leave room for more blocks (batched 512-graph
+    // workload: 2.29e9 -> 2.50e9 node-it/s; two waves the same, one slower)
+    const int nw = b.n <= 32768 ? 4 : 8;
     const int F = fft_task_ffts(g.L);
     const int RBK = 8;
     const size_t kern = ((size_t)((RBK + F - 1) / F) * F * g.L + g.L) * sizeof(float2);  // + twiddles
