@@ -394,15 +394,20 @@ __device__ __forceinline__ void brute_term(float2 p, float2 q, float tau, float 
 template <bool G2>
 __device__ __forceinline__ void brute_tile(const float2* tile, int j0, int j1, float2 p, float tau, float gamma,
                                            float& frx, float& fry) {
+    // four independent partial sums (positions jj + u, u mod 4) shorten the
+    // dependent chain of adds; they are combined in a fixed order
+    float sx[4] = {0.f, 0.f, 0.f, 0.f}, sy[4] = {0.f, 0.f, 0.f, 0.f};
     int jj = j0;
     for (; jj + 8 <= j1; jj += 8) {
         float2 q[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) q[u] = tile[jj + u];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) brute_term<G2>(p, q[u], tau, gamma, frx, fry);
+        for (int u = 0; u < 8; ++u) brute_term<G2>(p, q[u], tau, gamma, sx[u & 3], sy[u & 3]);
     }
-    for (; jj < j1; ++jj) brute_term<G2>(p, tile[jj], tau, gamma, frx, fry);
+    for (; jj < j1; ++jj) brute_term<G2>(p, tile[jj], tau, gamma, sx[0], sy[0]);
+    frx += (sx[0] + sx[1]) + (sx[2] + sx[3]);
+    fry += (sy[0] + sy[1]) + (sy[2] + sy[3]);
 }
 
 __device__ __forceinline__ void brute_body(const float2* __restrict__ pos, int n, float2* __restrict__ pos_out,
