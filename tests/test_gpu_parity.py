@@ -356,6 +356,34 @@ def test_multi_slice_edge_pass(T, n, slice_nodes, monkeypatch):
     lay.close()
 
 
+def test_mesh_100k_bench_configuration(T):
+    # the 100k-mesh workload in its benchmarked configuration (N_int 128;
+    # k = 3 runs at the radix-3 length 768), at the start and after 30
+    # iterations, compared in full
+    import torch
+    w = sg.mesh_100k()
+    g = w.graph
+    p = T.tfdp_params_default(n_int=w.n_int, total_iters=w.iters)
+    lay = T.Layout(g.row_ptr, g.col_idx, w.pos0, p)
+    for k in (1, 2, 3):
+        got = gpu_forces(lay, w.pos0, k)
+        want = oracle_forces(g, w.pos0, k, w.n_int)
+        errs = [rel_l2(a_, b_) for a_, b_ in zip(got, want)]
+        say(f"mesh start k={k}: {errs}")
+        assert max(errs) <= TOL
+    lay.step(30)
+    torch.cuda.synchronize()
+    assert lay.sync_status() == 0
+    pos30 = lay.pos.cpu().numpy()
+    for k in (1, 3):
+        got = gpu_forces(lay, pos30, k)
+        want = oracle_forces(g, pos30, k, w.n_int)
+        errs = [rel_l2(a_, b_) for a_, b_ in zip(got, want)]
+        say(f"mesh after 30 iterations k={k}: {errs}")
+        assert max(errs) <= TOL
+    lay.close()
+
+
 def test_chung_lu_1m_bench_configuration(T):
     # the benchmarked workload and launch configuration, compared in full
     import torch
