@@ -83,8 +83,8 @@ Member make_member(const tfdp_layout* h, int slot, int k) {
     m.alt = h->lay.pos_alt;
     m.slot = slot;
     spread_dims(m.b, m.g, &m.nw, &m.nkb);
-    rowfft_dims(m.g, &m.nqb);
-    rowifft_dims(m.g, &m.nrb);
+    rowfft_dims(m.g, &m.nqb, true);
+    rowifft_dims(m.g, &m.nrb, true);
     m.box_blocks = box_reduce_dims(h->n).grid;
     return m;
 }
@@ -244,11 +244,11 @@ tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s,
                     const Geom g = make_geom(b->mem[i]->p.n_int, ks[i]);
                     int nb = 0;
                     if (phase == B_ROWFFT)
-                        rowfft_dims(g, &nb);
+                        rowfft_dims(g, &nb, true);
                     else if (phase == B_COLCONV)
                         nb = colconv_dims(g).grid;
                     else
-                        rowifft_dims(g, &nb);
+                        rowifft_dims(g, &nb, true);
                     blocks.push_back(nb);
                 }
                 emit(phase, 0, kv.first, 0, 0, kv.second, blocks);

@@ -260,6 +260,10 @@ struct RowTile {
     // 128 blocks (measured: RB 8 -> 2 took the k = 1 row passes at N_int 256
     // from 17.5 + 11.2 us to 10.3 + 8.5 us)
     static constexpr int RB = L <= 512 ? 2 : 4;
+    // batched launches have blocks of many graphs to fill the chip: more
+    // rows per block at short lengths (512-graph workload: 2.49e9 ->
+    // 2.73e9 node-it/s with 8 rows at L <= 256; 4 and 16 rows were slower)
+    static constexpr int RBB = L <= 256 ? 8 : RB;
     static constexpr int RBK = 8;
     static constexpr int THREADS = L <= 512 ? 256 : 512;
 };
@@ -480,12 +484,11 @@ void launch_spread(const Bufs& b, const Geom& g, float gamma, float tau, hipStre
 
 // RB grid rows per (logical) block. Transforms of row pair q:
 // 3q = q1 + i qdx (row 2q), 3q+1 = qdy(2q) + i qdy(2q+1), 3q+2 = q1 + i qdx (row 2q+1).
-template <int L>
+template <int L, int RB>
 __device__ __forceinline__ void rowfft_body(const Bufs& b, const Geom& g, int lb) {
     extern __shared__ float2 z[];
     constexpr int F = task_ffts<L>();
     constexpr int TL = F * L;
-    constexpr int RB = RowTile<L>::RB;
     constexpr int NQT = (3 * RB / 2 + F - 1) / F;
     const int M = g.m, H = g.H, K = g.k;
     const int lane = threadIdx.x & 63;
@@ -551,7 +554,7 @@ template <int L>
 __global__ __launch_bounds__(RowTile<L>::THREADS) void k_rowfft(Bufs b, Geom g, int nqb) {
     const int lb = xcd_pair_block(blockIdx.x, nqb);
     if (lb < 0) return;
-    rowfft_body<L>(b, g, lb);
+    rowfft_body<L, RowTile<L>::RB>(b, g, lb);
 }
 
 template <int L>
@@ -559,14 +562,14 @@ __global__ __launch_bounds__(RowTile<L>::THREADS) void kb_rowfft(const Member* _
                                                                      const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
-    rowfft_body<L>(m.b, m.g, e.y);
+    rowfft_body<L, RowTile<L>::RBB>(m.b, m.g, e.y);
 }
 
-template <int L>
+template <int L, bool BATCHED = false>
 static Dims rowfft_dims_t(const Geom& g, int* nqb) {
     constexpr int F = task_ffts<L>();
     constexpr int TL = F * L;
-    constexpr int RB = RowTile<L>::RB;
+    constexpr int RB = BATCHED ? RowTile<L>::RBB : RowTile<L>::RB;
     constexpr int NQT = (3 * RB / 2 + F - 1) / F;
     *nqb = (g.m + RB - 1) / RB;
     return Dims{*nqb, RowTile<L>::THREADS, (size_t)(NQT * TL + L) * sizeof(float2)};
@@ -679,12 +682,11 @@ void launch_colconv(const Bufs& b, const Geom& g, hipStream_t s) {
 // RB potential rows per block, read as column tiles. Transforms: row r holds
 // phi_1 + i G_x (task area r), row pair q holds G_y(2q) + i G_y(2q+1)
 // (area RB + q); the spectra of real rows are extended by Hermitian symmetry.
-template <int L>
+template <int L, int RB>
 __device__ __forceinline__ void rowifft_body(const Bufs& b, const Geom& g, int lb) {
     extern __shared__ float2 z[];
     constexpr int F = task_ffts<L>();
     constexpr int TL = F * L;
-    constexpr int RB = RowTile<L>::RB;
     constexpr int NT = (3 * RB / 2 + F - 1) / F;
     const int M = g.m, H = g.H;
     const int lane = threadIdx.x & 63;
@@ -733,7 +735,7 @@ template <int L>
 __global__ __launch_bounds__(RowTile<L>::THREADS) void k_rowifft(Bufs b, Geom g, int nrb) {
     const int lb = xcd_pair_block(blockIdx.x, nrb);
     if (lb < 0) return;
-    rowifft_body<L>(b, g, lb);
+    rowifft_body<L, RowTile<L>::RB>(b, g, lb);
 }
 
 template <int L>
@@ -741,14 +743,14 @@ __global__ __launch_bounds__(RowTile<L>::THREADS) void kb_rowifft(const Member* 
                                                                       const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
-    rowifft_body<L>(m.b, m.g, e.y);
+    rowifft_body<L, RowTile<L>::RBB>(m.b, m.g, e.y);
 }
 
-template <int L>
+template <int L, bool BATCHED = false>
 static Dims rowifft_dims_t(const Geom& g, int* nrb) {
     constexpr int F = task_ffts<L>();
     constexpr int TL = F * L;
-    constexpr int RB = RowTile<L>::RB;
+    constexpr int RB = BATCHED ? RowTile<L>::RBB : RowTile<L>::RB;
     constexpr int NT = (3 * RB / 2 + F - 1) / F;
     *nrb = (g.m + RB - 1) / RB;
     return Dims{*nrb, RowTile<L>::THREADS, (size_t)(NT * TL + L) * sizeof(float2)};
@@ -767,17 +769,17 @@ void launch_rowifft(const Bufs& b, const Geom& g, hipStream_t s) {
 #undef TFDP_C
 }
 
-Dims rowfft_dims(const Geom& g, int* nqb) {
+Dims rowfft_dims(const Geom& g, int* nqb, bool batched) {
     Dims d{};
-#define TFDP_D(LG) d = rowfft_dims_t<LG>(g, nqb)
+#define TFDP_D(LG) d = batched ? rowfft_dims_t<LG, true>(g, nqb) : rowfft_dims_t<LG, false>(g, nqb)
     TFDP_L_SWITCH(g.L, TFDP_D)
 #undef TFDP_D
     return d;
 }
 
-Dims rowifft_dims(const Geom& g, int* nrb) {
+Dims rowifft_dims(const Geom& g, int* nrb, bool batched) {
     Dims d{};
-#define TFDP_D(LG) d = rowifft_dims_t<LG>(g, nrb)
+#define TFDP_D(LG) d = batched ? rowifft_dims_t<LG, true>(g, nrb) : rowifft_dims_t<LG, false>(g, nrb)
     TFDP_L_SWITCH(g.L, TFDP_D)
 #undef TFDP_D
     return d;
@@ -787,7 +789,7 @@ void launch_b_rowfft(int len, const Member* mem, const int2* map, int blocks, hi
     if (blocks <= 0) return;
     const Geom g{1, 1, len, len / 2 + 1, 1};
     int nqb;
-    const Dims d = rowfft_dims(g, &nqb);
+    const Dims d = rowfft_dims(g, &nqb, true);
 #define TFDP_L(LG) hipLaunchKernelGGL(kb_rowfft<LG>, dim3(blocks), dim3(d.block), d.lds, s, mem, map)
     TFDP_L_SWITCH(len, TFDP_L)
 #undef TFDP_L
@@ -806,7 +808,7 @@ void launch_b_rowifft(int len, const Member* mem, const int2* map, int blocks, h
     if (blocks <= 0) return;
     const Geom g{1, 1, len, len / 2 + 1, 1};
     int nrb;
-    const Dims d = rowifft_dims(g, &nrb);
+    const Dims d = rowifft_dims(g, &nrb, true);
 #define TFDP_L(LG) hipLaunchKernelGGL(kb_rowifft<LG>, dim3(blocks), dim3(d.block), d.lds, s, mem, map)
     TFDP_L_SWITCH(len, TFDP_L)
 #undef TFDP_L

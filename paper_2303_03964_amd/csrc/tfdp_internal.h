@@ -181,9 +181,10 @@ Dims bin_scan_dims(const Bufs& b);
 Dims bin_scatter_dims(const Bufs& b);
 // spreading: grid = chunk blocks + logical kernel-row blocks (nkb); nw waves
 Dims spread_dims(const Bufs& b, const Geom& g, int* nw, int* nkb);
-Dims rowfft_dims(const Geom& g, int* nqb);
+// batched: the row tiles of the batched kernels (more rows per block)
+Dims rowfft_dims(const Geom& g, int* nqb, bool batched = false);
 Dims colconv_dims(const Geom& g);
-Dims rowifft_dims(const Geom& g, int* nrb);
+Dims rowifft_dims(const Geom& g, int* nrb, bool batched = false);
 
 // ---- batched launchers: one launch for every map entry {member, block} ----
 // tcall: per-slot iteration counters at the start of the call; j: iteration
