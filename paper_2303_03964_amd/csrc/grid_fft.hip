@@ -371,7 +371,7 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
         const int f = i / L, a = i % L;
         const int r = r0 + f;
         float2 v = make_float2(0.f, 0.f);
-        if (f < RBK && r < L) {
+        if (f < RBK && r <= L / 2) {
             const int bt = signed_offset(r, M, L), at = signed_offset(a, M, L);
             if (bt != INT_MIN && at != INT_MIN) {
                 const double d2 = (double)tau * (s * s * ((double)at * at + (double)bt * bt));
@@ -385,14 +385,18 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
     __syncthreads();
     for (int tk = w; tk < NKT; tk += nw) wave_fft<L, false>(z + tk * TL, tws, lane);
     __syncthreads();
+    // K and H_x are even in the row offset, so rows r and L - r of the
+    // table are equal: rows 0 .. L/2 are transformed and written to both
     for (int i = threadIdx.x; i < H * RBK; i += blockDim.x) {
         const int f = i % RBK, u = i / RBK;
         const int r = r0 + f;
-        if (r >= L) continue;
+        if (r > L / 2) continue;
         const float2* zr = z + f * L;
         const float a = zr[u].x;
         const float c = zr[u == 0 ? 0 : L - u].x;
-        b.kcol[(size_t)u * L + r] = make_float2(0.5f * (a + c), -0.5f * (a - c));
+        const float2 v = make_float2(0.5f * (a + c), -0.5f * (a - c));
+        b.kcol[(size_t)u * L + r] = v;
+        if (r > 0 && r < L / 2) b.kcol[(size_t)u * L + (L - r)] = v;
     }
 }
 
@@ -427,7 +431,7 @@ Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
     const int RBK = 8;
     const size_t kern = ((size_t)((RBK + F - 1) / F) * F * g.L + g.L) * sizeof(float2);  // + twiddles
     const size_t lds = per > kern ? per : kern;
-    const int nkb = (g.L + RBK - 1) / RBK;
+    const int nkb = (g.L / 2 + 1 + RBK - 1) / RBK;  // rows 0 .. L/2
     *nw_out = nw;
     *nkb_out = nkb;
     return Dims{b.max_chunks + nkb, nw * 64, lds};
