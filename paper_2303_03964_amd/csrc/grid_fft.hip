@@ -266,6 +266,10 @@ struct RowTile {
     static constexpr int RBB = L <= 256 ? 8 : RB;
     static constexpr int RBK = 8;
     static constexpr int THREADS = L <= 512 ? 256 : 512;
+    // batched blocks at L = 768 have three transform tasks (two transforms
+    // each): four waves, so that two blocks of ~170-VGPR waves share a CU
+    // (a single grid of 384 rows keeps eight: its 96 blocks are too few)
+    static constexpr int THREADS_B = (L <= 512 || L == 768) ? 256 : 512;
 };
 
 // Allow dynamic LDS beyond 64 KB (gfx950 has 160 KB per workgroup, static
@@ -562,7 +566,7 @@ __global__ __launch_bounds__(RowTile<L>::THREADS) void k_rowfft(Bufs b, Geom g, 
 }
 
 template <int L>
-__global__ __launch_bounds__(RowTile<L>::THREADS) void kb_rowfft(const Member* __restrict__ mem,
+__global__ __launch_bounds__(RowTile<L>::THREADS_B) void kb_rowfft(const Member* __restrict__ mem,
                                                                      const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
@@ -576,7 +580,8 @@ static Dims rowfft_dims_t(const Geom& g, int* nqb) {
     constexpr int RB = BATCHED ? RowTile<L>::RBB : RowTile<L>::RB;
     constexpr int NQT = (3 * RB / 2 + F - 1) / F;
     *nqb = (g.m + RB - 1) / RB;
-    return Dims{*nqb, RowTile<L>::THREADS, (size_t)(NQT * TL + L) * sizeof(float2)};
+    constexpr int T = BATCHED ? RowTile<L>::THREADS_B : RowTile<L>::THREADS;
+    return Dims{*nqb, T, (size_t)(NQT * TL + L) * sizeof(float2)};
 }
 
 template <int L>
@@ -743,7 +748,7 @@ __global__ __launch_bounds__(RowTile<L>::THREADS) void k_rowifft(Bufs b, Geom g,
 }
 
 template <int L>
-__global__ __launch_bounds__(RowTile<L>::THREADS) void kb_rowifft(const Member* __restrict__ mem,
+__global__ __launch_bounds__(RowTile<L>::THREADS_B) void kb_rowifft(const Member* __restrict__ mem,
                                                                       const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
@@ -757,7 +762,8 @@ static Dims rowifft_dims_t(const Geom& g, int* nrb) {
     constexpr int RB = BATCHED ? RowTile<L>::RBB : RowTile<L>::RB;
     constexpr int NT = (3 * RB / 2 + F - 1) / F;
     *nrb = (g.m + RB - 1) / RB;
-    return Dims{*nrb, RowTile<L>::THREADS, (size_t)(NT * TL + L) * sizeof(float2)};
+    constexpr int T = BATCHED ? RowTile<L>::THREADS_B : RowTile<L>::THREADS;
+    return Dims{*nrb, T, (size_t)(NT * TL + L) * sizeof(float2)};
 }
 
 template <int L>
