@@ -246,7 +246,7 @@ tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s,
                     if (phase == B_ROWFFT)
                         rowfft_dims(g, &nb, true);
                     else if (phase == B_COLCONV)
-                        nb = colconv_dims(g).grid;
+                        nb = colconv_dims(g, true).grid;
                     else
                         rowifft_dims(g, &nb, true);
                     blocks.push_back(nb);

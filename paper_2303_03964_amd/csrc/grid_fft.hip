@@ -22,9 +22,10 @@
 //            transform), row spectra stored column-major in tiles of RB
 //            consecutive rows (one cache line per column); further blocks do
 //            the same for the kernel rows (K + i H_x packed)
-//   colconv  one block per group of spectrum columns: five forward column
-//            FFTs (kernel pair, three charges), spectral products, three
-//            inverse column FFTs; contiguous column reads and writes
+//   colconv  one block per one or two groups of spectrum columns: four
+//            forward column FFTs per group (kernel spectra, three charges),
+//            spectral products, three inverse column FFTs; contiguous column
+//            reads and writes
 //   rowifft  RB potential rows per block from column tiles: inverse real
 //            FFTs, (phi_1, G_x, G_y) written per grid node.
 //
@@ -599,79 +600,97 @@ void launch_rowfft(const Bufs& b, const Geom& g, hipStream_t s) {
 
 // ----------------------------------------------------------------- column pass
 
-// Columns u0 .. u0+F-1 (F = transforms per task). Forward column FFTs of
-//   C1 = FFT_b(R1 + i R2)   -> K^ = Re C1, H_x^ = i Im C1   (both real-even rows)
-//   C2 = FFT_b(s b R1)      -> H_y^ = i Im C2                (real-odd rows)
-//   Q1, Qdx, Qdy            (charge row spectra, rows y < M)
+// Column groups per block: one for a single grid; two for the batched
+// launches at L <= 256, where a group's four forward transform tasks leave
+// half of the eight waves idle and the blocks of many graphs fill the chip.
+constexpr int col_groups(int L, bool batched) { return batched && L <= 256 ? 2 : 1; }
+
+// Columns u0 .. u0 + G F - 1 (F = transforms per task, G column groups).
+// Per group, forward column FFTs of
+//   Z = FFT_b(R1 + s b R1 + i R2)  (R1 = K row spectrum and R2 = H_x row
+//       spectrum / i, both real and even in b; s b R1 real and odd in b):
+//       K^ = Re Z; Im Z = H_x^/i + H_y^/i, H_x^/i its even part in the
+//       frequency, H_y^/i its odd part
+//   Q1, Qdx, Qdy  (charge row spectra, rows y < M)
 // then phi_1 = K^ Q1, G_x = H_x^ Q1 - K^ Qdx, G_y = H_y^ Q1 - K^ Qdy (scaled by
 // 1/L^2) and three inverse column FFTs; rows y < M stored column-major.
-template <int L>
+template <int L, int G>
 __device__ __forceinline__ void colconv_body(const Bufs& b, const Geom& g, int bid) {
     extern __shared__ float2 sm2[];
     constexpr int F = task_ffts<L>();
     constexpr int TL = F * L;
+    constexpr int GT = 4 * TL;  // one group's areas: Z, Q1, Qdx, Qdy
     const int M = g.m, H = g.H;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int u0 = bid * F;
+    const int u0 = bid * G * F;
     const Box bx = b.st->box;
     const float s = (float)(bx.h / (double)g.k);
     const float inv = 1.f / ((float)L * (float)L);
-    // task c (0..4) of transform f covers column u0 + f
-    for (int i = threadIdx.x; i < TL; i += blockDim.x) {
-        const int f = i / L, r = i % L;
-        const int u = u0 + f;
+    // transform f of group gi covers column u0 + gi F + f
+    for (int i = threadIdx.x; i < G * TL; i += blockDim.x) {
+        const int gi = i / TL, j = i % TL;
+        const int f = j / L, r = j % L;
+        const int u = u0 + gi * F + f;
+        float2* a = sm2 + gi * GT;
         float2 kr = make_float2(0.f, 0.f);
         if (u < H) kr = b.kcol[(size_t)u * L + r];
         const int bt = signed_offset(r, M, L);
-        sm2[i] = kr;
-        sm2[TL + i] = make_float2(bt != INT_MIN ? s * (float)bt * kr.x : 0.f, 0.f);
+        const float e = bt != INT_MIN ? s * (float)bt * kr.x : 0.f;
+        a[j] = make_float2(kr.x + e, kr.y);
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             float2 v = make_float2(0.f, 0.f);
             if (u < H && r < M) v = b.qcol[((size_t)ch * H + u) * M + r];
-            sm2[(2 + ch) * TL + i] = v;
+            a[(1 + ch) * TL + j] = v;
         }
     }
-    const float2* tws = stage_twiddles<L>(sm2 + 5 * TL, b.tw);
+    const float2* tws = stage_twiddles<L>(sm2 + G * GT, b.tw);
     __syncthreads();
-    if (w < 5) wave_fft<L, false>(sm2 + w * TL, tws, lane);
+    static_assert(4 * G <= 8, "one forward task per wave of the 512-thread block");
+    if (w < 4 * G) wave_fft<L, false>(sm2 + w * TL, tws, lane);
     __syncthreads();
-    for (int i = threadIdx.x; i < TL; i += blockDim.x) {
-        const float kk = sm2[i].x * inv;
-        const float h1 = sm2[i].y * inv;
-        const float h2 = sm2[TL + i].y * inv;
-        const float2 q1 = sm2[2 * TL + i], qx = sm2[3 * TL + i], qy = sm2[4 * TL + i];
-        sm2[2 * TL + i] = make_float2(kk * q1.x, kk * q1.y);
-        sm2[3 * TL + i] = make_float2(-h1 * q1.y - kk * qx.x, h1 * q1.x - kk * qx.y);
-        sm2[4 * TL + i] = make_float2(-h2 * q1.y - kk * qy.x, h2 * q1.x - kk * qy.y);
+    for (int i = threadIdx.x; i < G * TL; i += blockDim.x) {
+        const int gi = i / TL, j = i % TL;
+        const int f = j / L, v = j % L;
+        float2* a = sm2 + gi * GT;
+        const float zi = a[j].y, zm = a[f * L + (v == 0 ? 0 : L - v)].y;
+        const float kk = a[j].x * inv;
+        const float h1 = 0.5f * (zi + zm) * inv;
+        const float h2 = 0.5f * (zi - zm) * inv;
+        const float2 q1 = a[TL + j], qx = a[2 * TL + j], qy = a[3 * TL + j];
+        a[TL + j] = make_float2(kk * q1.x, kk * q1.y);
+        a[2 * TL + j] = make_float2(-h1 * q1.y - kk * qx.x, h1 * q1.x - kk * qx.y);
+        a[3 * TL + j] = make_float2(-h2 * q1.y - kk * qy.x, h2 * q1.x - kk * qy.y);
     }
     __syncthreads();
-    if (w < 3) wave_fft<L, true>(sm2 + (2 + w) * TL, tws, lane);
+    if (w < 3 * G) wave_fft<L, true>(sm2 + (w / 3) * GT + (1 + w % 3) * TL, tws, lane);
     __syncthreads();
-    for (int i = threadIdx.x; i < 3 * F * M; i += blockDim.x) {
-        const int ch = i / (F * M), rem = i % (F * M);
+    for (int i = threadIdx.x; i < G * 3 * F * M; i += blockDim.x) {
+        const int gi = i / (3 * F * M), rem0 = i % (3 * F * M);
+        const int ch = rem0 / (F * M), rem = rem0 % (F * M);
         const int f = rem / M, y = rem % M;
-        const int u = u0 + f;
-        if (u < H) b.pcol[((size_t)ch * H + u) * M + y] = sm2[(2 + ch) * TL + f * L + y];
+        const int u = u0 + gi * F + f;
+        if (u < H) b.pcol[((size_t)ch * H + u) * M + y] = sm2[gi * GT + (1 + ch) * TL + f * L + y];
     }
 }
 
 template <int L>
 __global__ __launch_bounds__(512) void k_colconv(Bufs b, Geom g) {
-    colconv_body<L>(b, g, blockIdx.x);
+    colconv_body<L, col_groups(L, false)>(b, g, blockIdx.x);
 }
 
 template <int L>
 __global__ __launch_bounds__(512) void kb_colconv(const Member* __restrict__ mem, const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
-    colconv_body<L>(m.b, m.g, e.y);
+    colconv_body<L, col_groups(L, true)>(m.b, m.g, e.y);
 }
 
-Dims colconv_dims(const Geom& g) {
+Dims colconv_dims(const Geom& g, bool batched) {
     const int F = fft_task_ffts(g.L);
-    return Dims{(g.H + F - 1) / F, 512, ((size_t)5 * F * g.L + g.L) * sizeof(float2)};
+    const int G = col_groups(g.L, batched);
+    return Dims{(g.H + G * F - 1) / (G * F), 512, ((size_t)4 * G * F * g.L + g.L) * sizeof(float2)};
 }
 
 template <int L>
@@ -808,7 +827,7 @@ void launch_b_rowfft(int len, const Member* mem, const int2* map, int blocks, hi
 void launch_b_colconv(int len, const Member* mem, const int2* map, int blocks, hipStream_t s) {
     if (blocks <= 0) return;
     const Geom g{1, 1, len, len / 2 + 1, 1};
-    const Dims d = colconv_dims(g);
+    const Dims d = colconv_dims(g, true);
 #define TFDP_L(LG) hipLaunchKernelGGL(kb_colconv<LG>, dim3(blocks), dim3(d.block), d.lds, s, mem, map)
     TFDP_L_SWITCH(len, TFDP_L)
 #undef TFDP_L

@@ -183,7 +183,7 @@ Dims bin_scatter_dims(const Bufs& b);
 Dims spread_dims(const Bufs& b, const Geom& g, int* nw, int* nkb);
 // batched: the row tiles of the batched kernels (more rows per block)
 Dims rowfft_dims(const Geom& g, int* nqb, bool batched = false);
-Dims colconv_dims(const Geom& g);
+Dims colconv_dims(const Geom& g, bool batched = false);
 Dims rowifft_dims(const Geom& g, int* nrb, bool batched = false);
 
 // ---- batched launchers: one launch for every map entry {member, block} ----
