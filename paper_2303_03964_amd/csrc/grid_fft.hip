@@ -601,9 +601,11 @@ void launch_rowfft(const Bufs& b, const Geom& g, hipStream_t s) {
 // ----------------------------------------------------------------- column pass
 
 // Column groups per block: one for a single grid; two for the batched
-// launches at L <= 256, where a group's four forward transform tasks leave
-// half of the eight waves idle and the blocks of many graphs fill the chip.
-constexpr int col_groups(int L, bool batched) { return batched && L <= 256 ? 2 : 1; }
+// launches at L = 256, where a group's four forward transform tasks leave
+// half of the eight waves idle and the blocks of many graphs fill the chip
+// (at L <= 128 a graph has only 33-65 columns, and halving its few blocks
+// measured slower).
+constexpr int col_groups(int L, bool batched) { return batched && L == 256 ? 2 : 1; }
 
 // Columns u0 .. u0 + G F - 1 (F = transforms per task, G column groups).
 // Per group, forward column FFTs of
