@@ -266,7 +266,10 @@ struct RowTile {
     // 2.73e9 node-it/s with 8 rows at L <= 256; 4 and 16 rows were slower)
     static constexpr int RBB = L <= 256 ? 8 : RB;
     static constexpr int RBK = 8;
-    static constexpr int THREADS = L <= 512 ? 256 : 512;
+    // a single grid at L = 512 has only M / 2 = 128 row blocks: eight waves
+    // halve each thread's partial-row loads and column stores (the k = 1
+    // forward row pass at N_int 256: 8.0 -> 5.7 us against four waves)
+    static constexpr int THREADS = L <= 256 ? 256 : 512;
     // batched blocks at L = 768 have three transform tasks (two transforms
     // each): four waves, so that two blocks of ~170-VGPR waves share a CU
     // (a single grid of 384 rows keeps eight: its 96 blocks are too few)
