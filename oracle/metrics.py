@@ -41,10 +41,14 @@ def optimal_scale(lay_d, graph_d):
     return float(r.sum() / (r * r).sum())
 
 
-def stress_error(pos, row_ptr, col_idx, sources=None):
-    """Normalised stress error with the optimal scale, over pairs (i, j),
-    i != j, with finite graph distance. With ``sources`` the pairs are
-    restricted to rows in ``sources`` (sampled estimate)."""
+def stress_pairs(pos, row_ptr, col_idx, sources=None):
+    """Layout distances d and hop distances D of the pairs that the stress
+    error counts (Sec. 4, "Metrics"): all unordered pairs {i, j}, i != j,
+    with finite D; with ``sources`` every ordered pair (s, v), s taken from
+    ``sources`` (row q of the distance matrix belongs to sources[q]),
+    v != s, with finite D (a sampled estimate: over all nodes as sources each
+    unordered pair appears twice, which changes neither the optimal scale
+    nor the mean)."""
     x = np.asarray(pos, dtype=np.float64)
     n = x.shape[0]
     src = np.arange(n) if sources is None else np.asarray(sources)
@@ -53,8 +57,13 @@ def stress_error(pos, row_ptr, col_idx, sources=None):
     mask = np.isfinite(d) & (d > 0)
     if sources is None:
         mask &= np.arange(n)[None, :] > np.arange(n)[:, None]
-    dd = d[mask]
-    ll = lay[mask]
+    return lay[mask], d[mask]
+
+
+def stress_error(pos, row_ptr, col_idx, sources=None):
+    """Normalised stress error with the optimal scale, the mean of
+    ((s d - D) / D)^2 over the pairs of ``stress_pairs``."""
+    ll, dd = stress_pairs(pos, row_ptr, col_idx, sources)
     s = optimal_scale(ll, dd)
     return float((((s * ll - dd) / dd) ** 2).mean())
 

@@ -3,6 +3,7 @@ check that the pins catch each one. Guards the pins themselves."""
 import numpy as np
 import pytest
 
+from oracle import metrics as om
 from oracle import tfdp as ot
 import tests.test_oracle_pins as pins
 
@@ -101,3 +102,36 @@ def test_one_sided_edge_weights_are_caught(monkeypatch):
     monkeypatch.setattr(ot, "attraction", bad)
     assert fails(pins.test_local_refinement_two_nodes_closed_form)
     assert fails(pins.test_generalised_forces_are_minus_energy_gradient, 1.7, True)
+
+
+def _sampled_pairs_with(mask_rule, src_rows):
+    """stress_pairs with a planted change in how sampled rows are masked or
+    where their source positions are read."""
+    def bad(pos, row_ptr, col_idx, sources=None):
+        x = np.asarray(pos, dtype=np.float64)
+        n = x.shape[0]
+        src = np.arange(n) if sources is None else np.asarray(sources)
+        d = om.graph_distances(n, row_ptr, col_idx, src)
+        rows = src_rows(src)
+        lay = np.sqrt(((x[rows, None, :] - x[None, :, :]) ** 2).sum(-1))
+        mask = np.isfinite(d) & (d > 0)
+        mask &= mask_rule(n, src)
+        return lay[mask], d[mask]
+    return bad
+
+
+def test_upper_triangle_mask_on_sampled_rows_is_caught(monkeypatch):
+    # the all-pairs i < j rule applied to sampled rows, by node index or by
+    # row position
+    by_node = lambda n, src: np.arange(n)[None, :] > src[:, None]
+    by_row = lambda n, src: np.arange(n)[None, :] > np.arange(len(src))[:, None]
+    for rule in (by_node, by_row):
+        monkeypatch.setattr(om, "stress_pairs", _sampled_pairs_with(rule, lambda src: src))
+        assert fails(pins.test_sampled_stress_hand_computed)
+
+
+def test_sampled_rows_read_by_position_are_caught(monkeypatch):
+    monkeypatch.setattr(om, "stress_pairs",
+                        _sampled_pairs_with(lambda n, src: True, lambda src: np.arange(len(src))))
+    assert fails(pins.test_sampled_stress_hand_computed)
+    assert fails(pins.test_sampled_stress_over_all_sources_equals_all_pairs)
