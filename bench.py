@@ -6,7 +6,11 @@ binning, spreading, FFT convolution, gather, CSR attraction and the move.
 Default workload: Chung-Lu power-law graph, 1,000,000 nodes, exponent 2.5,
 mean degree 10, int32 CSR, FP32 positions uniform in [-1, 1]^2, N_int = 256,
 T = 500 iterations of the k schedule (k = 1/2/3 for 450/25/25 iterations).
-With the default --steps 500 the timed region is the whole layout.
+With --steps >= T (default 500) the timed region is the whole layout. With
+fewer steps K it is a schedule-weighted sample of it: K - 2m iterations at
+k = 1 from the start and m = round(K/20) at k = 2 and at k = 3, started from
+the positions and counters saved at the two switches by an untimed pass over
+the whole schedule (which also gives the quality of the final layout).
 
 Prints one JSON line. ``value`` = n * steps / seconds (node-iterations/s)
 with the inputs resident in HBM. ``roofline`` prices the dominant kernel
@@ -117,9 +121,10 @@ def gather_reference(torch, lay, stream, reps=20):
             "avg_ms": ms, "gathers": int(col.numel()), "gathers_per_s": col.numel() / (ms * 1e-3)}
 
 
-def cpu_baseline(w, iters):
+def cpu_baseline(w, iters, budget=15.0):
     """The FP64 oracle (as it stands) on the same graph: `iters` iterations of
-    forces + move at k = 1 from the initial positions."""
+    forces + move at k = 1 from the initial positions (iters = 0: as many as
+    fit in `budget` seconds)."""
     from oracle import tfdp as ot
     p = ot.Params(n_int=w.n_int, total_iters=w.iters, k_mode=-1)
     x = w.pos0.astype(np.float64)
@@ -128,7 +133,6 @@ def cpu_baseline(w, iters):
     c0 = time.process_time()
     s0 = time.perf_counter()
     done = 0
-    budget = 15.0
     target = iters if iters > 0 else 10 ** 9
     while done < target:
         k = ot.k_for_iteration(done, w.iters)
@@ -355,51 +359,88 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def reset():
-        lay.pos.copy_(pos0)
-        lay.iteration = 0
+    def reset(pos=pos0, t=0):
+        lay.pos.copy_(pos)
+        lay.iteration = t
         torch.cuda.synchronize()
 
+    # untimed pass over the whole schedule (T iterations from the start): the
+    # quality of the final layout, and the states at the k = 2 and k = 3
+    # switches from which a timed region shorter than T starts its k = 2 and
+    # k = 3 iterations
+    T_all = w.iters
+    t_k2, t_k3 = (9 * T_all) // 10, (19 * T_all) // 20
+    reset()
+    lay.step(t_k2)
+    pos_k2 = lay.pos.clone()
+    lay.step(t_k3 - t_k2)
+    pos_k3 = lay.pos.clone()
+    lay.step(T_all - t_k3)
+    torch.cuda.synchronize()
+    if lay.sync_status() != 0:
+        raise RuntimeError("non-finite positions in the schedule pass")
+    # quality of the final layout: stress error and neighbourhood preservation
+    # over 64 seeded sources (BFS, sums and the radix select on the device)
+    t_q = time.perf_counter()
+    src = torch.as_tensor(np.random.default_rng(20230307).choice(g.n, 64, replace=False), dtype=torch.int32).to(dev)
+    se, nps, levels = T.tfdp_quality_sampled(lay.row_ptr, lay.col_idx, lay.pos, src)
+    quality = {"after_iters": T_all, "se_sampled": se, "np1_sampled": nps[0], "np2_sampled": nps[1],
+               "sources": 64, "bfs_levels": levels, "seconds": round(time.perf_counter() - t_q, 4)}
+
+    # timed region: K iterations. K >= T: the schedule from the start (its
+    # first K iterations). K < T: a schedule-weighted sample, K - 2 m
+    # iterations at k = 1 from the start and m = round(K / 20) (at least one
+    # when K >= 3) at k = 2 and at k = 3, each from the state saved at its
+    # switch: the 90/5/5 % mix of the whole layout
+    if args.steps >= T_all or args.steps < 3:
+        segments = [(pos0, 0, args.steps)]
+    else:
+        m = max(1, int(round(args.steps / 20)))
+        segments = [(pos0, 0, args.steps - 2 * m), (pos_k2, t_k2, m), (pos_k3, t_k3, m)]
+    k_mix = {}
+    for p_, t_, c_ in segments:
+        for it in range(t_, t_ + c_):
+            kk = 1 if it < t_k2 else (2 if it < t_k3 else 3)
+            k_mix[f"k{kk}"] = k_mix.get(f"k{kk}", 0) + 1
+
     if args.warmup > 0:
+        reset()
         lay.step(args.warmup)
         torch.cuda.synchronize()
         if lay.sync_status() != 0:
             raise RuntimeError("non-finite positions during warm-up")
     times = []
     for _ in range(max(1, args.repeats)):
-        reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        lay.step(args.steps)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
+        total = 0.0
+        for p_, t_, c_ in segments:
+            reset(p_, t_)
+            t0 = time.perf_counter()
+            lay.step(c_)
+            torch.cuda.synchronize()
+            total += time.perf_counter() - t0
+        times.append(total)
     st = lay.sync_status()
     if st != 0:
         raise RuntimeError(f"layout status {st}")
     secs = float(np.median(times))
-    print(f"# timed {args.steps} iterations: {secs * 1e3:.2f} ms (runs: {[round(t * 1e3, 2) for t in times]})",
+    print(f"# timed {args.steps} iterations {k_mix}: {secs * 1e3:.2f} ms (runs: {[round(t * 1e3, 2) for t in times]})",
           file=sys.stderr, flush=True)
 
-    # second pass over the same iterations with HIP events around each phase
+    # per-phase times with HIP events recorded by the library on the launch
+    # stream: the k = 1 iterations of the timed region from the start, and a
+    # few iterations from each switch
     reset()
-    k1_iters = min(args.steps, (9 * w.iters) // 10)
+    k1_iters = max(1, min(args.steps, t_k2))
     T.tfdp_layout_set_profiling(lay.handle, 1)
     lay.step(k1_iters)
     ph1 = T.tfdp_layout_phase_times(lay.handle)
-    rest = args.steps - k1_iters
-    ph_rest = {}
-    if rest > 0:
-        lay.step(rest)
-        ph_rest = T.tfdp_layout_phase_times(lay.handle)
+    ph_k = {}
+    for kk, (p_, t_) in ((2, (pos_k2, t_k2)), (3, (pos_k3, t_k3))):
+        reset(p_, t_)
+        lay.step(min(5, T_all - t_))
+        ph_k[kk] = T.tfdp_layout_phase_times(lay.handle)
     T.tfdp_layout_set_profiling(lay.handle, 0)
     torch.cuda.synchronize()
-    # quality of the final layout: stress error and neighbourhood preservation
-    # over 64 seeded sources (BFS, sums and the radix select on the device)
-    t_q = time.perf_counter()
-    src = torch.as_tensor(np.random.default_rng(20230307).choice(g.n, 64, replace=False), dtype=torch.int32).to(dev)
-    se, nps, levels = T.tfdp_quality_sampled(lay.row_ptr, lay.col_idx, lay.pos, src)
-    quality = {"se_sampled": se, "np1_sampled": nps[0], "np2_sampled": nps[1], "sources": 64,
-               "bfs_levels": levels, "seconds": round(time.perf_counter() - t_q, 4)}
 
     gather_ref = gather_reference(torch, lay, stream)
     gm_ms, gm_n = ph1["gather_update"]
@@ -409,8 +450,17 @@ def main():
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic("paper_2303_03964_amd/csrc/node_forces.hip")
     phases = {name: round(ms / cnt, 4) for name, (ms, cnt) in ph1.items() if cnt}
-    phases_rest = {name: round(ms / cnt, 4) for name, (ms, cnt) in ph_rest.items() if cnt}
+    phases_k23 = {f"k{kk}": {name: round(ms / cnt, 4) for name, (ms, cnt) in ph.items() if cnt}
+                  for kk, ph in ph_k.items()}
     iter_ms_k1 = sum(ms for ms, _ in ph1.values()) / max(k1_iters, 1)
+    dbar = g.nnz / g.n
+    # bytes per node-iteration: algorithmic (positions read by the spreading
+    # and by the edge pass, written once, row_ptr, column index and neighbour
+    # position per CSR entry) and compulsory (neighbour positions served from
+    # the on-chip caches)
+    alg_node_it = 28.0 + 12.0 * dbar
+    comp_node_it = 28.0 + 4.0 * dbar
+    step_s = secs / args.steps
 
     rec = {
         "metric": "t-FDP node-iterations/s at 1M nodes" if w.name == "chung_lu_1m"
@@ -433,6 +483,8 @@ def main():
             "n_int": w.n_int,
             "total_iters": w.iters,
             "k_schedule": "1/2/3 over 90/5/5%",
+            "timed_k_mix": k_mix,
+            "timed_segments_start_iter": [t_ for _, t_, _ in segments],
             "params": {"alpha": 0.1, "beta": 8.0, "gamma": 2.0},
             "positions": "uniform [-1,1]^2 float32, seeded",
         },
@@ -449,8 +501,16 @@ def main():
             "launches": gm_n,
             "gather_reference": gather_ref,
         },
+        "step_bytes": {
+            "algorithmic_per_node_iter": alg_node_it,
+            "compulsory_per_node_iter": comp_node_it,
+            "algorithmic_GBps": alg_node_it * g.n / step_s / 1e9,
+            "algorithmic_frac": alg_node_it * g.n / step_s / 1e9 / HBM_PEAK_GBS,
+            "compulsory_GBps": comp_node_it * g.n / step_s / 1e9,
+            "compulsory_frac": comp_node_it * g.n / step_s / 1e9 / HBM_PEAK_GBS,
+        },
         "phase_ms_k1": phases,
-        "phase_ms_k23": phases_rest,
+        "phase_ms_k23": phases_k23,
         "iteration_ms_k1_events": iter_ms_k1,
         "final_layout_quality": quality,
         "hip_graphs": not args.no_graphs,
@@ -468,6 +528,9 @@ def main():
         rec["serving"] = serving_section(T, torch, stream, args.serve_requests)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
+        if w.name == "chung_lu_1m":
+            # the oracle on the 100k-mesh workload as well (about 5 s)
+            rec["cpu_baseline_mesh_100k"] = cpu_baseline(workload("mesh_100k"), 0, budget=5.0)
     print(json.dumps(rec), flush=True)
 
 

@@ -221,8 +221,10 @@ tfdp_status tfdp_layout_phase_times(tfdp_layout* h, double* total_ms, int64_t* l
  *        (c ||x_s - x_v|| / D(s, v) - 1)^2
  * with D the hop distance and c = sum(||x_s - x_v|| / D) / sum((||x_s - x_v|| / D)^2)
  * the optimal uniform scale of the layout. Hop distances come from one
- * multi-source BFS on the device (up to 254 levels; farther nodes count as
- * unreachable).
+ * multi-source BFS on the device, stored as 16-bit integers: graphs whose
+ * BFS from the sources still finds new nodes at level 65534 are refused with
+ * TFDP_ERR_UNSUPPORTED (every connected graph of diameter below 65534 is
+ * measured exactly; nodes in other components count as unreachable).
  *   n, nnz, d_row_ptr, d_col_idx  symmetric CSR (device, as for tfdp_layout_init;
  *               checked on the device first: TFDP_ERR_INVALID_ARG if invalid)
  *   d_pos       float32[n][2] positions (device)

@@ -2,7 +2,8 @@
 // the neighbourhood preservation NP_1, NP_2 estimated from a sample of
 // source nodes. Hop distances from up to 64
 // sources come from one multi-source BFS with a 64-bit source mask per node
-// (a level per launch, pulled from the neighbours' frontier masks); the
+// (a level per launch, pulled from the neighbours' frontier masks; 16-bit
+// distances, so graphs of diameter up to kMaxLevel are measured exactly); the
 // stress sums over all (source, node) pairs at finite distance are reduced
 // per block in float64 and added on the host in block order.
 #include <cmath>
@@ -14,6 +15,12 @@
 namespace tfdp {
 
 constexpr int kMetricThreads = 256;
+// Hop distances are stored as uint16: levels 0 .. kMaxLevel, kUnreached for
+// nodes no source reaches. A BFS still finding nodes at level kMaxLevel is
+// refused (the distances of farther nodes would not fit).
+typedef unsigned short hop_t;
+constexpr int kUnreached = 0xffff;
+constexpr int kMaxLevel = kUnreached - 1;
 
 // Sources outside [0, n) mark the check flag (read with the CSR check).
 __global__ void k_src_check(const int* __restrict__ src, int nsrc, int n, int* bad) {
@@ -22,14 +29,14 @@ __global__ void k_src_check(const int* __restrict__ src, int nsrc, int n, int* b
 }
 
 // visited = frontier = the mask of the sources at each node; distances of
-// the sources to themselves 0, all others unreached (255).
+// the sources to themselves 0, all others unreached.
 __global__ void k_bfs_init(int n, const int* __restrict__ src, int nsrc, unsigned long long* visited,
-                           unsigned long long* frontier, unsigned char* dist) {
+                           unsigned long long* frontier, hop_t* dist) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     unsigned long long m = 0ull;
     for (int s = 0; s < nsrc; ++s) {
-        dist[(size_t)s * n + v] = 255;
+        dist[(size_t)s * n + v] = (hop_t)kUnreached;
         if (src[s] == v) m |= 1ull << s;
     }
     for (int s = 0; s < nsrc; ++s)
@@ -42,7 +49,7 @@ __global__ void k_bfs_init(int n, const int* __restrict__ src, int nsrc, unsigne
 // neighbour in the previous level and not the node itself.
 __global__ void k_bfs_level(int n, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
                             const unsigned long long* __restrict__ frontier, unsigned long long* next,
-                            unsigned long long* visited, unsigned char* dist, int level, int* changed) {
+                            unsigned long long* visited, hop_t* dist, int level, int* changed) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     unsigned long long acc = 0ull;
@@ -57,17 +64,17 @@ __global__ void k_bfs_level(int n, const int* __restrict__ row_ptr, const int* _
         while (m) {
             const int s = __ffsll((long long)m) - 1;
             m &= m - 1;
-            dist[(size_t)s * n + v] = (unsigned char)level;
+            dist[(size_t)s * n + v] = (hop_t)level;
         }
         *changed = 1;
     }
 }
 
-// Per block: sums over (source, node) pairs with 1 <= D < 255 of r = d / D
+// Per block: sums over (source, node) pairs at finite hop distance D >= 1 of r = d / D
 // and r^2 (d = layout distance, D = hop distance) and the pair count.
 __global__ __launch_bounds__(kMetricThreads) void k_stress_sums(int n, const float2* __restrict__ pos,
                                                                const int* __restrict__ src, int nsrc,
-                                                               const unsigned char* __restrict__ dist,
+                                                               const hop_t* __restrict__ dist,
                                                                double* partial) {
     __shared__ double red[3][kMetricThreads / 64];
     double sr = 0.0, sr2 = 0.0, cnt = 0.0;
@@ -75,7 +82,7 @@ __global__ __launch_bounds__(kMetricThreads) void k_stress_sums(int n, const flo
         const float2 p = pos[v];
         for (int s = 0; s < nsrc; ++s) {
             const int d = dist[(size_t)s * n + v];
-            if (d == 0 || d == 255) continue;
+            if (d == 0 || d == kUnreached) continue;
             const float2 q = pos[src[s]];
             const double dx = (double)p.x - (double)q.x;
             const double dy = (double)p.y - (double)q.y;
@@ -113,7 +120,7 @@ __global__ __launch_bounds__(kMetricThreads) void k_stress_sums(int n, const flo
 constexpr int kStressBlocks = 1024;
 
 // neighbourhood preservation over the BFS distances (below)
-int np_sampled(int n, const float2* pos, const int* src, int nsrc, const unsigned char* dist, void* extra,
+int np_sampled(int n, const float2* pos, const int* src, int nsrc, const hop_t* dist, void* extra,
                double* np, hipStream_t s);
 size_t np_extra_bytes(int nsrc);
 
@@ -124,7 +131,7 @@ size_t stress_workspace_bytes(int n, int nsrc) {
     take((size_t)n * 8);          // visited
     take((size_t)n * 8);          // frontier
     take((size_t)n * 8);          // next
-    take((size_t)nsrc * n);       // distances
+    take((size_t)nsrc * n * sizeof(hop_t));  // distances
     take(sizeof(int));            // changed flag
     take((size_t)kStressBlocks * 3 * sizeof(double));
     take(np_extra_bytes(nsrc));
@@ -132,7 +139,8 @@ size_t stress_workspace_bytes(int n, int nsrc) {
 }
 
 // Returns 0 on success, -1 for an invalid CSR, -2 for a source outside
-// [0, n), else the HIP error; fills SE
+// [0, n), -3 when the BFS still reaches new nodes at level kMaxLevel, else
+// the HIP error; fills SE
 // (NaN without pairs) and, when np is not NULL, NP_1 and NP_2.
 int stress_sampled(int n, long long nnz, const int* row_ptr, const int* col_idx, const float2* pos, const int* src,
                    int nsrc, void* work, double* se, double* np, int* levels, hipStream_t s) {
@@ -161,14 +169,15 @@ int stress_sampled(int n, long long nnz, const int* row_ptr, const int* col_idx,
     auto* visited = static_cast<unsigned long long*>(take((size_t)n * 8));
     auto* frontier = static_cast<unsigned long long*>(take((size_t)n * 8));
     auto* next = static_cast<unsigned long long*>(take((size_t)n * 8));
-    auto* dist = static_cast<unsigned char*>(take((size_t)nsrc * n));
+    auto* dist = static_cast<hop_t*>(take((size_t)nsrc * n * sizeof(hop_t)));
     auto* changed = static_cast<int*>(take(sizeof(int)));
     auto* partial = static_cast<double*>(take((size_t)kStressBlocks * 3 * sizeof(double)));
     void* np_extra = take(np_extra_bytes(nsrc));
     const int blocks = (n + kMetricThreads - 1) / kMetricThreads;
     hipLaunchKernelGGL(k_bfs_init, dim3(blocks), dim3(kMetricThreads), 0, s, n, src, nsrc, visited, frontier, dist);
     int level = 1;
-    for (; level < 255; ++level) {
+    bool ended = false;
+    for (; level <= kMaxLevel; ++level) {
         hipError_t e = hipMemsetAsync(changed, 0, sizeof(int), s);
         if (e != hipSuccess) return (int)e;
         hipLaunchKernelGGL(k_bfs_level, dim3(blocks), dim3(kMetricThreads), 0, s, n, row_ptr, col_idx, frontier,
@@ -180,9 +189,13 @@ int stress_sampled(int n, long long nnz, const int* row_ptr, const int* col_idx,
         unsigned long long* t = frontier;
         frontier = next;
         next = t;
-        if (!h) break;
+        if (!h) {
+            ended = true;
+            break;
+        }
     }
     *levels = level;
+    if (!ended) return -3;
     hipLaunchKernelGGL(k_stress_sums, dim3(kStressBlocks), dim3(kMetricThreads), 0, s, n, pos, src, nsrc, dist,
                        partial);
     std::vector<double> host((size_t)kStressBlocks * 3);
@@ -231,7 +244,7 @@ __device__ __forceinline__ unsigned long long d2_key(const float2 p, const float
 }
 
 // Ring sizes: count[s] += #{v : lo <= D(s, v) <= r}.
-__global__ __launch_bounds__(kMetricThreads) void k_ring_count(int n, int nsrc, const unsigned char* __restrict__ dist,
+__global__ __launch_bounds__(kMetricThreads) void k_ring_count(int n, int nsrc, const hop_t* __restrict__ dist,
                                                               int r, unsigned int* count) {
     __shared__ unsigned int c[64];
     if (threadIdx.x < 64) c[threadIdx.x] = 0;
@@ -287,7 +300,7 @@ __global__ __launch_bounds__(kMetricThreads) void k_np_hist(int n, const float2*
 // (key below the selected (squared distance, index) pair).
 __global__ __launch_bounds__(kMetricThreads) void k_np_overlap(int n, const float2* __restrict__ pos,
                                                               const int* __restrict__ src, int nsrc,
-                                                              const unsigned char* __restrict__ dist, int r,
+                                                              const hop_t* __restrict__ dist, int r,
                                                               NpSel sel, const unsigned int* __restrict__ isel,
                                                               unsigned int* overlap) {
     __shared__ unsigned int c[64];
@@ -314,7 +327,7 @@ size_t np_extra_bytes(int) { return ((size_t)64 * 256 * 4 + 256) + ((size_t)64 *
 // NP_r for r = 1 and 2 from the BFS distances in the stress workspace (the
 // same sources); np[0] = NP_1, np[1] = NP_2 (NaN when no source has a
 // non-empty ring).
-int np_sampled(int n, const float2* pos, const int* src, int nsrc, const unsigned char* dist, void* extra,
+int np_sampled(int n, const float2* pos, const int* src, int nsrc, const hop_t* dist, void* extra,
                double* np, hipStream_t s) {
     char* base = static_cast<char*>(extra);
     unsigned int* hist = reinterpret_cast<unsigned int*>(base);

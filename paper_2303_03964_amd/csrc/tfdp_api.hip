@@ -813,6 +813,10 @@ static tfdp_status quality_sampled(int32_t n, int64_t nnz, const int32_t* d_row_
         set_msg("a source node is outside [0, n)");
         return TFDP_ERR_INVALID_ARG;
     }
+    if (e == -3) {
+        set_msg("the BFS still reaches new nodes at hop distance 65534 (16-bit distances)");
+        return TFDP_ERR_UNSUPPORTED;
+    }
     if (e != 0) return check_hip((hipError_t)e, "metrics");
     return check_hip(hipGetLastError(), "kernel launch");
 }

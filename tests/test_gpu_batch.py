@@ -201,3 +201,64 @@ def test_batch_with_tau_and_refinement_weights(T, stream):
             assert a.iteration == b.iteration == 40
             assert torch.equal(a.pos, b.pos)
         B.close()
+
+
+def test_batch_members_match_oracle_one_step(T, stream):
+    """One batched iteration of members of every class against the FP64
+    oracle's forces and capped move (Sec. 3.3 Eq.5-7 and Sec. 3.4 applied to
+    each member): the exact method, fixed k = 2, the k schedule at t = 0
+    (k = 1), t = 275 (k = 2) and t = 290 (k = 3) of T = 300, and a member
+    with tau and local-refinement weights. Positions are spread to about a
+    laid-out extent (side ~ sqrt(n)), so that the grids are coarse and the
+    update caps some moves. Bound: relative L2 of the move <= 1e-5 and the
+    per-node bound of the plain parity tests."""
+    import torch
+    from oracle import tfdp as ot
+    from tests.test_gpu_parity import NODE_TOL
+    # (label, batch member index, parameters, counter, weights)
+    cases = [
+        ("exact", 1, dict(k_mode=0, n_int=16), 0, False),
+        ("fixed k=2", 2, dict(k_mode=2, n_int=48), 0, False),
+        ("schedule t=0", 0, dict(k_mode=-1, n_int=64), 0, False),
+        ("schedule t=275", 3, dict(k_mode=-1, n_int=32), 275, False),
+        ("schedule t=290", 19, dict(k_mode=-1, n_int=40), 290, False),
+        ("tau + weights", 18, dict(k_mode=1, n_int=24, tau=0.6, alpha=0.05, beta=6.0, rep_weight=1.5), 0, True),
+    ]
+    rng = np.random.default_rng(8)
+    with torch.cuda.stream(stream):
+        B = T.Batch(len(cases))
+        items = []
+        for label, idx, extra, t, weighted in cases:
+            g, pos = sg.sbm_batch_member(idx)
+            pos = (pos * (0.5 * np.sqrt(g.n))).astype(np.float32)
+            p = T.tfdp_params_default(total_iters=300, **extra)
+            lay = T.Layout(g.row_ptr, g.col_idx, torch.as_tensor(pos).cuda(), p)
+            lay.iteration = t
+            rw = aw = None
+            if weighted:
+                rw = rng.uniform(0.5, 3.0, g.n).astype(np.float32)
+                aw = rng.uniform(0.2, 4.0, g.n).astype(np.float32)
+                lay.set_node_weights(torch.as_tensor(rw), torch.as_tensor(aw))
+            B.add(lay)
+            items.append((label, g, pos, extra, t, rw, aw, lay))
+        B.step(1)
+        torch.cuda.synchronize()
+        for label, g, pos, extra, t, rw, aw, lay in items:
+            assert lay.sync_status() == 0 and lay.iteration == t + 1
+            got = lay.pos.cpu().numpy().astype(np.float64)
+            op = ot.Params(total_iters=300, **extra)
+            k = extra["k_mode"] if extra["k_mode"] >= 0 else ot.k_for_iteration(t, 300)
+            x = pos.astype(np.float64)
+            _, _, disp = ot.forces(x, g.row_ptr, g.col_idx, op, k,
+                                   rep_w=None if rw is None else rw.astype(np.float64),
+                                   att_w=None if aw is None else aw.astype(np.float64))
+            want = ot.capped_move(x, disp, ot.step_cap(t, 300, ot.default_t0(g.n)))
+            err = float(np.linalg.norm((got - x) - (want - x)) / np.linalg.norm(want - x))
+            mv = np.linalg.norm(want - x, axis=1)
+            node = float((np.linalg.norm(got - want, axis=1) / (mv + np.median(mv))).max())
+            say(f"{label}: n={g.n} k={k} move rel L2 {err:.2e}, per node {node:.2e}")
+            assert err <= 1e-5
+            assert node <= NODE_TOL
+        B.close()
+        for it in items:
+            it[-1].close()

@@ -180,3 +180,48 @@ def test_quality_1m_bench_configuration(T):
         say(f"1M: NP_{r} gpu {nps[r - 1]:.15f} oracle {want:.15f}")
         assert abs(nps[r - 1] - want) <= 1e-12
     lay.close()
+
+
+@pytest.mark.parametrize("case", ["path_400", "lattice_200"])
+def test_metrics_beyond_255_hops(T, case):
+    """Graphs whose hop distances exceed 255 (a 400-node path; an unrewired
+    200 x 200 lattice, diameter 398: the mesh family of Sec. 4): SE and NP
+    over the same sources as the oracle metrics, every distance counted."""
+    rng = np.random.default_rng(5)
+    if case == "path_400":
+        n = 400
+        g = sg.csr_from_edges(n, np.stack([np.arange(n - 1), np.arange(1, n)], axis=1))
+        pos = (np.stack([np.arange(n), np.zeros(n)], axis=1) + sg.uniform_positions(n, 3, -2, 2)).astype(np.float32)
+        src = np.array([0, 7, 200, 399])
+    else:
+        g = sg.lattice_rewired(200, 0.0, 1)
+        idx = np.arange(g.n)
+        pos = (np.stack([idx % 200, idx // 200], axis=1) + sg.uniform_positions(g.n, 4, -0.4, 0.4)).astype(np.float32)
+        src = np.concatenate([[0, g.n - 1], rng.choice(g.n, 10, replace=False)])
+    se, nps, levels = gpu_quality(T, g, pos, src)
+    d = om.graph_distances(g.n, g.row_ptr, g.col_idx, src)
+    ecc = int(d[np.isfinite(d)].max())
+    want = om.stress_error(pos.astype(np.float64), g.row_ptr, g.col_idx, sources=src)
+    say(f"{case}: max hop distance {ecc}, BFS levels {levels}; SE gpu {se:.12f} oracle {want:.12f}")
+    assert ecc > 255 and levels == ecc + 1
+    assert abs(se - want) <= 1e-9 * abs(want)
+    for r in (1, 2):
+        w_np = om.neighborhood_preservation(pos, g.row_ptr, g.col_idx, r, nodes=[int(s) for s in src])
+        say(f"  NP_{r} gpu {nps[r - 1]:.15f} oracle {w_np:.15f}")
+        assert abs(nps[r - 1] - w_np) <= 1e-12
+
+
+def test_bfs_beyond_16_bit_distances_is_refused(T):
+    """A path of 66,000 nodes from one end: the BFS still finds nodes at hop
+    distance 65534, the largest 16-bit distance, so the call is refused with
+    TFDP_ERR_UNSUPPORTED rather than counting farther nodes as unreachable."""
+    n = 66000
+    g = sg.csr_from_edges(n, np.stack([np.arange(n - 1), np.arange(1, n)], axis=1))
+    pos = sg.uniform_positions(n, 9, -5, 5)
+    say("path of 66,000 nodes: one BFS level per launch up to level 65534")
+    with pytest.raises(T.TfdpError) as e:
+        gpu_se(T, g, pos, [0])
+    assert e.value.status == -5
+    # the same path from its middle node has eccentricity 33,000: measured
+    se, levels = gpu_se(T, g, pos, [n // 2])
+    assert levels == n // 2 + 1 and np.isfinite(se)

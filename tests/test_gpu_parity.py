@@ -57,6 +57,32 @@ def oracle_forces(g, pos, k, n_int, alpha=0.1, beta=8.0, gamma=2.0, rep_weight=1
     return fr, fa, rep_weight * fr + fa
 
 
+# Per-node bound: |F_gpu_i - F_i| <= NODE_TOL (s_i + median_j s_j) for every
+# node, s_i the magnitude of what node i's result is summed from (|F_i| for
+# the repulsion and the attraction, w_r |F^r_i| + |F^a_i| for the
+# displacement, whose two parts may cancel). The median term covers nodes
+# whose force is a near-cancelling sum far below the typical force: float32
+# rounding is relative to the summands, not to the sum.
+NODE_TOL = 1e-4
+
+
+def node_errors(got, want, rep_weight=1.0, heavy=None):
+    """max over nodes of |dF_i| / (s_i + median s) for F^r, F^a, D; and the
+    same over the heavy rows only (degree > 512: the edge pass's block-wide
+    path) when `heavy` is given."""
+    scale = [np.linalg.norm(want[0], axis=1), np.linalg.norm(want[1], axis=1)]
+    scale.append(rep_weight * scale[0] + scale[1])
+    out, out_heavy = [], []
+    for gv, wv, sc in zip(got, want, scale):
+        den = sc + np.median(sc)
+        dn = np.linalg.norm(np.asarray(gv, np.float64) - wv, axis=1)
+        r = np.where(den > 0, dn / np.where(den > 0, den, 1.0), dn)
+        out.append(float(r.max()) if r.size else 0.0)
+        if heavy is not None:
+            out_heavy.append(float(r[heavy].max()) if heavy.any() else 0.0)
+    return out, out_heavy
+
+
 def check(T, g, pos, k, n_int, tol=TOL, **params):
     say(f"case n={g.n} nnz={g.nnz} k={k} n_int={n_int} {params}")
     lay = make_layout(T, g, pos, n_int=n_int, **params)
@@ -64,12 +90,16 @@ def check(T, g, pos, k, n_int, tol=TOL, **params):
     want = oracle_forces(g, pos, k, n_int, **{kk: v for kk, v in params.items()
                                               if kk in ("alpha", "beta", "gamma", "rep_weight")})
     errs = [rel_l2(a, b) for a, b in zip(got, want)]
+    heavy = np.diff(g.row_ptr) > 512
+    node, node_heavy = node_errors(got, want, params.get("rep_weight", 1.0), heavy)
     say(f"  rel L2 rep/att/tot = {errs}")
+    say(f"  per node rep/att/tot: ordinary and heavy rows {node}, heavy rows ({int(heavy.sum())}) {node_heavy}")
     if np.linalg.norm(want[0]) > 0:
         assert errs[0] <= tol
     if np.linalg.norm(want[1]) > 0:
         assert errs[1] <= tol
     assert errs[2] <= tol or np.linalg.norm(want[2]) == 0
+    assert max(node) <= NODE_TOL
     lay.close()
     return got, want
 
@@ -369,8 +399,9 @@ def test_mesh_100k_bench_configuration(T):
         got = gpu_forces(lay, w.pos0, k)
         want = oracle_forces(g, w.pos0, k, w.n_int)
         errs = [rel_l2(a_, b_) for a_, b_ in zip(got, want)]
-        say(f"mesh start k={k}: {errs}")
-        assert max(errs) <= TOL
+        node, _ = node_errors(got, want)
+        say(f"mesh start k={k}: {errs}; per node {node}")
+        assert max(errs) <= TOL and max(node) <= NODE_TOL
     lay.step(30)
     torch.cuda.synchronize()
     assert lay.sync_status() == 0
@@ -379,8 +410,9 @@ def test_mesh_100k_bench_configuration(T):
         got = gpu_forces(lay, pos30, k)
         want = oracle_forces(g, pos30, k, w.n_int)
         errs = [rel_l2(a_, b_) for a_, b_ in zip(got, want)]
-        say(f"mesh after 30 iterations k={k}: {errs}")
-        assert max(errs) <= TOL
+        node, _ = node_errors(got, want)
+        say(f"mesh after 30 iterations k={k}: {errs}; per node {node}")
+        assert max(errs) <= TOL and max(node) <= NODE_TOL
     lay.close()
 
 
@@ -391,12 +423,14 @@ def test_chung_lu_1m_bench_configuration(T):
     g = w.graph
     p = T.tfdp_params_default(n_int=w.n_int, total_iters=w.iters)
     lay = T.Layout(g.row_ptr, g.col_idx, w.pos0, p)
+    heavy = np.diff(g.row_ptr) > 512
     for k in (1, 3):
         got = gpu_forces(lay, w.pos0, k)
         want = oracle_forces(g, w.pos0, k, w.n_int)
         errs = [rel_l2(a_, b_) for a_, b_ in zip(got, want)]
-        say(f"1M start k={k}: {errs}")
-        assert max(errs) <= TOL
+        node, node_heavy = node_errors(got, want, 1.0, heavy)
+        say(f"1M start k={k}: {errs}; per node {node}, heavy rows ({int(heavy.sum())}) {node_heavy}")
+        assert max(errs) <= TOL and max(node) <= NODE_TOL
     lay.step(30)
     torch.cuda.synchronize()
     assert lay.sync_status() == 0
@@ -404,8 +438,9 @@ def test_chung_lu_1m_bench_configuration(T):
     got = gpu_forces(lay, pos30, 1)
     want = oracle_forces(g, pos30, 1, w.n_int)
     errs = [rel_l2(a_, b_) for a_, b_ in zip(got, want)]
-    say(f"1M after 30 iterations k=1: {errs}")
-    assert max(errs) <= TOL
+    node, node_heavy = node_errors(got, want, 1.0, heavy)
+    say(f"1M after 30 iterations k=1: {errs}; per node {node}, heavy rows {node_heavy}")
+    assert max(errs) <= TOL and max(node) <= NODE_TOL
     # interpolation against the exact sum on sampled nodes (a property of the
     # scheme at this spacing, reported; bound only at k = 3)
     rows = np.random.default_rng(0).choice(g.n, 64, replace=False)
@@ -516,8 +551,10 @@ def test_generalised_tforce_tau(T, tau, k):
     fr = ot.repulsion_exact(x, 2.5, tau=tau) if k == 0 else ot.repulsion_ibfft_stable(x, 2.5, n_int, k, tau=tau)
     fa = ot.attraction(x, g.row_ptr, g.col_idx, 0.1, 8.0, tau=tau)
     errs = [rel_l2(got[0], fr), rel_l2(got[1], fa), rel_l2(got[2], fr + fa)]
-    say(f"  rel L2 rep/att/tot = {errs}")
+    node, node_heavy = node_errors(got, (fr, fa, fr + fa), 1.0, np.diff(g.row_ptr) > 512)
+    say(f"  rel L2 rep/att/tot = {errs}; per node {node}, heavy rows {node_heavy}")
     assert max(errs) <= TOL
+    assert max(node) <= NODE_TOL
     lay.close()
 
 
@@ -536,8 +573,10 @@ def test_local_refinement_weights(T, k):
     want = ot.forces(pos.astype(np.float64), g.row_ptr, g.col_idx, p, k,
                      rep_w=rep_w.astype(np.float64), att_w=att_w.astype(np.float64))
     errs = [rel_l2(a, b) for a, b in zip(got, want)]
-    say(f"weighted k={k}: rel L2 rep/att/tot = {errs}")
+    node, node_heavy = node_errors(got, want, 1.5 * rep_w.astype(np.float64), np.diff(g.row_ptr) > 512)
+    say(f"weighted k={k}: rel L2 rep/att/tot = {errs}; per node {node}, heavy rows {node_heavy}")
     assert max(errs) <= TOL
+    assert max(node) <= NODE_TOL
     # one capped step with weights and tau against the oracle's move
     lay.iteration = 0
     lay.set_params(T.tfdp_params_default(n_int=48, alpha=0.05, beta=6.0, rep_weight=1.5, tau=0.7, k_mode=k,

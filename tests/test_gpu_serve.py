@@ -75,6 +75,29 @@ def test_results_same_alone_and_in_the_mix(T):
             say(f"request {r.rid} {r.kind} n={r.n} latency {r.latency * 1e3:.1f} ms same={same}")
             assert same
             lay.close()
+    # the first re-tune request's first iteration against the FP64 oracle
+    # (Sec. 5 global refinement: new weights, unit step cap, the schedule
+    # restarted): a replay alone equals the served result bit for bit
+    # (above), so this anchors the served re-tune to the oracle
+    from oracle import tfdp as ot
+    r, req = next((r, q) for r, q in zip(recs, trace) if r.kind == "retune")
+    g = pool[trace[req.target].graph][0]
+    with torch.cuda.stream(stream):
+        lay = T.Layout(g.row_ptr, g.col_idx, r.start_pos.clone(), r.params)
+        lay.step(1)
+        torch.cuda.synchronize()
+        got = lay.pos.cpu().numpy().astype(np.float64)
+        lay.close()
+    q = r.params
+    op = ot.Params(alpha=q.alpha, beta=q.beta, gamma=q.gamma, rep_weight=q.rep_weight, n_int=q.n_int,
+                   k_mode=q.k_mode, total_iters=q.total_iters, t0=q.t0, tau=q.tau)
+    x = r.start_pos.cpu().numpy().astype(np.float64)
+    k = q.k_mode if q.k_mode >= 0 else ot.k_for_iteration(0, q.total_iters)
+    _, _, disp = ot.forces(x, g.row_ptr, g.col_idx, op, k)
+    want = ot.capped_move(x, disp, ot.step_cap(0, q.total_iters, q.t0))
+    err = float(np.linalg.norm(got - want) / np.linalg.norm(want - x))
+    say(f"re-tune request {r.rid} (n={g.n}, k={k}, gamma={q.gamma:.2f}): first step vs oracle {err:.2e}")
+    assert err <= 1e-5
 
 
 def test_sequential_baseline_serves_everything(T):
