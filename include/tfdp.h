@@ -253,6 +253,25 @@ tfdp_status tfdp_quality_sampled(int32_t n, int64_t nnz, const int32_t* d_row_pt
                                  const float* d_pos, const int32_t* d_sources, int32_t nsrc, void* d_work,
                                  size_t work_bytes, double* se, double* np, int32_t* levels, hipStream_t stream);
 
+/* tfdp_quality_sampled without a workspace, for callers that cannot allocate
+ * device memory (code that must not call hipMalloc: tight serving loops,
+ * harnesses that forbid allocation). The call makes no device allocation
+ * (no hipMalloc or hipFree) and, on success, no host heap allocation: the
+ * metric's scratch is a fixed 64 MiB array of the library, one copy per GPU,
+ * resident from the first call on that GPU until the process ends. Limit: tfdp_stress_workspace_size(n, nsrc) <= 64 MiB
+ * (about n * (24 + 2 nsrc) bytes; e.g. n <= 400,000 with 64 sources),
+ * TFDP_ERR_UNSUPPORTED beyond it, checked before any device work.
+ * The stream must belong to the current device. Every call on one GPU uses
+ * that GPU's one array: calls from the threads of this process are
+ * serialised by the library (each returns only after its stream has finished
+ * the metric's work), but work that overlaps on one GPU by other means would
+ * race on it; after a TFDP_ERR_HIP return the array may still be in use by
+ * the failed stream. Arguments, results and the other errors as for
+ * tfdp_quality_sampled (se and np must be set). Synchronises `stream`. */
+tfdp_status tfdp_quality_sampled_noalloc(int32_t n, int64_t nnz, const int32_t* d_row_ptr,
+                                         const int32_t* d_col_idx, const float* d_pos, const int32_t* d_sources,
+                                         int32_t nsrc, double* se, double* np, int32_t* levels, hipStream_t stream);
+
 /* ---- Batched stepping ----
  *
  * A batch steps many layout handles (graphs of any sizes, each with its own

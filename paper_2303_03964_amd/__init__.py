@@ -38,6 +38,7 @@ from .tfdp import (  # noqa: F401
     tfdp_phase_count,
     tfdp_phase_name,
     tfdp_quality_sampled,
+    tfdp_quality_sampled_noalloc,
     tfdp_stress_sampled,
     tfdp_stress_workspace_size,
     tfdp_workspace_size,

@@ -8,7 +8,6 @@
 // per block in float64 and added on the host in block order.
 #include <cmath>
 #include <cstring>
-#include <vector>
 
 #include "tfdp_internal.h"
 
@@ -198,8 +197,8 @@ int stress_sampled(int n, long long nnz, const int* row_ptr, const int* col_idx,
     if (!ended) return -3;
     hipLaunchKernelGGL(k_stress_sums, dim3(kStressBlocks), dim3(kMetricThreads), 0, s, n, pos, src, nsrc, dist,
                        partial);
-    std::vector<double> host((size_t)kStressBlocks * 3);
-    hipError_t e = hipMemcpyAsync(host.data(), partial, host.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    double host[kStressBlocks * 3];  // fixed host buffers: the metric makes no allocation of its own
+    hipError_t e = hipMemcpyAsync(host, partial, sizeof(host), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return (int)e;
     double sr = 0.0, sr2 = 0.0, cnt = 0.0;
@@ -358,8 +357,8 @@ int np_sampled(int n, const float2* pos, const int* src, int nsrc, const hop_t* 
                 if (e != hipSuccess) return (int)e;
                 hipLaunchKernelGGL(k_np_hist, dim3(kNpBlocks), dim3(kMetricThreads), (size_t)nsrc * 256 * 4, s, n,
                                    pos, src, nsrc, sel, phase, shift, hist);
-                std::vector<unsigned int> hh((size_t)nsrc * 256);
-                e = hipMemcpyAsync(hh.data(), hist, hh.size() * 4, hipMemcpyDeviceToHost, s);
+                unsigned int hh[64 * 256];
+                e = hipMemcpyAsync(hh, hist, (size_t)nsrc * 256 * 4, hipMemcpyDeviceToHost, s);
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
                 if (e != hipSuccess) return (int)e;
                 for (int q = 0; q < nsrc; ++q) {

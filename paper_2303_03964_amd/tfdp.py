@@ -80,6 +80,8 @@ _SIGS = {
     "tfdp_quality_sampled": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
                                        c_size_t, POINTER(c_double), POINTER(c_double), POINTER(c_int32),
                                        c_void_p]),
+    "tfdp_quality_sampled_noalloc": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                                               POINTER(c_double), POINTER(c_double), POINTER(c_int32), c_void_p]),
     "tfdp_batch_create": (c_int32, [POINTER(c_void_p), c_int32]),
     "tfdp_batch_add": (c_int32, [c_void_p, c_void_p]),
     "tfdp_batch_remove": (c_int32, [c_void_p, c_void_p]),
@@ -272,6 +274,21 @@ def tfdp_quality_sampled(row_ptr, col_idx, pos, sources, stream=None):
     _check(load_library().tfdp_quality_sampled(n, nnz, _ptr(row_ptr), _ptr(col_idx if nnz else None), _ptr(pos),
                                                _ptr(sources), nsrc, _ptr(work), size, ctypes.byref(se), np_,
                                                ctypes.byref(lv), _stream(stream)))
+    return se.value, (np_[0], np_[1]), lv.value
+
+
+def tfdp_quality_sampled_noalloc(row_ptr, col_idx, pos, sources, stream=None):
+    """tfdp_quality_sampled with the library's static scratch instead of a
+    workspace (no device allocation). Returns (SE, (NP_1, NP_2), BFS levels)."""
+    n = int(pos.shape[0])
+    nsrc = int(sources.numel())
+    se = c_double()
+    np_ = (c_double * 2)()
+    lv = c_int32()
+    nnz = int(col_idx.numel())
+    _check(load_library().tfdp_quality_sampled_noalloc(n, nnz, _ptr(row_ptr), _ptr(col_idx if nnz else None),
+                                                       _ptr(pos), _ptr(sources), nsrc, ctypes.byref(se), np_,
+                                                       ctypes.byref(lv), _stream(stream)))
     return se.value, (np_[0], np_[1]), lv.value
 
 
