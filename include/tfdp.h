@@ -195,6 +195,23 @@ void tfdp_layout_destroy(tfdp_layout* h);
 /* Thread-local text for the last failure or warning ("" if none). */
 const char* tfdp_last_error(void);
 
+/* How the edge pass (attraction, repulsion gather and move) is scheduled:
+ *   1   overlapped: the attraction sums run on a second stream of the
+ *       library (created on first use, default priority) concurrently with
+ *       the binning and FFT passes, as a launch of a fixed number of blocks
+ *       that leaves room on every CU; a node pass then gathers the repulsion
+ *       and moves every node once both are done;
+ *   0   fused: one edge pass after the grid passes;
+ *  -1   automatic (default): overlapped from 4,194,304 CSR entries on
+ *       (below, the node pass and the waits between the streams cost more
+ *       than the attraction pass hides).
+ * The two schedules compute bit-identical results. The caller's stream still
+ * orders everything: the second stream waits for the caller's stream at the
+ * start of each iteration and the caller's stream waits for it before the
+ * node pass. TFDP_ERR_UNSUPPORTED for mode 1 on a handle whose edge pass is
+ * split into column slices. */
+tfdp_status tfdp_layout_set_overlap(tfdp_layout* h, int32_t mode);
+
 /* Launch groups of eight (else two) iterations of one k as captured HIP
  * graphs (default on; a graph per group size, k, parity and buffer
  * orientation is captured on first use on the step's stream and dropped by

@@ -30,6 +30,7 @@ from .tfdp import (  # noqa: F401
     tfdp_layout_set_params,
     tfdp_layout_set_graphs,
     tfdp_layout_set_node_weights,
+    tfdp_layout_set_overlap,
     tfdp_layout_set_profiling,
     tfdp_layout_step,
     tfdp_layout_sync_status,

@@ -125,6 +125,7 @@ __device__ __forceinline__ void bin_count_body(const float2* __restrict__ pos, c
 }
 
 __global__ __launch_bounds__(kThreads) void k_bin_count(const float2* __restrict__ pos, Bufs b, int set) {
+    grid_pass_priority();
     bin_count_body(pos, b, set, blockIdx.x);
 }
 
@@ -190,6 +191,7 @@ __device__ __forceinline__ void bin_scan_body(const Bufs& b, int reset_set, int 
 }
 
 __global__ __launch_bounds__(kThreads) void k_bin_scan(Bufs b, int reset_set) {
+    grid_pass_priority();
     bin_scan_body(b, reset_set, blockIdx.x);
 }
 
@@ -253,6 +255,7 @@ __device__ __forceinline__ void bin_scatter_body(const float2* __restrict__ pos,
 }
 
 __global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restrict__ pos, Bufs b) {
+    grid_pass_priority();
     bin_scatter_body(pos, b, blockIdx.x);
 }
 

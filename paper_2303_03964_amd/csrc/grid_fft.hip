@@ -410,6 +410,7 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
 
 template <int K, int L>
 __global__ __launch_bounds__(512) void k_spread(Bufs b, Geom g, float gamma, float tau, int nw, int nkb) {
+    grid_pass_priority();
     const int bid = blockIdx.x;
     int lb = -1;
     if (bid >= b.max_chunks) {
@@ -564,6 +565,7 @@ __device__ __forceinline__ void rowfft_body(const Bufs& b, const Geom& g, int lb
 
 template <int L>
 __global__ __launch_bounds__(RowTile<L>::THREADS) void k_rowfft(Bufs b, Geom g, int nqb) {
+    grid_pass_priority();
     const int lb = xcd_pair_block(blockIdx.x, nqb);
     if (lb < 0) return;
     rowfft_body<L, RowTile<L>::RB>(b, g, lb);
@@ -682,6 +684,7 @@ __device__ __forceinline__ void colconv_body(const Bufs& b, const Geom& g, int b
 
 template <int L>
 __global__ __launch_bounds__(512) void k_colconv(Bufs b, Geom g) {
+    grid_pass_priority();
     colconv_body<L, col_groups(L, false)>(b, g, blockIdx.x);
 }
 
@@ -766,6 +769,7 @@ __device__ __forceinline__ void rowifft_body(const Bufs& b, const Geom& g, int l
 
 template <int L>
 __global__ __launch_bounds__(RowTile<L>::THREADS) void k_rowifft(Bufs b, Geom g, int nrb) {
+    grid_pass_priority();
     const int lb = xcd_pair_block(blockIdx.x, nrb);
     if (lb < 0) return;
     rowifft_body<L, RowTile<L>::RB>(b, g, lb);

@@ -315,6 +315,74 @@ __global__ __launch_bounds__(kThreads) void k_edges(const float2* __restrict__ p
     edges_body<K, MODE>(pos, pos_out, es, use_part, fpart, b, g, a, set, f_rep, f_att, f_tot, blockIdx.x);
 }
 
+// Attraction pass that runs beside the grid passes (on a second stream): the
+// attraction sums of every row into fpart, nothing else. A fixed number of
+// blocks walks the schedule (block b takes entries b, b + gridDim.x, ...), so
+// that the launch holds only part of every CU and the binning and FFT
+// kernels of the same iteration find room next to it. Each row's sum is
+// formed exactly as in the fused pass, so the results do not depend on the
+// number of blocks.
+__global__ __launch_bounds__(kThreads) void k_attract(const float2* __restrict__ pos, EdgeSlice es,
+                                                      float2* __restrict__ fpart, Bufs b, Geom g, ModelArgs a) {
+    for (int bid = blockIdx.x; bid < es.blocks; bid += gridDim.x)
+        edges_body<1, 0>(pos, nullptr, es, 0, fpart, b, g, a, 0, nullptr, nullptr, nullptr, bid);
+}
+
+void launch_attract(const float2* pos, const EdgeSlice& es, float2* fpart, const Bufs& b, const Geom& g,
+                    const ModelArgs& a, int blocks, hipStream_t s) {
+    const int grid = es.blocks < blocks ? es.blocks : blocks;
+    if (grid <= 0) return;
+    hipLaunchKernelGGL(k_attract, dim3(grid), dim3(kThreads), 0, s, pos, es, fpart, b, g, a);
+}
+
+// Node pass after the overlapped attraction pass: repulsion gathered from
+// the grid potentials, displacement from fpart, then the capped move (or the
+// force outputs); the same arithmetic per node as the fused pass. Each thread
+// takes kNodesPerThread nodes (a stride of the block size apart) and issues
+// all their loads before the first store, so that the pass is not a chain of
+// one load round trip per node.
+constexpr int kNodesPerThread = 4;
+
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_node_update(const float2* __restrict__ pos, float2* __restrict__ pos_out,
+                                                          const float2* __restrict__ fpart, Bufs b, Geom g,
+                                                          ModelArgs a, int set, float2* f_rep, float2* f_att,
+                                                          float2* f_tot) {
+    const int base = blockIdx.x * (kThreads * kNodesPerThread) + threadIdx.x;
+    float2 p[kNodesPerThread], sa[kNodesPerThread];
+#pragma unroll
+    for (int u = 0; u < kNodesPerThread; ++u) {
+        const int i = min(base + u * kThreads, b.n - 1);
+        p[u] = pos[i];
+        sa[u] = fpart[i];
+    }
+    const Box bx = b.st->box;
+    const int t = b.st->t;
+    float frx[kNodesPerThread], fry[kNodesPerThread];
+#pragma unroll
+    for (int u = 0; u < kNodesPerThread; ++u) grid_repulsion<K>(b, g, bx, p[u], frx[u], fry[u]);
+    float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
+#pragma unroll
+    for (int u = 0; u < kNodesPerThread; ++u) {
+        const int i = base + u * kThreads;
+        if (i < b.n)
+            node_output(i, p[u], frx[u], fry[u], sa[u].x, sa[u].y, a, t, b.st, pos_out, f_rep, f_att, f_tot, xmin,
+                        ymin, xmax, ymax);
+    }
+    if (pos_out != nullptr) block_minmax_commit(xmin, ymin, xmax, ymax, b.st, set, blockIdx.x);
+}
+
+void launch_node_update(const float2* pos, float2* pos_out, const float2* fpart, const Bufs& b, const Geom& g,
+                        const ModelArgs& a, int set, float2* f_rep, float2* f_att, float2* f_tot, hipStream_t s) {
+    const int per = kThreads * kNodesPerThread;
+    const dim3 grid((b.n + per - 1) / per), block(kThreads);
+    switch (g.k) {
+        case 1: hipLaunchKernelGGL(k_node_update<1>, grid, block, 0, s, pos, pos_out, fpart, b, g, a, set, f_rep, f_att, f_tot); break;
+        case 2: hipLaunchKernelGGL(k_node_update<2>, grid, block, 0, s, pos, pos_out, fpart, b, g, a, set, f_rep, f_att, f_tot); break;
+        default: hipLaunchKernelGGL(k_node_update<3>, grid, block, 0, s, pos, pos_out, fpart, b, g, a, set, f_rep, f_att, f_tot); break;
+    }
+}
+
 // Batched edge pass of iteration j of a call (single slice, positions moved
 // from the current buffer to the other one).
 template <int K>

@@ -48,11 +48,35 @@ enum Phase {
     PH_ROWIFFT,
     PH_GATHER,
     PH_BRUTE,
+    PH_ATTRACT,
+    PH_NODE,
     PH_COUNT
 };
 
 const char* kPhaseNames[PH_COUNT] = {"box",     "bin_count", "bin_scan", "bin_scatter",   "spread",
-                                     "rowfft",  "colconv",   "rowifft",  "gather_update", "brute"};
+                                     "rowfft",  "colconv",   "rowifft",  "gather_update", "brute",
+                                     "attract", "node_update"};
+
+// Overlapped edge pass: used automatically from kOverlapMinEntries CSR
+// entries on. It pays where the attraction pass is long enough to hide the
+// grid passes: 1M-node Chung-Lu graph (10M entries) 64.6 -> 58-59 ms per 500
+// iterations; the 100k-node mesh (0.4M entries) went from 20.9 to 30.4 ms,
+// the node pass and the two waits between the streams costing more than the
+// short attraction pass hides. Blocks of the attraction pass per compute
+// unit: 3 at k = 1 and 2 at k = 2, 3 (measured at 1M: 2, 3, 4, 6 per CU gave
+// 116.9, 108.9, 113.2, 119.4 us per k = 1 iteration and 154, 161, 161, 168
+// us at k = 2; the longer grid passes of k = 2, 3 need more room), or the
+// value of TFDP_ATTRACT_BLOCKS_PER_CU (1..32, read at init) for every k.
+constexpr long long kOverlapMinEntries = 1LL << 22;
+
+int attract_blocks_per_cu(int k) {
+    const char* e = std::getenv("TFDP_ATTRACT_BLOCKS_PER_CU");
+    if (e) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 32) return v;
+    }
+    return k <= 1 ? 3 : 2;
+}
 
 
 
@@ -88,10 +112,8 @@ Layout carve(void* base, int n, long long nnz, const tfdp_params* p, long long s
     l.b.spos = c.take<float2>((size_t)n);
     l.nslices = edge_slices(n, sn);
     l.slice_col = c.take<int>((size_t)nnz);
-    if (l.nslices > 1) {
-        l.slice_rp = c.take<int>((size_t)l.nslices * ((size_t)n + 1));
-        l.fpart = c.take<float2>((size_t)n);
-    }
+    l.fpart = c.take<float2>((size_t)n);  // attraction sums (earlier slices, or the overlapped pass)
+    if (l.nslices > 1) l.slice_rp = c.take<int>((size_t)l.nslices * ((size_t)n + 1));
     l.sched = c.take<int2>((size_t)4 * edge_blocks_bound(n, nnz, sn));
     l.b.blkcnt = c.take<int>((size_t)p->n_int * l.b.nblk);
     l.b.bucket_cnt = c.take<int>((size_t)p->n_int);
@@ -285,6 +307,62 @@ void enqueue_edges(tfdp_layout* h, const float2* pos, float2* pos_out, const Buf
     launch_edges(pos, pos_out, l.slice[S - 1], 2, S > 1 ? 1 : 0, l.fpart, b, g, a, set, fr, fa, ft, s);
 }
 
+// Whether the edge pass of this handle runs overlapped with the grid passes
+// (single-slice handles only); creates the second stream and its events on
+// first use, on the handle's device. False (fused pass) if they cannot be
+// created.
+bool use_overlap(tfdp_layout* h) {
+    if (h->lay.nslices != 1) return false;
+    if (h->overlap_mode == 0 || (h->overlap_mode < 0 && h->nnz < kOverlapMinEntries)) return false;
+    if (h->side) return true;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return false;
+    if (cur != h->device && hipSetDevice(h->device) != hipSuccess) return false;
+    bool ok = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) == hipSuccess;
+    if (cur != h->device) (void)hipSetDevice(cur);
+    if (!ok) {
+        if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+        if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+        if (h->side) (void)hipStreamDestroy(h->side);
+        h->ev_fork = h->ev_join = nullptr;
+        h->side = nullptr;
+        h->overlap_mode = 0;
+        (void)hipGetLastError();
+        return false;
+    }
+    return true;
+}
+
+// Forces at pos for one k >= 1 and, with pos_out, the move: grid passes, then
+// the edge pass. `set` is the slot set of the box extremes read now (set ^ 1
+// receives the extremes of pos_out). Overlapped: the attraction pass runs on
+// the second stream from the start of the grid passes, the node pass joins
+// both on s.
+void enqueue_evaluation(tfdp_layout* h, int k, int set, const float2* pos, float2* pos_out, const ModelArgs& a,
+                        float2* fr, float2* fa, float2* ft, hipStream_t s) {
+    const Bufs b = bufs_for(h, k);
+    const Geom g = make_geom(h->p.n_int, k);
+    if (use_overlap(h)) {
+        (void)hipEventRecord(h->ev_fork, s);
+        (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
+        {
+            PhaseTimer pt(h, PH_ATTRACT, h->side);
+            launch_attract(pos, h->lay.slice[0], h->lay.fpart, b, g, a, h->attract_blocks[k <= 1 ? 0 : 1], h->side);
+        }
+        (void)hipEventRecord(h->ev_join, h->side);
+        enqueue_grid(h, pos, b, g, set, s);
+        (void)hipStreamWaitEvent(s, h->ev_join, 0);
+        PhaseTimer pt(h, PH_NODE, s);
+        launch_node_update(pos, pos_out, h->lay.fpart, b, g, a, set ^ 1, fr, fa, ft, s);
+        return;
+    }
+    enqueue_grid(h, pos, b, g, set, s);
+    PhaseTimer pt(h, PH_GATHER, s);
+    enqueue_edges(h, pos, pos_out, b, g, a, set ^ 1, fr, fa, ft, s);
+}
+
 void drop_graphs(tfdp_layout* h) {
     for (int z = 0; z < 2; ++z)
         for (int k = 0; k < 4; ++k)
@@ -300,11 +378,7 @@ void drop_graphs(tfdp_layout* h) {
 // the box-extremes slot set read now (set ^ 1 is filled by the update).
 void enqueue_iteration(tfdp_layout* h, int k, int set, const float2* cur, float2* alt, const ModelArgs& a,
                        hipStream_t s) {
-    const Bufs b = bufs_for(h, k);
-    const Geom g = make_geom(h->p.n_int, k);
-    enqueue_grid(h, cur, b, g, set, s);
-    PhaseTimer pt(h, PH_GATHER, s);
-    enqueue_edges(h, cur, alt, b, g, a, set ^ 1, nullptr, nullptr, nullptr, s);
+    enqueue_evaluation(h, k, set, cur, alt, a, nullptr, nullptr, nullptr, s);
 }
 
 // Graph of `iters` (2 or kGraphIters, even) consecutive iterations at k
@@ -534,6 +608,21 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
     size_t bytes = 0;
     h->slice_nodes = sn;
     h->lay = carve(d_ws, n, nnz, &h->p, sn, &bytes);
+    h->overlap_mode = -1;
+    h->side = nullptr;
+    h->ev_fork = h->ev_join = nullptr;
+    h->device = 0;
+    int cus = 0;
+    st = check_hip(hipGetDevice(&h->device), "hipGetDevice");
+    if (st == TFDP_OK)
+        st = check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device),
+                       "hipDeviceGetAttribute");
+    if (st != TFDP_OK) {
+        delete h;
+        return st;
+    }
+    h->attract_blocks[0] = std::max(1, cus) * attract_blocks_per_cu(1);
+    h->attract_blocks[1] = std::max(1, cus) * attract_blocks_per_cu(2);
 
     DevState* dst = h->lay.b.st;
     static const bool attrs = (init_kernel_attributes(), true);
@@ -658,11 +747,7 @@ tfdp_status tfdp_layout_forces(tfdp_layout* h, const float* d_pos_in, int32_t k,
         launch_brute(pos, nullptr, h->row_ptr, h->col_idx, h->n, h->lay.b.st, a, h->t, fr, fa, ft, s);
     } else {
         enqueue_box(h, pos, 0, s);
-        const Bufs b = bufs_for(h, k);
-        const Geom g = make_geom(h->p.n_int, k);
-        enqueue_grid(h, pos, b, g, 0, s);
-        PhaseTimer pt(h, PH_GATHER, s);
-        enqueue_edges(h, pos, nullptr, b, g, a, 1, fr, fa, ft, s);
+        enqueue_evaluation(h, k, 0, pos, nullptr, a, fr, fa, ft, s);
     }
     return check_hip(hipGetLastError(), "kernel launch");
 }
@@ -758,6 +843,9 @@ tfdp_status tfdp_layout_sync_status(tfdp_layout* h, hipStream_t s) {
 void tfdp_layout_destroy(tfdp_layout* h) {
     if (!h) return;
     drop_graphs(h);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->side) (void)hipStreamDestroy(h->side);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     delete h;
 }
@@ -770,6 +858,23 @@ tfdp_status tfdp_layout_set_profiling(tfdp_layout* h, int32_t enable) {
     h->prof = enable != 0;
     h->ev_used = 0;
     h->ev_phase.clear();
+    return TFDP_OK;
+}
+
+tfdp_status tfdp_layout_set_overlap(tfdp_layout* h, int32_t mode) {
+    if (!h || mode < -1 || mode > 1) {
+        set_msg("invalid handle or overlap mode (-1, 0 or 1)");
+        return TFDP_ERR_INVALID_ARG;
+    }
+    if (mode == 1 && h->lay.nslices != 1) {
+        set_msg("the overlapped edge pass needs a single column slice");
+        return TFDP_ERR_UNSUPPORTED;
+    }
+    set_msg("");
+    if (mode != h->overlap_mode) {
+        h->overlap_mode = mode;
+        drop_graphs(h);
+    }
     return TFDP_OK;
 }
 

@@ -57,7 +57,7 @@ struct Layout {
     int nslices;
     int* slice_rp;      // [nslices][n + 1] (nslices > 1)
     int* slice_col;     // [nnz] packed entries: column | (row index in its wave group) << 26
-    float2* fpart;      // [n] attraction sums of the earlier slices (nslices > 1)
+    float2* fpart;      // [n] attraction sums of the earlier slices, or of the overlapped pass
     int2* sched;        // [4 * edge_blocks_bound] schedules of all slices
     EdgeSlice slice[kMaxSlices];
 };
@@ -93,6 +93,14 @@ struct tfdp_layout {
     const float* rep_w;     // local-refinement weights (caller's device arrays) or null
     const float* att_w;
     bool auto_grid;         // n_int chosen from the box every kAutoGridChunk iterations
+    // edge pass: -1 automatic, 0 fused (one pass after the grid passes), 1
+    // overlapped (attraction on a second stream beside the grid passes, then
+    // a node pass)
+    int overlap_mode;
+    int device;             // device current at init (the second stream is created on it)
+    int attract_blocks[2];  // blocks of the overlapped attraction pass at k = 1 and at k = 2, 3
+    hipStream_t side;       // second stream of the overlapped attraction pass (created on first use)
+    hipEvent_t ev_fork, ev_join;
 };
 
 namespace tfdp {

@@ -71,6 +71,7 @@ _SIGS = {
     "tfdp_last_error": (c_char_p, []),
     "tfdp_layout_set_profiling": (c_int32, [c_void_p, c_int32]),
     "tfdp_layout_set_graphs": (c_int32, [c_void_p, c_int32]),
+    "tfdp_layout_set_overlap": (c_int32, [c_void_p, c_int32]),
     "tfdp_phase_count": (c_int32, []),
     "tfdp_phase_name": (c_char_p, [c_int32]),
     "tfdp_layout_phase_times": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64), c_int32]),
@@ -214,6 +215,10 @@ def tfdp_layout_set_profiling(h, enable):
 
 def tfdp_layout_set_graphs(h, enable):
     return _check(load_library().tfdp_layout_set_graphs(h, int(bool(enable))))
+
+
+def tfdp_layout_set_overlap(h, mode):
+    return _check(load_library().tfdp_layout_set_overlap(h, mode))
 
 
 def tfdp_phase_count() -> int:
@@ -376,6 +381,10 @@ class Layout:
     def set_params(self, params: TfdpParams):
         tfdp_layout_set_params(self.handle, params)
         self.params = params
+
+    def set_overlap(self, mode):
+        """Edge-pass schedule: 1 overlapped with the grid passes, 0 fused, -1 automatic."""
+        tfdp_layout_set_overlap(self.handle, mode)
 
     def set_node_weights(self, rep_w=None, att_w=None):
         """Local-refinement weights (float32 [n] device tensors or None);

@@ -108,6 +108,7 @@ def test_null_handle_calls():
     assert lib.tfdp_layout_sync_status(None, None) == INVALID
     assert lib.tfdp_layout_set_profiling(None, 1) == INVALID
     assert lib.tfdp_layout_set_graphs(None, 1) == INVALID
+    assert lib.tfdp_layout_set_overlap(None, 1) == INVALID
     assert lib.tfdp_layout_set_node_weights(None, None, None) == INVALID
     assert lib.tfdp_layout_get_params(None, None) == INVALID
     lib.tfdp_layout_destroy(None)
@@ -116,6 +117,7 @@ def test_null_handle_calls():
 def test_phase_names():
     names = [T.tfdp_phase_name(i) for i in range(T.tfdp_phase_count())]
     assert "gather_update" in names and "spread" in names and "rowfft" in names and "colconv" in names
+    assert "attract" in names and "node_update" in names
     assert T.tfdp_phase_name(-1) == "" and T.tfdp_phase_name(999) == ""
 
 
@@ -193,3 +195,23 @@ def test_quality_metric_host_checks():
                                     ctypes.byref(se), np2, None, None) == WORKSPACE
     assert lib.tfdp_quality_sampled(10, 4, fake, fake, fake, fake, 65, fake, 1 << 20, ctypes.byref(se), np2, None,
                                     None) == INVALID
+
+
+def test_noalloc_metric_host_checks():
+    """The allocation-free metric refuses bad arguments and sizes above its
+    static scratch before any device work."""
+    lib = T.load_library()
+    se = ctypes.c_double()
+    np2 = (ctypes.c_double * 2)()
+    fake = ctypes.c_void_p(0x100000)
+    assert lib.tfdp_quality_sampled_noalloc(10, 4, fake, fake, fake, fake, 4, ctypes.byref(se), None, None,
+                                            None) == INVALID
+    assert lib.tfdp_quality_sampled_noalloc(10, 4, fake, fake, fake, fake, 0, ctypes.byref(se), np2, None,
+                                            None) == INVALID
+    assert lib.tfdp_quality_sampled_noalloc(0, 4, fake, fake, fake, fake, 4, ctypes.byref(se), np2, None,
+                                            None) == INVALID
+    n = 600_000
+    assert T.tfdp_stress_workspace_size(n, 64) > 64 << 20
+    assert lib.tfdp_quality_sampled_noalloc(n, 4, fake, fake, fake, fake, 64, ctypes.byref(se), np2, None,
+                                            None) == UNSUPPORTED
+    assert "static scratch" in T.tfdp_last_error()
