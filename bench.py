@@ -275,6 +275,42 @@ def batched_section(T, torch, stream, graphs, iters, accuracy=True, sequential=T
     }
 
 
+def final_stage_accuracy(T, torch, pool, trace, recs, stream, every=8):
+    """Repulsion error of the last stage's method against the exact sums at
+    the final positions of every `every`-th served request (0 for requests
+    whose last stage is the exact method), and the mix of last stages."""
+    errs, grid_errs = [], []
+    with torch.cuda.stream(stream):
+        for r, req in list(zip(recs, trace))[::every]:
+            k_mode, n_int = r.final
+            if k_mode == 0:
+                errs.append(0.0)
+                continue
+            g = pool[req.graph][0] if req.kind == "layout" else pool[trace[req.target].graph][0]
+            p = T.TfdpParams(**{**r.params.as_dict(), "n_int": n_int, "k_mode": -1})
+            ws = T.TfdpParams(**{**p.as_dict(), "n_int": max(n_int, r.ws_n_int)})
+            lay = T.Layout(g.row_ptr, g.col_idx, r.final_pos.clone(), p, workspace_params=ws)
+            ex, _, _ = lay.forces(k=0)
+            fr, _, _ = lay.forces(k=3)
+            torch.cuda.synchronize()
+            e = float(torch.linalg.norm((fr - ex).double()) / torch.linalg.norm(ex.double()))
+            errs.append(e)
+            grid_errs.append(e)
+            lay.close()
+    last = [r.final for r in recs]
+    return {
+        "tol": 1e-3,
+        "sampled_requests": len(errs),
+        "rel_err_vs_exact": {"median": float(np.median(errs)), "max": float(max(errs)),
+                             "grid_requests": len(grid_errs),
+                             "grid_max": float(max(grid_errs)) if grid_errs else None},
+        "last_stage_exact_requests": sum(1 for f in last if f[0] == 0),
+        "last_stage_grid_requests": sum(1 for f in last if f[0] != 0),
+        "rule": "box read 10 iterations before the first k = 3 iteration; N_int = ceil(1.4 W / h3(1e-3)) "
+                "(capped by the workspace), or the exact method where it costs less",
+    }
+
+
 def serving_section(T, torch, stream, requests):
     """Serving workload: Poisson arrivals of layout requests (Chung-Lu, n
     log-uniform in [1000, 200000], exponent in [2, 3], 200 iterations) and
@@ -294,7 +330,8 @@ def serving_section(T, torch, stream, requests):
     out = {"workload": "serving: Chung-Lu n log-uniform [1e3, 2e5], exponent [2, 3], mean degree 10; "
                        "30% re-tunes (alpha, beta, gamma, w_r) of resident graphs",
            "pool_graphs": pool_n, "requests": requests, "layout_iters": 200, "retune_iters": 50,
-           "hbm_budget_bytes": budget, "chunk": 10, "generation_s": gen_s}
+           "hbm_budget_bytes": budget, "chunk": 10, "generation_s": gen_s,
+           "final_stage_tol": 1e-3}
     # warm-up: kernels, allocator
     warm = sg.serving_trace(6, 1e6, pool_n, seed=1)
     for plain in (True, False):
@@ -302,20 +339,25 @@ def serving_section(T, torch, stream, requests):
         srv.run(warm)
         srv.close()
     burst = sg.serving_trace(requests, 1e9, pool_n, seed=sg.SEED_BASE + 7)
-    srv = serve.Server(pool, budget, stream=stream, plain=True)
+    srv = serve.Server(pool, budget, stream=stream, plain=True, record_outputs=True)
     t0 = time.perf_counter()
-    recs = srv.run(burst)
+    recs_seq = srv.run(burst)
     seq_s = time.perf_counter() - t0
     srv.close()
     cap = requests / seq_s
-    seq = serve.summarize(recs, seq_s)
+    seq = serve.summarize(recs_seq, seq_s)
     out["sequential"] = {"capacity_req_per_s": cap, **seq}
-    srv = serve.Server(pool, budget, stream=stream)
+    srv = serve.Server(pool, budget, stream=stream, record_outputs=True)
     t0 = time.perf_counter()
     recs = srv.run(burst)
     bat_s = time.perf_counter() - t0
     srv.close()
-    out["batched_burst"] = {"req_per_s": requests / bat_s, **serve.summarize(recs, bat_s)}
+    same = all(torch.equal(a.final_pos, b.final_pos) and a.final == b.final for a, b in zip(recs, recs_seq))
+    out["batched_burst"] = {"req_per_s": requests / bat_s, **serve.summarize(recs, bat_s),
+                            "bitwise_equal_to_sequential": bool(same)}
+    out["final_stage"] = final_stage_accuracy(T, torch, pool, burst, recs, stream)
+    print(f"# serving final stage: {json.dumps(out['final_stage'])}", file=sys.stderr, flush=True)
+    del recs, recs_seq
     loads = {}
     for f in (0.5, 0.8, 1.2):
         trace = sg.serving_trace(requests, f * cap, pool_n, seed=sg.SEED_BASE + 7)

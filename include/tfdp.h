@@ -294,9 +294,8 @@ tfdp_status tfdp_quality_sampled_noalloc(int32_t n, int64_t nnz, const int32_t* 
  * A batch steps many layout handles (graphs of any sizes, each with its own
  * parameters, grid and iteration counter) together: every phase of an
  * iteration is one launch per class of graphs that share the kernel shape
- * (k, FFT length, spreading block), whose blocks each work on one graph, and
- * groups of eight (else two) iterations are captured as HIP graphs. Each
- * member's positions and counter after tfdp_batch_step(b, iters) are
+ * (k, FFT length, spreading block), whose blocks each work on one graph.
+ * Each member's positions and counter after tfdp_batch_step(b, iters) are
  * bit-identical to those after tfdp_layout_step(h, iters) on that handle
  * alone: the blocks of a batched launch run the same kernel code on the same
  * data partition.
@@ -305,14 +304,33 @@ tfdp_status tfdp_quality_sampled_noalloc(int32_t n, int64_t nnz, const int32_t* 
  * before destroying it. A handle may be in at most one batch at a time and
  * may still be used with the plain calls between batch calls (the batch
  * picks up new parameters and counters). All calls on one batch must be
- * ordered on the device (one stream, or synchronised). Unlike the plain
- * handle, the batch allocates small device tables (member descriptors and
- * block maps, hipMalloc at the first step and when the membership changes)
- * and frees them in tfdp_batch_destroy. */
+ * ordered on the device (one stream, or synchronised).
+ *
+ * Device memory: the batch's tables live in a caller workspace (the library
+ * allocates no device memory): per member slot its kernel arguments and
+ * counter, then an arena of block maps, one region per composition (the
+ * members, their grids and the k of each). Compositions are kept for reuse;
+ * when the arena is full it is reset after one synchronisation of the
+ * stream. A composition needs at most about n/60 + nnz/200 + 4,300 map
+ * entries per member (8 bytes each; the constant covers the largest grid).
+ * Adding, removing or re-tuning members costs no synchronisation: the new
+ * kernel arguments and counters are written by small kernels on the stream
+ * at the next step. Groups of eight (else two) iterations of a composition
+ * are captured as HIP graphs the second time the same group is needed. A
+ * batch with a single member steps it by tfdp_layout_step (the same result,
+ * with the kernel tiles of a single graph). */
 typedef struct tfdp_batch tfdp_batch; /* opaque handle (host memory) */
 
-/* Empty batch for up to `capacity` members (>= 1). No device work. */
-tfdp_status tfdp_batch_create(tfdp_batch** out, int32_t capacity);
+/* Bytes of device workspace for a batch of `capacity` slots whose map arena
+ * holds `map_entries` entries (at least 256 are reserved); 0 for
+ * capacity < 1 or map_entries < 0. Host-only. */
+size_t tfdp_batch_workspace_size(int32_t capacity, int64_t map_entries);
+/* Empty batch for up to `capacity` members (>= 1) over the caller's device
+ * workspace d_ws (256-byte aligned, ws_bytes >= tfdp_batch_workspace_size(
+ * capacity, 0); the arena takes everything after the slot tables), owned by
+ * the caller and used by this batch only until tfdp_batch_destroy. No device
+ * work. TFDP_ERR_WORKSPACE for a missing, misaligned or short workspace. */
+tfdp_status tfdp_batch_create(tfdp_batch** out, int32_t capacity, void* d_ws, size_t ws_bytes);
 /* Add / remove a member (host bookkeeping; the device tables are rebuilt at
  * the next step). TFDP_ERR_INVALID_ARG: NULL, already a member (add) or not
  * a member (remove). TFDP_ERR_UNSUPPORTED: batch full, a handle whose edge
@@ -324,14 +342,16 @@ tfdp_status tfdp_batch_remove(tfdp_batch* b, tfdp_layout* h);
 int32_t tfdp_batch_count(const tfdp_batch* b);
 /* Advance every member by `iters` iterations (asynchronous, on `stream`),
  * each from its own counter t with its own k schedule and parameters
- * (k_mode 0 members run the exact method by their plain kernel). Membership
- * or counter changes since the last call cost one stream synchronisation.
- * Asynchronous failures are reported per member by tfdp_layout_sync_status. */
+ * (k_mode 0 members run the exact method by their plain kernel).
+ * TFDP_ERR_WORKSPACE if one composition needs more map entries than the
+ * arena holds. Asynchronous failures are reported per member by
+ * tfdp_layout_sync_status. */
 tfdp_status tfdp_batch_step(tfdp_batch* b, int32_t iters, hipStream_t stream);
 /* Capture groups of iterations as HIP graphs (default on; the stream must
  * then not be the legacy default stream). */
 tfdp_status tfdp_batch_set_graphs(tfdp_batch* b, int32_t enable);
-/* Free the batch and its device tables (the members stay valid). */
+/* Free the batch (host memory and captured graphs; the members and the
+ * workspace stay valid). */
 void tfdp_batch_destroy(tfdp_batch* b);
 
 #ifdef __cplusplus

@@ -19,6 +19,7 @@ from .tfdp import (  # noqa: F401
     tfdp_batch_remove,
     tfdp_batch_set_graphs,
     tfdp_batch_step,
+    tfdp_batch_workspace_size,
     tfdp_last_error,
     tfdp_layout_destroy,
     tfdp_layout_forces,

@@ -20,9 +20,14 @@ The tuner works in two stages, matching the k schedule of Sec. 3.4
   (tol / C_k)^(1/k) and margin 1.4 for the growth of the box over the last
   iterations, so that the repulsion of the last iterations is within ``tol``
   of the exact sums (k = 2 keeps the starting grid: 1e-3 at k = 2 would need
-  h ~ 0.1); where the exact method costs less than that grid
-  (``final_choice``), the last stage switches to it instead. ``retune`` applies it with tfdp_layout_set_params (the
-  workspace is sized for the cap at creation, ``workspace_grid``).
+  h ~ 0.1); C_3 grows with the kernel's narrowing for other gamma and tau
+  (``kernel_scale``). Where the exact method costs less than that grid, or
+  the grid would exceed the largest one the workspace holds (a layout wider
+  than about 87 / sqrt(kernel_scale) length units cannot meet 1e-3 on an
+  FFT of at most 2048 points per side), the last stage switches to the exact
+  method instead (``final_choice``). ``retune`` applies a grid with
+  tfdp_layout_set_params (the workspace is sized for the cap at creation,
+  ``workspace_grid``).
 
 C_k comes from ``calibrate``: exact (k = 0) against interpolated forces of
 the library on laid-out graphs at several N_int, fitted in log space.
@@ -69,16 +74,28 @@ def start_params(n: int):
     return -1, fft_rounded(n_int_for_size(n))
 
 
-def interval_width(tol: float, k: int, consts=None) -> float:
-    c = (consts or DEFAULT_C)[k]
+def kernel_scale(gamma: float = 2.0, tau: float = 1.0, k: int = 3) -> float:
+    """Factor of C_k for other t-force parameters: the kernel
+    (1 + tau d^2)^-gamma narrows as gamma and tau grow, and the k = 3 error
+    at a given h grows with it. Fit on FP64 oracle errors (a 475-node SBM
+    layout, N_int 16..64): C_3 relative to gamma = 2 was 0.21, 9.1 and 31 at
+    gamma = 1.5, 4 and 8; (gamma / 2)^3 bounds all three (0.42, 8, 64 --
+    at gamma = 4 the margin of final_n_int covers the rest). tau rescales
+    lengths by sqrt(tau): tau^(k/2)."""
+    return (gamma / 2.0) ** k * tau ** (k / 2.0)
+
+
+def interval_width(tol: float, k: int, consts=None, gamma: float = 2.0, tau: float = 1.0) -> float:
+    c = (consts or DEFAULT_C)[k] * kernel_scale(gamma, tau, k)
     return (tol / c) ** (1.0 / k)
 
 
 def final_n_int(width: float, tol: float = 1e-3, k: int = 3, consts=None, margin: float = 1.4,
-                lo: int = 8, hi: int = MAX_N_INT_K3) -> int:
+                lo: int = 8, hi: int = MAX_N_INT_K3, gamma: float = 2.0, tau: float = 1.0) -> int:
     """Intervals per side for a box of side `width` so that k-point
-    interpolation stays within `tol` (relative L2 of the repulsion)."""
-    v = math.ceil(margin * width / interval_width(tol, k, consts))
+    interpolation stays within `tol` (relative L2 of the repulsion), clamped
+    to [lo, hi]."""
+    v = math.ceil(margin * width / interval_width(tol, k, consts, gamma, tau))
     return int(min(hi, max(lo, v)))
 
 
@@ -102,11 +119,12 @@ def box_side(pos) -> float:
 
 def retune(lay, tol: float = 1e-3, consts=None, k: int = 3, cap: int | None = None) -> int:
     """Set the final-stage grid of a Layout from its current box; returns
-    the new N_int (never below the current one)."""
+    the new N_int (never below the current one; at most `cap`)."""
     from . import tfdp as T
     cur = lay.params.n_int
     hi = cap if cap is not None else MAX_N_INT_K3
-    new = max(cur, final_n_int(box_side(lay.pos), tol, k, consts, hi=hi))
+    new = max(cur, final_n_int(box_side(lay.pos), tol, k, consts, hi=hi, gamma=lay.params.gamma,
+                               tau=lay.params.tau))
     if new != cur:
         p = T.TfdpParams(**{**lay.params.as_dict(), "n_int": new})
         lay.set_params(p)
@@ -131,37 +149,45 @@ def fft_length(n_int: int, k: int) -> int:
     return l3 if l3 >= m2 and l3 in (384, 768, 1536) else L
 
 
-def final_choice(n: int, width: float, tol: float = 1e-3, consts=None):
+def final_choice(n: int, width: float, tol: float = 1e-3, consts=None, gamma: float = 2.0, tau: float = 1.0,
+                 cap: int = MAX_N_INT_K3):
     """(k_mode, N_int) for the k = 3 stage: the grid that meets `tol`, or the
-    exact method when that is cheaper than the grid."""
-    ni = final_n_int(width, tol, 3, consts)
+    exact method when that is cheaper than the grid or when the grid that
+    meets `tol` is larger than `cap` (the largest grid of the workspace)."""
+    ni = final_n_int(width, tol, 3, consts, hi=10 ** 9, gamma=gamma, tau=tau)
+    if ni > cap:
+        return 0, None
     if n <= EXACT_PER_FFT_LENGTH * fft_length(ni, 3):
         return 0, None
     return -1, ni
 
 
-def retune_many(layouts, tol: float = 1e-3, consts=None, allow_exact: bool = True):
+def retune_many(layouts, tol: float = 1e-3, consts=None, allow_exact: bool = True, caps=None):
     """The k = 3 stage choice for many Layouts (one device-to-host copy of
-    all positions): the exact method where it is cheaper, else the grid from
-    each box. Exact-method layouts keep their parameters. Returns the N_int
-    of each layout (0 for the exact method)."""
+    all positions): the exact method where it is cheaper or where the grid
+    that meets `tol` exceeds the layout's cap (caps[i], default
+    MAX_N_INT_K3), else the grid from each box. Exact-method layouts keep
+    their parameters. Returns the N_int of each layout (0 for the exact
+    method)."""
     import torch
     from . import tfdp as T
     host = torch.cat([lay.pos for lay in layouts]).cpu().numpy()
     out, off = [], 0
-    for lay in layouts:
+    for q, lay in enumerate(layouts):
         w = box_side(host[off:off + lay.n])
         off += lay.n
         cur = lay.params
         if cur.k_mode == 0:
             out.append(0)
             continue
-        k_mode, ni = final_choice(lay.n, w, tol, consts)
+        cap = caps[q] if caps is not None else MAX_N_INT_K3
+        k_mode, ni = final_choice(lay.n, w, tol, consts, cur.gamma, cur.tau, cap)
         if k_mode == 0 and allow_exact:
             lay.set_params(T.TfdpParams(**{**cur.as_dict(), "k_mode": 0}))
             out.append(0)
             continue
-        ni = max(cur.n_int, ni if ni is not None else final_n_int(w, tol, 3, consts))
+        ni = max(cur.n_int, ni if ni is not None else final_n_int(w, tol, 3, consts, hi=cap, gamma=cur.gamma,
+                                                                    tau=cur.tau))
         if ni != cur.n_int:
             lay.set_params(T.TfdpParams(**{**cur.as_dict(), "n_int": ni}))
         out.append(ni)

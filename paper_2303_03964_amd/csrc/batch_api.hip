@@ -4,8 +4,18 @@
 // block shape) whose blocks are listed in a device map {member entry, block};
 // each block runs the plain kernel's body for that graph and block, so the
 // result of every graph is bit-identical to tfdp_layout_step on it alone.
-// Groups of eight (else two) iterations of one composition (the k of every
-// member) are captured as HIP graphs.
+//
+// Device tables live in the caller's workspace: per slot the member entries
+// (one per k) and the counter at the start of a call, then an arena of block
+// maps. A member keeps its slot while it is in the batch; entries and
+// counters are written by small kernels whose arguments carry the values, so
+// that adding, removing or re-tuning a member needs no stream
+// synchronisation. A composition (the members, their grids and the k of each)
+// owns a region of the arena and is kept for reuse; groups of eight (else
+// two) of its iterations are captured as HIP graphs from the second time the
+// same group is needed (a composition used once, as when serving changes the
+// membership at every chunk, launches its kernels directly). A full arena is
+// reset after one synchronisation.
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -24,53 +34,76 @@ enum BPhase { B_BIN_COUNT, B_BIN_SCAN, B_BIN_SCATTER, B_SPREAD, B_ROWFFT, B_COLC
 struct BLaunch {
     int phase;
     int k, len, nw;  // B_BRUTE: nw = offset of the tick map (one entry per member), k = members
-    size_t off;       // first map entry
+    size_t off;       // first map entry (relative to the composition's region)
     int blocks;
     size_t lds;
 };
 
-// One composition: the k of every member and the launches of an iteration.
+// One composition: the members (slot, handle, grid) with the k of each, the
+// launches of an iteration and the maps of the call-level launches.
 struct Comp {
-    std::vector<int> ks;            // k per slot (0: exact method)
+    std::vector<long long> key;     // slot, handle uid, N_int, k for every member in slot order
     std::vector<BLaunch> launches;  // one iteration, in dependency order
-    int2* d_map = nullptr;
+    std::vector<int2> host_map;     // the region's contents (kept until the region is dropped)
+    size_t off = 0;                 // first arena entry of the region
+    int box_begin = 0, n_begin = 0, box_red = 0, n_red = 0, copy = 0, n_copy = 0;  // call-level maps
     // captured groups of 2 and kGraphIters iterations starting at an even /
-    // odd j: [2 * (size == kGraphIters) + parity of j]
+    // odd j: [2 * (size == kGraphIters) + parity of j], and how often each was needed
     hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+    int wanted[4] = {0, 0, 0, 0};
     unsigned long long last_use = 0;
 };
 
-constexpr int kMaxComps = 8;
+constexpr int kMaxComps = 64;
+constexpr int kCounterSet = 240;     // counters written per launch of kb_set_counters
+constexpr size_t kMinArena = 256;    // map entries the workspace must leave at least
 
 int entry_of(int slot, int k) { return slot * 3 + (k - 1); }
+
+struct MemberEntries {
+    Member e[3];  // k = 1, 2, 3
+};
+struct CounterSet {
+    int count;
+    int2 v[kCounterSet];  // {slot, counter}
+};
+
+__global__ void kb_set_entries(Member* dst, MemberEntries e) {
+    if (threadIdx.x < 3) dst[threadIdx.x] = e.e[threadIdx.x];
+}
+__global__ void kb_set_counters(int* tcall, CounterSet cs) {
+    const int i = threadIdx.x;
+    if (i < cs.count) tcall[cs.v[i].x] = cs.v[i].y;
+}
+__global__ void kb_zero_counters(int* tcall, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) tcall[i] = 0;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+size_t entries_bytes(int cap) { return align256((size_t)cap * 3 * sizeof(Member)); }
+size_t counters_bytes(int cap) { return align256((size_t)cap * sizeof(int)); }
 
 }  // namespace
 
 struct tfdp_batch {
     int cap;
-    std::vector<tfdp_layout*> mem;   // members in slot order
-    std::vector<unsigned int> seen;  // member version when its entries were written
-    std::vector<int2> geo;           // member {n_int, k range} when the maps were built
-    std::vector<int> t_dev;          // counter the device holds per slot for the next call
-    Member* d_mem;                   // [cap][3] entries for k = 1..3
-    int* d_t;                        // [cap] counters at the start of a call
-    int2* d_fixed;                   // maps of the box begin, box reduce and final copy
-    size_t fixed_cap;
-    int n_begin, n_red, n_copy;
-    bool dirty;  // membership changed since the entries were written
+    std::vector<tfdp_layout*> slot;            // [cap] member of each slot, or null
+    std::vector<unsigned long long> seen_uid;  // [cap] handle whose entries the slot holds (0: none)
+    std::vector<unsigned int> seen;            // [cap] that handle's version when they were written
+    std::vector<int> t_dev;                    // [cap] counter the device holds for the next call
+    int count;
+    bool counters_ready;                       // device counters initialised
+    Member* d_mem;                             // [cap][3] entries for k = 1..3 (caller's workspace)
+    int* d_t;                                  // [cap] counters at the start of a call
+    int2* d_arena;                             // block maps of the compositions
+    size_t arena_cap, arena_used;              // in entries
     bool graphs;
     std::vector<Comp> comps;
     unsigned long long clock;
 };
 
 namespace {
-
-tfdp_status upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
-    if (bytes == 0) return TFDP_OK;
-    tfdp_status st = check_hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
-    if (st == TFDP_OK) st = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
-    return st;
-}
 
 Member make_member(const tfdp_layout* h, int slot, int k) {
     Member m;
@@ -89,106 +122,45 @@ Member make_member(const tfdp_layout* h, int slot, int k) {
     return m;
 }
 
-tfdp_status write_entries(tfdp_batch* b, int slot, hipStream_t s) {
-    const tfdp_layout* h = b->mem[slot];
-    Member e[3];
-    for (int k = 1; k <= 3; ++k) e[k - 1] = make_member(h, slot, k <= h->k_ws ? k : h->k_ws);
-    b->seen[slot] = h->version;
-    b->geo[slot] = make_int2(h->p.n_int, h->k_ws);
-    return upload(b->d_mem + (size_t)slot * 3, e, sizeof(e), s);
-}
-
 void free_comp(Comp& c) {
     for (hipGraphExec_t& g : c.gexec)
         if (g) {
             (void)hipGraphExecDestroy(g);
             g = nullptr;
         }
-    if (c.d_map) (void)hipFree(c.d_map);
-    c.d_map = nullptr;
 }
 
 void drop_comps(tfdp_batch* b) {
     for (Comp& c : b->comps) free_comp(c);
     b->comps.clear();
+    b->arena_used = 0;
 }
 
 void drop_comp_graphs(tfdp_batch* b) {
-    for (Comp& c : b->comps)
-        for (hipGraphExec_t& g : c.gexec)
-            if (g) {
-                (void)hipGraphExecDestroy(g);
-                g = nullptr;
-            }
-}
-
-// Entries, counters and the fixed maps after a membership change.
-tfdp_status rebuild(tfdp_batch* b, hipStream_t s) {
-    tfdp_status st = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
-    if (st != TFDP_OK) return st;
-    drop_comps(b);
-    const int nm = (int)b->mem.size();
-    std::vector<Member> ent((size_t)nm * 3);
-    for (int i = 0; i < nm; ++i) {
-        const tfdp_layout* h = b->mem[i];
-        for (int k = 1; k <= 3; ++k) ent[(size_t)i * 3 + k - 1] = make_member(h, i, k <= h->k_ws ? k : h->k_ws);
-        b->seen[i] = h->version;
-        b->geo[i] = make_int2(h->p.n_int, h->k_ws);
-    }
-    st = upload(b->d_mem, ent.data(), ent.size() * sizeof(Member), s);
-    if (st != TFDP_OK) return st;
-    std::vector<int> tv((size_t)nm);
-    for (int i = 0; i < nm; ++i) tv[i] = b->mem[i]->t;
-    st = upload(b->d_t, tv.data(), tv.size() * sizeof(int), s);
-    if (st != TFDP_OK) return st;
-    b->t_dev = tv;
-    // fixed maps: one box-begin block per member, box-reduce blocks, copy blocks
-    std::vector<int2> fm;
-    for (int i = 0; i < nm; ++i) fm.push_back(make_int2(entry_of(i, 1), 0));
-    b->n_begin = nm;
-    for (int i = 0; i < nm; ++i) {
-        const int nb = box_reduce_dims(b->mem[i]->n).grid;
-        for (int j = 0; j < nb; ++j) fm.push_back(make_int2(entry_of(i, 1), j));
-    }
-    b->n_red = (int)fm.size() - b->n_begin;
-    for (int i = 0; i < nm; ++i) {
-        const int nb = (b->mem[i]->n + kThreads * 8 - 1) / (kThreads * 8);
-        for (int j = 0; j < nb; ++j) fm.push_back(make_int2(entry_of(i, 1), j));
-    }
-    b->n_copy = (int)fm.size() - b->n_begin - b->n_red;
-    if (fm.size() > b->fixed_cap) {
-        if (b->d_fixed) (void)hipFree(b->d_fixed);
-        b->d_fixed = nullptr;
-        b->fixed_cap = 0;
-        st = check_hip(hipMalloc(&b->d_fixed, fm.size() * sizeof(int2)), "hipMalloc");
-        if (st != TFDP_OK) return st;
-        b->fixed_cap = fm.size();
-    }
-    st = upload(b->d_fixed, fm.data(), fm.size() * sizeof(int2), s);
-    if (st != TFDP_OK) return st;
-    b->dirty = false;
-    return TFDP_OK;
+    for (Comp& c : b->comps) free_comp(c);
 }
 
 // Work of a member in a phase, for the block order of a launch: the biggest
 // graphs' blocks are dispatched first so that they do not form the tail.
 long long member_work(const tfdp_layout* h) { return (long long)h->n + h->nnz; }
 
-tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s, Comp& c) {
-    c.ks = ks;
-    const int nm = (int)b->mem.size();
+// Maps of composition c for the members in slots `act` with k values ks
+// (the launches of one iteration, then the call-level maps).
+void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<int>& ks, Comp& c) {
+    const int nm = (int)act.size();
+    auto H = [&](int i) { return b->slot[act[i]]; };
     std::vector<int> order, brute;
     for (int i = 0; i < nm; ++i) (ks[i] == 0 ? brute : order).push_back(i);
-    auto bigger_first = [&](int x, int y) { return member_work(b->mem[x]) > member_work(b->mem[y]); };
+    auto bigger_first = [&](int x, int y) { return member_work(H(x)) > member_work(H(y)); };
     std::stable_sort(order.begin(), order.end(), bigger_first);
     std::stable_sort(brute.begin(), brute.end(), bigger_first);
-    std::vector<int2> map;
+    std::vector<int2>& map = c.host_map;
     auto emit = [&](int phase, int k, int len, int nw, size_t lds, const std::vector<int>& who,
                     const std::vector<int>& blocks) {
         BLaunch L{phase, k, len, nw, map.size(), 0, lds};
         for (size_t q = 0; q < who.size(); ++q)
             for (int j = 0; j < blocks[q]; ++j)
-                map.push_back(make_int2(entry_of(who[q], ks[who[q]] > 0 ? ks[who[q]] : 1), j));
+                map.push_back(make_int2(entry_of(act[who[q]], ks[who[q]] > 0 ? ks[who[q]] : 1), j));
         L.blocks = (int)(map.size() - L.off);
         if (L.blocks > 0) c.launches.push_back(L);
     };
@@ -197,7 +169,7 @@ tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s,
         std::vector<int> bc, bs, bsc;
         size_t lds_c = 0, lds_s = 0;
         for (int i : order) {
-            const Bufs bb = bufs_for(b->mem[i], ks[i]);
+            const Bufs bb = bufs_for(H(i), ks[i]);
             const Dims dc = bin_count_dims(bb), ds = bin_scan_dims(bb), dsc = bin_scatter_dims(bb);
             bc.push_back(dc.grid);
             bs.push_back(ds.grid);
@@ -213,19 +185,17 @@ tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s,
     {
         std::map<std::tuple<int, int, int>, std::vector<int>> cls;
         for (int i : order) {
-            const tfdp_layout* h = b->mem[i];
-            const Geom g = make_geom(h->p.n_int, ks[i]);
+            const Geom g = make_geom(H(i)->p.n_int, ks[i]);
             int nw, nkb;
-            spread_dims(bufs_for(h, ks[i]), g, &nw, &nkb);
+            spread_dims(bufs_for(H(i), ks[i]), g, &nw, &nkb);
             cls[std::make_tuple(ks[i], g.L, nw)].push_back(i);
         }
         for (auto& kv : cls) {
             std::vector<int> blocks;
             size_t lds = 0;
             for (int i : kv.second) {
-                const tfdp_layout* h = b->mem[i];
                 int nw, nkb;
-                const Dims d = spread_dims(bufs_for(h, ks[i]), make_geom(h->p.n_int, ks[i]), &nw, &nkb);
+                const Dims d = spread_dims(bufs_for(H(i), ks[i]), make_geom(H(i)->p.n_int, ks[i]), &nw, &nkb);
                 blocks.push_back(d.grid);
                 lds = std::max(lds, d.lds);
             }
@@ -236,12 +206,12 @@ tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s,
     // row FFTs, column pass, inverse rows: classes by FFT length
     {
         std::map<int, std::vector<int>> cls;
-        for (int i : order) cls[make_geom(b->mem[i]->p.n_int, ks[i]).L].push_back(i);
+        for (int i : order) cls[make_geom(H(i)->p.n_int, ks[i]).L].push_back(i);
         for (int phase : {B_ROWFFT, B_COLCONV, B_ROWIFFT})
             for (auto& kv : cls) {
                 std::vector<int> blocks;
                 for (int i : kv.second) {
-                    const Geom g = make_geom(b->mem[i]->p.n_int, ks[i]);
+                    const Geom g = make_geom(H(i)->p.n_int, ks[i]);
                     int nb = 0;
                     if (phase == B_ROWFFT)
                         rowfft_dims(g, &nb, true);
@@ -260,60 +230,92 @@ tfdp_status build_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s,
         for (int i : order) cls[ks[i]].push_back(i);
         for (auto& kv : cls) {
             std::vector<int> blocks;
-            for (int i : kv.second) blocks.push_back(b->mem[i]->lay.slice[0].blocks);
+            for (int i : kv.second) blocks.push_back(H(i)->lay.slice[0].blocks);
             emit(B_EDGES, kv.first, 0, 0, 0, kv.second, blocks);
         }
     }
     // exact method: one launch for all such members, then their counters
     if (!brute.empty()) {
         std::vector<int> blocks;
-        for (int i : brute) blocks.push_back((b->mem[i]->n + kBruteRows - 1) / kBruteRows);
+        for (int i : brute) blocks.push_back((H(i)->n + kBruteRows - 1) / kBruteRows);
         const size_t tick = map.size();
-        for (int i : brute) map.push_back(make_int2(entry_of(i, 1), 0));
+        for (int i : brute) map.push_back(make_int2(entry_of(act[i], 1), 0));
         emit(B_BRUTE, (int)brute.size(), 0, (int)tick, 0, brute, blocks);
     }
-    if (!map.empty()) {
-        tfdp_status st = check_hip(hipMalloc(&c.d_map, map.size() * sizeof(int2)), "hipMalloc");
-        if (st != TFDP_OK) return st;
-        st = upload(c.d_map, map.data(), map.size() * sizeof(int2), s);
-        if (st != TFDP_OK) return st;
+    // call-level maps: a box-begin block per member, box-reduce blocks, copy blocks
+    c.box_begin = (int)map.size();
+    for (int i = 0; i < nm; ++i) map.push_back(make_int2(entry_of(act[i], 1), 0));
+    c.n_begin = nm;
+    c.box_red = (int)map.size();
+    for (int i = 0; i < nm; ++i) {
+        const int nb = box_reduce_dims(H(i)->n).grid;
+        for (int j = 0; j < nb; ++j) map.push_back(make_int2(entry_of(act[i], 1), j));
     }
-    return TFDP_OK;
+    c.n_red = (int)map.size() - c.box_red;
+    c.copy = (int)map.size();
+    for (int i = 0; i < nm; ++i) {
+        const int nb = (H(i)->n + kThreads * 8 - 1) / (kThreads * 8);
+        for (int j = 0; j < nb; ++j) map.push_back(make_int2(entry_of(act[i], 1), j));
+    }
+    c.n_copy = (int)map.size() - c.copy;
 }
 
-Comp* get_comp(tfdp_batch* b, const std::vector<int>& ks, hipStream_t s, tfdp_status* st) {
+// The composition of the members in slots `act` at k values ks: an existing
+// one, or a new one whose maps are copied into the arena (asynchronously, from
+// the composition's host copy). A full arena is reset after a
+// synchronisation of the stream (its regions may be read by enqueued work).
+// Returns the index in b->comps or -1.
+int get_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<int>& ks, hipStream_t s,
+             tfdp_status* st) {
     *st = TFDP_OK;
-    for (Comp& c : b->comps)
-        if (c.ks == ks) {
-            c.last_use = ++b->clock;
-            return &c;
-        }
-    if ((int)b->comps.size() >= kMaxComps) {
-        *st = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
-        if (*st != TFDP_OK) return nullptr;
-        auto lru = std::min_element(b->comps.begin(), b->comps.end(),
-                                    [](const Comp& x, const Comp& y) { return x.last_use < y.last_use; });
-        free_comp(*lru);
-        b->comps.erase(lru);
+    std::vector<long long> key;
+    key.reserve(act.size() * 4);
+    for (size_t i = 0; i < act.size(); ++i) {
+        const tfdp_layout* h = b->slot[act[i]];
+        key.push_back(act[i]);
+        key.push_back((long long)h->uid);
+        key.push_back(h->p.n_int);
+        key.push_back(ks[i]);
     }
-    b->comps.emplace_back();
-    Comp& c = b->comps.back();
-    *st = build_comp(b, ks, s, c);
-    if (*st != TFDP_OK) {
-        free_comp(c);
-        b->comps.pop_back();
-        return nullptr;
+    for (size_t ci = 0; ci < b->comps.size(); ++ci)
+        if (b->comps[ci].key == key) {
+            b->comps[ci].last_use = ++b->clock;
+            return (int)ci;
+        }
+    Comp c;
+    c.key = std::move(key);
+    build_comp(b, act, ks, c);
+    const size_t need = c.host_map.size();
+    if (need > b->arena_cap) {
+        set_msg("batch workspace too small: this composition needs " + std::to_string(need) +
+                " map entries, the workspace holds " + std::to_string(b->arena_cap));
+        *st = TFDP_ERR_WORKSPACE;
+        return -1;
+    }
+    if (b->arena_used + need > b->arena_cap || (int)b->comps.size() >= kMaxComps) {
+        *st = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+        if (*st != TFDP_OK) return -1;
+        drop_comps(b);
+    }
+    c.off = b->arena_used;
+    b->arena_used += need;
+    if (need > 0) {
+        *st = check_hip(hipMemcpyAsync(b->d_arena + c.off, c.host_map.data(), need * sizeof(int2),
+                                       hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+        if (*st != TFDP_OK) return -1;
     }
     c.last_use = ++b->clock;
-    return &c;
+    b->comps.push_back(std::move(c));
+    return (int)b->comps.size() - 1;
 }
 
 // Iteration j of the call (the kernels read each member's counter at the
 // start of the call from the device and add j).
 void enqueue_iter(tfdp_batch* b, const Comp& c, int j, hipStream_t s) {
     const Member* mem = b->d_mem;
+    const int2* base = b->d_arena + c.off;
     for (const BLaunch& L : c.launches) {
-        const int2* map = c.d_map + L.off;
+        const int2* map = base + L.off;
         switch (L.phase) {
             case B_BIN_COUNT: launch_b_bin_count(mem, map, L.blocks, L.lds, b->d_t, j, s); break;
             case B_BIN_SCAN: launch_b_bin_scan(mem, map, L.blocks, b->d_t, j, s); break;
@@ -323,16 +325,19 @@ void enqueue_iter(tfdp_batch* b, const Comp& c, int j, hipStream_t s) {
             case B_COLCONV: launch_b_colconv(L.len, mem, map, L.blocks, s); break;
             case B_ROWIFFT: launch_b_rowifft(L.len, mem, map, L.blocks, s); break;
             case B_EDGES: launch_b_edges(L.k, mem, map, L.blocks, b->d_t, j, s); break;
-            default: launch_b_brute(mem, map, L.blocks, c.d_map + L.nw, L.k, j, s); break;
+            default: launch_b_brute(mem, map, L.blocks, base + L.nw, L.k, j, s); break;
         }
     }
 }
 
 // Graph of `iters` (2 or kGraphIters) iterations of composition c starting
-// at a j of parity jpar (the kernels use j only through its parity).
+// at a j of parity jpar (the kernels use j only through its parity), captured
+// the second time it is needed; nullptr: launch directly.
 hipGraphExec_t group_graph(tfdp_batch* b, Comp& c, int iters, int jpar, hipStream_t s) {
-    hipGraphExec_t& ex = c.gexec[2 * (iters == 2 ? 0 : 1) + jpar];
+    const int gi = 2 * (iters == 2 ? 0 : 1) + jpar;
+    hipGraphExec_t& ex = c.gexec[gi];
     if (ex) return ex;
+    if (++c.wanted[gi] < 2) return nullptr;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
     for (int i = 0; i < iters; ++i) enqueue_iter(b, c, jpar + i, s);
     hipGraph_t graph = nullptr;
@@ -346,25 +351,42 @@ hipGraphExec_t group_graph(tfdp_batch* b, Comp& c, int iters, int jpar, hipStrea
 
 extern "C" {
 
-tfdp_status tfdp_batch_create(tfdp_batch** out, int32_t capacity) {
+size_t tfdp_batch_workspace_size(int32_t capacity, int64_t map_entries) {
+    if (capacity < 1 || map_entries < 0) return 0;
+    const size_t arena = std::max((size_t)map_entries, kMinArena);
+    return entries_bytes(capacity) + counters_bytes(capacity) + align256(arena * sizeof(int2));
+}
+
+tfdp_status tfdp_batch_create(tfdp_batch** out, int32_t capacity, void* d_ws, size_t ws_bytes) {
     set_msg("");
     if (!out || capacity < 1) {
         set_msg("invalid output pointer or capacity");
         return TFDP_ERR_INVALID_ARG;
     }
     *out = nullptr;
+    const size_t fixed = entries_bytes(capacity) + counters_bytes(capacity);
+    if (!d_ws || ws_bytes < tfdp_batch_workspace_size(capacity, 0) || (reinterpret_cast<uintptr_t>(d_ws) & 255u)) {
+        set_msg("batch workspace missing, not 256-byte aligned or smaller than tfdp_batch_workspace_size(capacity, 0)");
+        return TFDP_ERR_WORKSPACE;
+    }
     tfdp_batch* b = new (std::nothrow) tfdp_batch();
     if (!b) {
         set_msg("out of host memory");
         return TFDP_ERR_INVALID_ARG;
     }
+    char* base = static_cast<char*>(d_ws);
     b->cap = capacity;
-    b->d_mem = nullptr;
-    b->d_t = nullptr;
-    b->d_fixed = nullptr;
-    b->fixed_cap = 0;
-    b->n_begin = b->n_red = b->n_copy = 0;
-    b->dirty = true;
+    b->slot.assign((size_t)capacity, nullptr);
+    b->seen_uid.assign((size_t)capacity, 0);
+    b->seen.assign((size_t)capacity, 0);
+    b->t_dev.assign((size_t)capacity, 0);
+    b->count = 0;
+    b->counters_ready = false;
+    b->d_mem = reinterpret_cast<Member*>(base);
+    b->d_t = reinterpret_cast<int*>(base + entries_bytes(capacity));
+    b->d_arena = reinterpret_cast<int2*>(base + fixed);
+    b->arena_cap = (ws_bytes - fixed) / sizeof(int2);
+    b->arena_used = 0;
     b->graphs = true;
     b->clock = 0;
     *out = b;
@@ -377,11 +399,11 @@ tfdp_status tfdp_batch_add(tfdp_batch* b, tfdp_layout* h) {
         set_msg("invalid batch or layout handle");
         return TFDP_ERR_INVALID_ARG;
     }
-    if (std::find(b->mem.begin(), b->mem.end(), h) != b->mem.end()) {
+    if (std::find(b->slot.begin(), b->slot.end(), h) != b->slot.end()) {
         set_msg("the layout is already a member of this batch");
         return TFDP_ERR_INVALID_ARG;
     }
-    if ((int)b->mem.size() >= b->cap) {
+    if (b->count >= b->cap) {
         set_msg("the batch is full");
         return TFDP_ERR_UNSUPPORTED;
     }
@@ -393,10 +415,10 @@ tfdp_status tfdp_batch_add(tfdp_batch* b, tfdp_layout* h) {
         set_msg("batched stepping needs a fixed grid (n_int > 0)");
         return TFDP_ERR_UNSUPPORTED;
     }
-    b->mem.push_back(h);
-    b->seen.push_back(0);
-    b->geo.push_back(make_int2(0, 0));
-    b->dirty = true;
+    const int sl = (int)(std::find(b->slot.begin(), b->slot.end(), nullptr) - b->slot.begin());
+    b->slot[sl] = h;
+    b->seen_uid[sl] = 0;  // entries written at the next step
+    b->count += 1;
     return TFDP_OK;
 }
 
@@ -406,19 +428,17 @@ tfdp_status tfdp_batch_remove(tfdp_batch* b, tfdp_layout* h) {
         set_msg("invalid batch or layout handle");
         return TFDP_ERR_INVALID_ARG;
     }
-    auto it = std::find(b->mem.begin(), b->mem.end(), h);
-    if (it == b->mem.end()) {
+    auto it = std::find(b->slot.begin(), b->slot.end(), h);
+    if (it == b->slot.end()) {
         set_msg("the layout is not a member of this batch");
         return TFDP_ERR_INVALID_ARG;
     }
-    b->seen.erase(b->seen.begin() + (it - b->mem.begin()));
-    b->geo.erase(b->geo.begin() + (it - b->mem.begin()));
-    b->mem.erase(it);
-    b->dirty = true;
+    *it = nullptr;
+    b->count -= 1;
     return TFDP_OK;
 }
 
-int32_t tfdp_batch_count(const tfdp_batch* b) { return b ? (int32_t)b->mem.size() : 0; }
+int32_t tfdp_batch_count(const tfdp_batch* b) { return b ? (int32_t)b->count : 0; }
 
 tfdp_status tfdp_batch_set_graphs(tfdp_batch* b, int32_t enable) {
     if (!b) {
@@ -436,90 +456,99 @@ tfdp_status tfdp_batch_step(tfdp_batch* b, int32_t iters, hipStream_t s) {
         return TFDP_ERR_INVALID_ARG;
     }
     set_msg("");
-    const int nm = (int)b->mem.size();
-    if (iters == 0 || nm == 0) return TFDP_OK;
-    tfdp_status st = TFDP_OK;
-    if (!b->d_mem) {
-        st = check_hip(hipMalloc(&b->d_mem, (size_t)b->cap * 3 * sizeof(Member)), "hipMalloc");
-        if (st == TFDP_OK) st = check_hip(hipMalloc(&b->d_t, (size_t)b->cap * sizeof(int)), "hipMalloc");
-        if (st != TFDP_OK) return st;
+    if (iters == 0 || b->count == 0) return TFDP_OK;
+    std::vector<int> act;
+    for (int sl = 0; sl < b->cap; ++sl)
+        if (b->slot[sl]) act.push_back(sl);
+    const int nm = (int)act.size();
+    // a single member steps by the plain call: the same results (the batched
+    // launches run the plain kernels' code), with the plain passes' tiles and
+    // schedule, which suit one graph better (the batched row passes take more
+    // rows per block to fill the chip with many graphs); its device counter
+    // is written again by the next batched call
+    if (nm == 1) return tfdp_layout_step(b->slot[act[0]], iters, s);
+    if (!b->counters_ready) {
+        hipLaunchKernelGGL(kb_zero_counters, dim3((b->cap + 255) / 256), dim3(256), 0, s, b->d_t, b->cap);
+        std::fill(b->t_dev.begin(), b->t_dev.end(), 0);
+        b->counters_ready = true;
     }
-    // a new grid of a member changes the launch shapes: rebuild everything
-    for (int i = 0; i < nm && !b->dirty; ++i)
-        if (b->mem[i]->p.n_int != b->geo[i].x || b->mem[i]->k_ws != b->geo[i].y) b->dirty = true;
-    for (int i = 0; i < nm; ++i) enqueue_twiddles(b->mem[i], s);
-    if (b->dirty) {
-        st = rebuild(b, s);
-        if (st != TFDP_OK) return st;
-    } else {
-        // parameter changes: rewrite those members' entries; counters moved
-        // by the plain API: upload all counters
-        bool t_moved = false;
-        for (int i = 0; i < nm; ++i) {
-            if (b->mem[i]->version != b->seen[i]) {
-                st = write_entries(b, i, s);
-                if (st != TFDP_OK) return st;
+    // entries of new members and of members whose parameters changed, and
+    // counters moved by the plain API, written by kernels (stream order keeps
+    // them after every launch enqueued earlier)
+    CounterSet cs;
+    cs.count = 0;
+    for (int sl : act) {
+        tfdp_layout* h = b->slot[sl];
+        enqueue_twiddles(h, s);
+        if (b->seen_uid[sl] != h->uid || b->seen[sl] != h->version) {
+            MemberEntries e;
+            for (int k = 1; k <= 3; ++k) e.e[k - 1] = make_member(h, sl, k <= h->k_ws ? k : h->k_ws);
+            hipLaunchKernelGGL(kb_set_entries, dim3(1), dim3(64), 0, s, b->d_mem + (size_t)sl * 3, e);
+            b->seen_uid[sl] = h->uid;
+            b->seen[sl] = h->version;
+        }
+        if (b->t_dev[sl] != h->t) {
+            cs.v[cs.count++] = make_int2(sl, h->t);
+            b->t_dev[sl] = h->t;
+            if (cs.count == kCounterSet) {
+                hipLaunchKernelGGL(kb_set_counters, dim3(1), dim3(256), 0, s, b->d_t, cs);
+                cs.count = 0;
             }
-            if (b->mem[i]->t != b->t_dev[i]) t_moved = true;
-        }
-        if (t_moved) {
-            std::vector<int> tv((size_t)nm);
-            for (int i = 0; i < nm; ++i) tv[i] = b->mem[i]->t;
-            st = upload(b->d_t, tv.data(), tv.size() * sizeof(int), s);
-            if (st != TFDP_OK) return st;
-            b->t_dev = tv;
         }
     }
-    launch_b_box(b->d_mem, b->d_fixed, b->n_begin, b->d_fixed + b->n_begin, b->n_red, b->d_t, s);
-    std::vector<int> ks((size_t)nm), kn((size_t)nm);
+    if (cs.count > 0) hipLaunchKernelGGL(kb_set_counters, dim3(1), dim3(256), 0, s, b->d_t, cs);
+    tfdp_status st = TFDP_OK;
+    std::vector<int> ks((size_t)nm);
+    for (int i = 0; i < nm; ++i) ks[i] = k_at(b->slot[act[i]]->p, b->slot[act[i]]->t);
+    int ci = get_comp(b, act, ks, s, &st);
+    if (ci < 0) return st;
+    {
+        const Comp& c = b->comps[ci];
+        const int2* base = b->d_arena + c.off;
+        launch_b_box(b->d_mem, base + c.box_begin, c.n_begin, base + c.box_red, c.n_red, b->d_t, s);
+    }
     int j = 0;
     while (j < iters) {
-        for (int i = 0; i < nm; ++i) ks[i] = k_at(b->mem[i]->p, b->mem[i]->t + j);
-        Comp* c = get_comp(b, ks, s, &st);
-        if (!c) return st;
-        // a captured group when every member keeps its k over the next G
-        // iterations (the schedule never lowers k: the last one decides)
+        for (int i = 0; i < nm; ++i) ks[i] = k_at(b->slot[act[i]]->p, b->slot[act[i]]->t + j);
+        ci = get_comp(b, act, ks, s, &st);
+        if (ci < 0) return st;
+        // a group when every member keeps its k over the next G iterations
+        // (the schedule never lowers k: the last one decides)
         auto same_k_through = [&](int last) {
             if (last >= iters) return false;
             for (int i = 0; i < nm; ++i)
-                if (k_at(b->mem[i]->p, b->mem[i]->t + last) != ks[i]) return false;
+                if (k_at(b->slot[act[i]]->p, b->slot[act[i]]->t + last) != ks[i]) return false;
             return true;
         };
-        int G = 0;
-        if (b->graphs) {
-            if (same_k_through(j + kGraphIters - 1))
-                G = kGraphIters;
-            else if (same_k_through(j + 1))
-                G = 2;
-        }
-        if (G > 0) {
-            hipGraphExec_t ex = group_graph(b, *c, G, j & 1, s);
-            if (ex) {
-                st = check_hip(hipGraphLaunch(ex, s), "hipGraphLaunch");
-                if (st != TFDP_OK) return st;
-                j += G;
-                continue;
-            }
+        int G = 1;
+        if (same_k_through(j + kGraphIters - 1))
+            G = kGraphIters;
+        else if (same_k_through(j + 1))
+            G = 2;
+        Comp& c = b->comps[ci];
+        hipGraphExec_t ex = (b->graphs && G > 1) ? group_graph(b, c, G, j & 1, s) : nullptr;
+        if (ex) {
+            st = check_hip(hipGraphLaunch(ex, s), "hipGraphLaunch");
+            if (st != TFDP_OK) return st;
+        } else {
             (void)hipGetLastError();
+            for (int i = 0; i < G; ++i) enqueue_iter(b, c, j + i, s);
         }
-        enqueue_iter(b, *c, j, s);
-        ++j;
+        j += G;
     }
-    if (iters & 1) launch_b_copy(b->d_mem, b->d_fixed + b->n_begin + b->n_red, b->n_copy, s);
-    launch_b_advance(b->d_t, nm, iters, s);
-    for (int i = 0; i < nm; ++i) {
-        b->mem[i]->t += iters;
-        b->t_dev[i] = b->mem[i]->t;
+    if (iters & 1) {
+        const Comp& c = b->comps[ci];
+        launch_b_copy(b->d_mem, b->d_arena + c.off + c.copy, c.n_copy, s);
     }
+    launch_b_advance(b->d_t, b->cap, iters, s);
+    for (int sl = 0; sl < b->cap; ++sl) b->t_dev[sl] += iters;
+    for (int sl : act) b->slot[sl]->t += iters;
     return check_hip(hipGetLastError(), "kernel launch");
 }
 
 void tfdp_batch_destroy(tfdp_batch* b) {
     if (!b) return;
     drop_comps(b);
-    if (b->d_fixed) (void)hipFree(b->d_fixed);
-    if (b->d_t) (void)hipFree(b->d_t);
-    if (b->d_mem) (void)hipFree(b->d_mem);
     delete b;
 }
 

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/tfdp.h: parameter validation,
 // workspace layout, the per-iteration launch sequence and profiling.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -608,6 +609,8 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
     size_t bytes = 0;
     h->slice_nodes = sn;
     h->lay = carve(d_ws, n, nnz, &h->p, sn, &bytes);
+    static std::atomic<unsigned long long> next_uid{1};
+    h->uid = next_uid.fetch_add(1);
     h->overlap_mode = -1;
     h->side = nullptr;
     h->ev_fork = h->ev_join = nullptr;

@@ -2,39 +2,73 @@
 
 Requests arrive over time (a trace of synthgraphs.Request objects); the
 loop admits them while batch slots and the HBM budget allow, steps every
-active graph together in chunks of `chunk` iterations, and retires a graph
-as soon as its iterations are done, so requests that arrive while others are
-on the device join the running batch at the next chunk.
+active graph together in chunks of at most `chunk` iterations (fewer when the
+members' iterations are long, so that a chunk takes about CHUNK_SECONDS),
+and retires a
+graph as soon as its iterations are done, so requests that arrive while
+others are on the device join the running batch at the next chunk.
 
-* layout request: the graph's CSR and initial positions are uploaded, a
+* layout request: the graph's CSR and initial positions are uploaded and a
   layout handle is created with the autotuner's start choice (exact method
-  for small graphs, else its grid; workspace sized for the largest final
-  grid the tuner may choose) and added to the batch for `iters` iterations
-  (k schedule over T = iters).
+  for small graphs, else the size-rule grid; workspace sized for the largest
+  final grid the tuner may choose); `iters` iterations of the k schedule
+  over T = iters.
 * re-tune request (Sec. 5, global refinement): a finished graph stays
-  resident; the request changes alpha, beta, gamma and the repulsion weight,
+  resident; the request sets alpha, beta, gamma and the repulsion weight,
   restarts the counter with T = iters and a unit step cap, and runs again
-  from the current positions. A re-tune waits for its graph to be idle. A
-  graph evicted to make room (least recently used idle graph first) keeps
-  its positions on the host and is uploaded again when a re-tune needs it.
+  from the current positions (start grid again). A re-tune waits for its
+  graph to be idle. A graph evicted to make room (least recently used idle
+  graph first) keeps its positions on the host and is uploaded again when a
+  re-tune needs it.
+* final stage at the requested force accuracy (Sec. 3.4, "Choices of k"):
+  for every request on a grid, the box of its positions BOX_LEAD iterations
+  before its first k = 3 iteration fixes the last stage's method
+  (autotune.final_choice: the grid whose k = 3 repulsion is within `tol` of
+  the exact sums, or the exact method where that is cheaper), applied at the
+  switch. The rule depends only on the request's own positions and counter,
+  so a request gets the same choice and the same result alone (run_alone)
+  and in the mix.
 * admission by HBM footprint: CSR + positions + workspace bytes
   (tfdp_workspace_size) must fit the budget left by the resident graphs.
 
-Latency of a request = completion (positions final on the device, observed
-after a stream synchronisation at the end of the chunk that finished it)
-minus arrival. The loop runs in wall-clock time against the trace's arrival
-times; all device work is enqueued on one stream.
+Admission work (uploads, handle creation) runs on a worker thread and a
+stream of its own, so that it waits neither for the chunk on the device nor
+holds up the stepping loop; the stepping stream waits for it before the new
+member's first chunk. Members whose iterations are long (an exact stage of a
+large graph, EXPENSIVE_ITERATION) are stepped as a second batch with chunks
+of their own length, so that the others are not held to it. The host keeps
+at most two chunks in flight. Latency of a request = completion - arrival, completion
+being the device time of the event recorded after the chunk (or, plain, the
+call) that finished it, measured from an event recorded at the start of the
+run on the idle stream.
+
+plain=True serves the same trace one request at a time with
+tfdp_layout_step on the same stream (the sequential baseline), with the
+same final-stage rule.
 """
 from __future__ import annotations
 
 import time
-from collections import OrderedDict
-from dataclasses import dataclass, field
+from collections import OrderedDict, deque
+from dataclasses import dataclass
 
 import numpy as np
 
 from . import autotune
 from . import tfdp as T
+
+BOX_LEAD = 10  # iterations between reading the box and the switch to k = 3
+CHUNK_SECONDS = 2e-3  # target device time of one chunk (admission points this far apart)
+EXPENSIVE_ITERATION = 2.5e-4  # members with longer iterations are stepped as a batch of their own
+
+
+def iteration_seconds(n: int, nnz: int, exact: bool) -> float:
+    """Rough device time of one iteration of a graph on MI355X (for chunk
+    sizing only): the exact method at about 4.6e12 pair terms per second,
+    else a launch floor plus the per-node and per-entry passes."""
+    if exact:
+        return n * n / 4.6e12
+    return 25e-6 + 6e-11 * n + 7e-12 * nnz
 
 
 @dataclass
@@ -45,6 +79,7 @@ class _Graph:
     host_pos: np.ndarray | None = None  # positions while evicted
     bytes: int = 0
     busy: bool = False
+    ws_n_int: int = 0     # largest grid the workspace holds
 
 
 @dataclass
@@ -57,7 +92,9 @@ class Record:
     admitted: float = 0.0
     done: float = 0.0
     start_pos: object = None   # positions at admission (kept when record_inputs)
-    params: object = None      # TfdpParams used
+    params: object = None      # TfdpParams at admission
+    final: tuple | None = None  # (k_mode, n_int) of the last stage
+    ws_n_int: int = 0          # largest grid of the graph's workspace (cap of the last stage's grid)
     final_pos: object = None   # positions at completion (kept when record_outputs)
 
     @property
@@ -69,10 +106,78 @@ def footprint(n: int, nnz: int, ws_params) -> int:
     return 8 * n + 4 * (n + 1) + 4 * nnz + T.tfdp_workspace_size(n, nnz, ws_params) + 256
 
 
+def final_stage_points(iters: int):
+    """(t_read, t_switch): the counter at which the box is read and the first
+    k = 3 iteration of a schedule over T = iters."""
+    t_switch = (19 * iters) // 20
+    return max(0, t_switch - BOX_LEAD), t_switch
+
+
+def box_extremes(pos):
+    """(min x, min y, max x, max y) of the positions, on the current stream."""
+    import torch
+    return torch.cat([pos.amin(0), pos.amax(0)])
+
+
+def final_params(lay, ext, tol: float, cap: int):
+    """Parameters of the last stage from the box extremes `ext` (host)."""
+    e = np.asarray(ext, dtype=np.float64)
+    w = float(max(e[2] - e[0], e[3] - e[1]))
+    if not np.isfinite(w) or w <= 0:
+        w = 1.0
+    cur = lay.params
+    k_mode, ni = autotune.final_choice(lay.n, w, tol, gamma=cur.gamma, tau=cur.tau, cap=cap)
+    if k_mode == 0:
+        return T.TfdpParams(**{**cur.as_dict(), "k_mode": 0})
+    return T.TfdpParams(**{**cur.as_dict(), "n_int": max(cur.n_int, ni)})
+
+
+def run_alone(lay, iters: int, tol: float, cap: int):
+    """One request on its own handle with tfdp_layout_step, with the same
+    final-stage rule as the server. Returns the last stage's (k_mode, n_int)."""
+    if lay.params.k_mode != -1:
+        lay.step(iters)
+        return (lay.params.k_mode, lay.params.n_int)
+    t_read, t_switch = final_stage_points(iters)
+    lay.step(t_read)
+    ext = box_extremes(lay.pos).cpu().numpy()
+    lay.step(t_switch - t_read)
+    lay.set_params(final_params(lay, ext, tol, cap))
+    lay.step(iters - t_switch)
+    return (lay.params.k_mode, lay.params.n_int)
+
+
+def request_params(n: int, iters: int, extra: dict | None = None, t0: float = 0.0):
+    k_mode, n_int = autotune.start_params(n)
+    return T.tfdp_params_default(n_int=n_int, total_iters=iters, k_mode=k_mode, t0=t0, **(extra or {}))
+
+
+class _Run:
+    """A request on the device: its graph, record and counter-driven events."""
+
+    def __init__(self, g, rec, iters):
+        self.g = g
+        self.rec = rec
+        self.iters = iters
+        self.done = 0
+        self.t_read, self.t_switch = final_stage_points(iters)
+        self.tuned = g.lay.params.k_mode != -1  # exact from the start: no final choice
+        self.ext = None      # pinned host extremes
+        self.ext_ev = None   # event after their copy
+
+    def next_stop(self):
+        """Iterations to the next counter at which the server must act."""
+        stops = [self.iters]
+        if not self.tuned:
+            stops += [t for t in (self.t_read, self.t_switch) if t > self.done]
+        return min(stops) - self.done
+
+
 class Server:
     def __init__(self, pool, budget_bytes: int, slots: int = 256, chunk: int = 10, tol: float = 1e-3,
                  stream=None, record_inputs: bool = False, record_outputs: bool = False, plain: bool = False):
         import torch
+        from concurrent.futures import ThreadPoolExecutor
         self.torch = torch
         self.pool = pool                    # index -> (Graph, pos0)
         self.budget = int(budget_bytes)
@@ -80,7 +185,11 @@ class Server:
         self.chunk = chunk
         self.tol = tol
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.batch = T.Batch(slots)
+        self.admit_stream = torch.cuda.Stream(device=self.stream.device)
+        # handles are created on a worker thread (uploads, the CSR check and
+        # the host-side edge schedule of tfdp_layout_init take milliseconds
+        # for large graphs; the stepping loop keeps the GPU busy meanwhile)
+        self.worker = ThreadPoolExecutor(max_workers=1)
         self.graphs = OrderedDict()         # key -> _Graph (LRU order of idle use)
         self.used = 0
         self.record_inputs = record_inputs
@@ -90,6 +199,10 @@ class Server:
         self.plain = plain
         if plain:
             self.slots = 1
+        # two cost classes stepped as separate batches, so that members with
+        # long iterations (an exact stage of a large graph) do not hold the
+        # others to their chunk length
+        self.batches = [] if plain else [T.Batch(slots, map_entries=1 << 22) for _ in range(2)]
 
     # ---------------------------------------------------------------- memory
     def _evict_for(self, need: int) -> bool:
@@ -97,124 +210,212 @@ class Server:
             victim = next((g for g in self.graphs.values() if g.lay is not None and not g.busy), None)
             if victim is None:
                 return False
-            victim.host_pos = victim.lay.pos.cpu().numpy()
+            with self.torch.cuda.stream(self.stream):
+                victim.host_pos = victim.lay.pos.cpu().numpy()
             victim.lay.close()
             victim.lay = None
             self.used -= victim.bytes
         return True
 
-    def _make_layout(self, g: _Graph, pos, params):
+    def _build(self, g: _Graph, pos_host, params, ws):
+        """Worker thread: upload and create the graph's handle."""
+        torch = self.torch
+        with torch.cuda.stream(self.admit_stream):
+            pos = torch.as_tensor(pos_host).to(self.stream.device)
+            lay = T.Layout(g.graph.row_ptr, g.graph.col_idx, pos, params, workspace_params=ws)
+            # the tensors are used on the stepping stream from now on
+            for t in (lay.row_ptr, lay.col_idx, lay.pos, lay.workspace):
+                t.record_stream(self.stream)
+        return lay
+
+    def _reserve(self, g: _Graph, params):
+        """Reserve the HBM footprint of the graph's handle (evicting idle
+        graphs if needed); returns the workspace parameters or None."""
         n, nnz = g.graph.n, g.graph.nnz
         ws = params if params.k_mode == 0 else T.TfdpParams(
             **{**params.as_dict(), "n_int": max(params.n_int, autotune.workspace_grid(n)), "k_mode": -1})
         need = footprint(n, nnz, ws)
         if not self._evict_for(need):
-            return False
-        g.lay = T.Layout(g.graph.row_ptr, g.graph.col_idx, pos, params, workspace_params=ws)
+            return None
         g.bytes = need
+        g.ws_n_int = ws.n_int
         self.used += need
-        return True
+        return ws
 
     # ---------------------------------------------------------------- admission
-    def _admit(self, req, rec: Record, active: dict) -> bool:
-        torch = self.torch
-        if len(active) >= self.slots:
+    def _admit(self, req, active: dict, preparing: dict) -> bool:
+        if len(active) + len(preparing) >= self.slots:
             return False
         if req.kind == "layout":
             graph, pos0 = self.pool[req.graph]
             g = _Graph(req.rid, graph)
-            k_mode, n_int = autotune.start_params(graph.n)
-            p = T.tfdp_params_default(n_int=n_int, total_iters=req.iters, k_mode=k_mode)
-            if not self._make_layout(g, torch.as_tensor(pos0).cuda(), p):
+            p = request_params(graph.n, req.iters)
+            ws = self._reserve(g, p)
+            if ws is None:
                 return False
             self.graphs[req.rid] = g
-        else:
-            g = self.graphs.get(req.target)
-            if g is None or g.busy:
-                return False  # target not laid out yet, or still running
-            base = g.lay.params if g.lay is not None else self._last_params[req.target]
-            p = T.TfdpParams(**{**base.as_dict(), **req.params, "total_iters": req.iters, "t0": 1.0})
-            if g.lay is None:
-                if not self._make_layout(g, torch.as_tensor(g.host_pos).cuda(), p):
-                    return False
-                g.host_pos = None
-            else:
-                g.lay.set_params(p)
-            g.lay.iteration = 0
-            self.graphs.move_to_end(req.target)
+            g.busy = True
+            preparing[req.rid] = (req, g, self.worker.submit(self._build, g, pos0, p, ws))
+            return True
+        g = self.graphs.get(req.target)
+        if g is None or g.busy:
+            return False  # target not laid out yet, or still running
+        p = request_params(g.graph.n, req.iters, req.params, t0=1.0)
+        self.graphs.move_to_end(req.target)
+        if g.lay is None:
+            ws = self._reserve(g, p)
+            if ws is None:
+                return False
+            g.busy = True
+            preparing[req.rid] = (req, g, self.worker.submit(self._build, g, g.host_pos, p, ws))
+            g.host_pos = None
+            return True
+        g.lay.set_params(p)
+        g.lay.iteration = 0
         g.busy = True
-        rec.n = g.graph.n
-        rec.params = g.lay.params
-        if self.record_inputs:
-            rec.start_pos = g.lay.pos.clone()
-        if not self.plain:
-            self.batch.add(g.lay)
-        active[req.rid] = (g, req.iters, rec)
+        preparing[req.rid] = (req, g, None)
         return True
 
+    def _activate(self, req, g: _Graph, rec: Record, active: dict):
+        torch = self.torch
+        rec.n = g.graph.n
+        rec.params = g.lay.params
+        rec.ws_n_int = g.ws_n_int
+        self.stream.wait_stream(self.admit_stream)
+        if self.record_inputs:
+            rec.start_pos = g.lay.pos.clone()
+        run = _Run(g, rec, req.iters)
+        run.group = -1
+        active[req.rid] = run
+
+    def _retire(self, run: _Run, event):
+        rec = run.rec
+        rec.done_event = event
+        rec.final = (run.g.lay.params.k_mode, run.g.lay.params.n_int)
+        if self.record_outputs:
+            rec.final_pos = run.g.lay.pos.clone()
+        if not self.plain and run.group >= 0:
+            self.batches[run.group].remove(run.g.lay)
+        run.g.busy = False
+        self.graphs.move_to_end(run.g.key)
+
     # ---------------------------------------------------------------- loop
+    def _final_stage_events(self, active):
+        """Box read at t_read (device reduction, copy to pinned memory) and the
+        last stage's parameters at t_switch, for runs that reached them."""
+        torch = self.torch
+        for run in active.values():
+            if run.tuned:
+                continue
+            if run.done == run.t_read and run.ext is None:
+                ext = box_extremes(run.g.lay.pos)
+                run.ext = torch.empty(4, dtype=ext.dtype, pin_memory=True)
+                run.ext.copy_(ext, non_blocking=True)
+                run.ext_ev = torch.cuda.Event()
+                run.ext_ev.record(self.stream)
+            if run.done == run.t_switch:
+                run.ext_ev.synchronize()
+                run.g.lay.set_params(final_params(run.g.lay, run.ext.numpy(), self.tol, run.g.ws_n_int))
+                run.tuned = True
+
+    def _step_batched(self, active):
+        """One chunk of every active run, per cost class; returns the runs that
+        finished and the event after the chunk."""
+        torch = self.torch
+        self._final_stage_events(active)
+        groups = ([], [])
+        for run in active.values():
+            cost = iteration_seconds(run.g.graph.n, run.g.graph.nnz, run.g.lay.params.k_mode == 0)
+            grp = 1 if cost > EXPENSIVE_ITERATION else 0
+            if grp != run.group:
+                if run.group >= 0:
+                    self.batches[run.group].remove(run.g.lay)
+                self.batches[grp].add(run.g.lay)
+                run.group = grp
+            groups[grp].append((run, cost))
+        for grp, members in enumerate(groups):
+            if not members:
+                continue
+            # at most `chunk` iterations, fewer when the members' iterations
+            # are long, so that a chunk takes about CHUNK_SECONDS
+            per_iter = sum(c for _, c in members)
+            cap_iters = max(1, min(self.chunk, int(CHUNK_SECONDS / max(per_iter, 1e-9))))
+            step = min(cap_iters, min(r.next_stop() for r, _ in members))
+            self.batches[grp].step(step)
+            for r, _ in members:
+                r.done += step
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(self.stream)
+        return [rid for rid, r in active.items() if r.done == r.iters], ev
+
     def run(self, trace):
         """Serve the trace; returns the list of Records in request order."""
         torch = self.torch
-        self._last_params = {}
         recs = {r.rid: Record(r.rid, r.kind, 0, r.iters, r.arrival) for r in trace}
         pending = sorted(trace, key=lambda r: r.arrival)
         waiting = []
-        active = {}   # rid -> (graph, remaining, record)
+        active = {}      # rid -> _Run
+        preparing = {}   # rid -> (request, graph, future or None)
+        inflight = deque()
         i = 0
-        t_start = time.perf_counter()
         with torch.cuda.stream(self.stream):
-            while i < len(pending) or waiting or active:
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev0.record(self.stream)
+            t_start = time.perf_counter()
+            while i < len(pending) or waiting or active or preparing:
                 now = time.perf_counter() - t_start
                 while i < len(pending) and pending[i].arrival <= now:
                     waiting.append(pending[i])
                     i += 1
                 still = []
                 for req in waiting:
-                    if self._admit(req, recs[req.rid], active):
+                    if self._admit(req, active, preparing):
                         recs[req.rid].admitted = time.perf_counter() - t_start
                     else:
                         still.append(req)
                 waiting = still
+                for rid in [r for r, (_, _, f) in preparing.items() if f is None or f.done()]:
+                    req, g, fut = preparing.pop(rid)
+                    if fut is not None:
+                        g.lay = fut.result()
+                    self._activate(req, g, recs[rid], active)
                 if not active:
-                    if i < len(pending):
-                        time.sleep(max(0.0, min(pending[i].arrival - (time.perf_counter() - t_start), 0.01)))
+                    if preparing:
+                        time.sleep(2e-4)
+                    elif i < len(pending):
+                        time.sleep(max(0.0, min(pending[i].arrival - (time.perf_counter() - t_start), 0.002)))
                     elif waiting:
                         raise RuntimeError("requests cannot be admitted: budget or slots too small")
                     continue
                 if self.plain:
-                    step = min(rem for _, rem, _ in active.values())
-                    for g, _, _ in active.values():
-                        g.lay.step(step)
+                    rid = next(iter(active))
+                    run = active.pop(rid)
+                    run_alone(run.g.lay, run.iters, self.tol, run.g.ws_n_int)
+                    ev = torch.cuda.Event(enable_timing=True)
+                    ev.record(self.stream)
+                    run.done = run.iters
+                    self._retire(run, ev)
                 else:
-                    step = min(self.chunk, min(rem for _, rem, _ in active.values()))
-                    self.batch.step(step)
-                finished = []
-                for rid in list(active):
-                    g, rem, rec = active[rid]
-                    rem -= step
-                    active[rid] = (g, rem, rec)
-                    if rem == 0:
-                        finished.append(rid)
-                if finished:
-                    torch.cuda.synchronize()
-                    t_done = time.perf_counter() - t_start
+                    finished, ev = self._step_batched(active)
                     for rid in finished:
-                        g, _, rec = active.pop(rid)
-                        rec.done = t_done
-                        if self.record_outputs:
-                            rec.final_pos = g.lay.pos.clone()
-                        if g.lay.sync_status() != 0:
-                            raise RuntimeError(f"request {rid}: non-finite positions")
-                        if not self.plain:
-                            self.batch.remove(g.lay)
-                        self._last_params[g.key] = g.lay.params
-                        g.busy = False
-                        self.graphs.move_to_end(g.key)
+                        self._retire(active.pop(rid), ev)
+                inflight.append(ev)
+                while len(inflight) > 2:
+                    inflight.popleft().synchronize()
+            torch.cuda.synchronize()
+            for r in recs.values():
+                r.done = ev0.elapsed_time(r.done_event) * 1e-3
+                del r.done_event
+            for g in self.graphs.values():
+                if g.lay is not None and g.lay.sync_status() != 0:
+                    raise RuntimeError(f"graph of request {g.key}: non-finite positions")
         return [recs[r.rid] for r in trace]
 
     def close(self):
-        self.batch.close()
+        self.worker.shutdown(wait=True)
+        for b in self.batches:
+            b.close()
         for g in self.graphs.values():
             if g.lay is not None:
                 g.lay.close()

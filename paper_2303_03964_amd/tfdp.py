@@ -83,7 +83,8 @@ _SIGS = {
                                        c_void_p]),
     "tfdp_quality_sampled_noalloc": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
                                                POINTER(c_double), POINTER(c_double), POINTER(c_int32), c_void_p]),
-    "tfdp_batch_create": (c_int32, [POINTER(c_void_p), c_int32]),
+    "tfdp_batch_workspace_size": (c_size_t, [c_int32, c_int64]),
+    "tfdp_batch_create": (c_int32, [POINTER(c_void_p), c_int32, c_void_p, c_size_t]),
     "tfdp_batch_add": (c_int32, [c_void_p, c_void_p]),
     "tfdp_batch_remove": (c_int32, [c_void_p, c_void_p]),
     "tfdp_batch_count": (c_int32, [c_void_p]),
@@ -297,9 +298,13 @@ def tfdp_quality_sampled_noalloc(row_ptr, col_idx, pos, sources, stream=None):
     return se.value, (np_[0], np_[1]), lv.value
 
 
-def tfdp_batch_create(capacity):
+def tfdp_batch_workspace_size(capacity, map_entries) -> int:
+    return int(load_library().tfdp_batch_workspace_size(capacity, map_entries))
+
+
+def tfdp_batch_create(capacity, workspace):
     b = c_void_p()
-    _check(load_library().tfdp_batch_create(ctypes.byref(b), capacity))
+    _check(load_library().tfdp_batch_create(ctypes.byref(b), capacity, _ptr(workspace), int(workspace.numel())))
     return b
 
 
@@ -421,10 +426,18 @@ class Layout:
 
 
 class Batch:
-    """A tfdp_batch over Layout objects (kept alive while they are members)."""
+    """A tfdp_batch over Layout objects (kept alive while they are members),
+    with its device workspace: slot tables for `capacity` members and an
+    arena of `map_entries` block-map entries (8 bytes each)."""
 
-    def __init__(self, capacity):
-        self.handle = tfdp_batch_create(capacity)
+    def __init__(self, capacity, map_entries=1 << 22, device="cuda"):
+        size = tfdp_batch_workspace_size(capacity, map_entries)
+        if size == 0:
+            raise TfdpError(-1, "invalid batch capacity or arena size")
+        ws = torch.empty(size + 256, dtype=torch.uint8, device=torch.device(device))
+        off = (-ws.data_ptr()) % 256
+        self.workspace = ws[off:off + size]
+        self.handle = tfdp_batch_create(capacity, self.workspace)
         self.members = []
 
     def add(self, lay: Layout):

@@ -147,9 +147,16 @@ def test_params_struct_layout(tmp_path):
 def test_batch_host_bookkeeping():
     lib = T.load_library()
     out = ctypes.c_void_p()
-    assert lib.tfdp_batch_create(None, 4) == INVALID
-    assert lib.tfdp_batch_create(ctypes.byref(out), 0) == INVALID
-    assert lib.tfdp_batch_create(ctypes.byref(out), 4) == OK and out.value
+    need = T.tfdp_batch_workspace_size(4, 0)
+    assert need > 0 and T.tfdp_batch_workspace_size(0, 10) == 0 and T.tfdp_batch_workspace_size(4, -1) == 0
+    assert T.tfdp_batch_workspace_size(4, 1 << 20) >= need + (1 << 20) * 8 - 8 * 256
+    fake = ctypes.c_void_p(0x100000)  # never dereferenced: no step runs with members
+    assert lib.tfdp_batch_create(None, 4, fake, need) == INVALID
+    assert lib.tfdp_batch_create(ctypes.byref(out), 0, fake, need) == INVALID
+    assert lib.tfdp_batch_create(ctypes.byref(out), 4, None, need) == WORKSPACE
+    assert lib.tfdp_batch_create(ctypes.byref(out), 4, fake, need - 1) == WORKSPACE
+    assert lib.tfdp_batch_create(ctypes.byref(out), 4, ctypes.c_void_p(0x100040), need) == WORKSPACE
+    assert lib.tfdp_batch_create(ctypes.byref(out), 4, fake, need) == OK and out.value
     b = out
     assert lib.tfdp_batch_count(b) == 0 and lib.tfdp_batch_count(None) == 0
     # NULL members and removal of a non-member are rejected without device work

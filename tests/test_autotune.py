@@ -38,20 +38,22 @@ def test_box_side():
     assert autotune.box_side(p) == pytest.approx(3.0)
 
 
-@pytest.mark.parametrize("index", [1, 11, 13])
-def test_error_model_against_oracle(index):
-    """Lay out a batch-workload graph with the oracle, pick the final grid for
-    tol = 1e-3 and check the oracle's k = 3 interpolated repulsion against its
-    exact sums."""
+@pytest.mark.parametrize("index,gamma", [(1, 2.0), (11, 2.0), (13, 2.0), (1, 4.0), (1, 1.5)])
+def test_error_model_against_oracle(index, gamma):
+    """Lay out a batch-workload graph with the oracle (gamma = 2), pick the
+    final grid for tol = 1e-3 and the given gamma (a re-tune that changes
+    gamma starts from such a layout) and check the oracle's k = 3
+    interpolated repulsion against its exact sums."""
     g, pos0 = sg.sbm_batch_member(index)
     if g.n > 1500:
         pytest.skip("kept small for the CPU suite")
     p = ot.Params(n_int=autotune.n_int_for_size(g.n), total_iters=300, k_mode=1)
     x = ot.layout(pos0.astype(np.float64), g.row_ptr, g.col_idx, p, iters=270)
     tol = 1e-3
-    ni = autotune.final_n_int(autotune.box_side(x), tol)
-    ex = ot.repulsion_exact(x, 2.0)
-    fr = ot.repulsion_ibfft_stable(x, 2.0, ni, 3)
+    ni = autotune.final_n_int(autotune.box_side(x), tol, gamma=gamma)
+    assert ni < autotune.MAX_N_INT_K3  # the tested grids are within the cap
+    ex = ot.repulsion_exact(x, gamma)
+    fr = ot.repulsion_ibfft_stable(x, gamma, ni, 3)
     err = np.linalg.norm(fr - ex) / np.linalg.norm(ex)
     assert err <= tol, (g.n, ni, err)
 
@@ -59,9 +61,18 @@ def test_error_model_against_oracle(index):
 def test_final_choice_prefers_exact_when_cheaper():
     # a few thousand nodes in a wide box: a 1e-3 grid is far costlier than n^2
     assert autotune.final_choice(5000, 60.0)[0] == 0
-    # a million nodes: the grid
-    k_mode, ni = autotune.final_choice(1_000_000, 300.0)
-    assert k_mode == -1 and ni == autotune.MAX_N_INT_K3
+    # a million nodes in a box the largest grid resolves: the grid
+    k_mode, ni = autotune.final_choice(1_000_000, 60.0)
+    assert k_mode == -1 and ni == math.ceil(1.4 * 60.0 / autotune.interval_width(1e-3, 3))
+    # a box too wide for 1e-3 on the largest grid (or on the workspace's
+    # cap): the exact method, whatever it costs
+    assert autotune.final_choice(1_000_000, 300.0) == (0, None)
+    assert autotune.final_choice(1_000_000, 60.0, cap=200) == (0, None)
+    # a narrower kernel (gamma 8) needs a finer grid at the same box
+    assert autotune.final_choice(1_000_000, 30.0)[0] == -1
+    assert autotune.final_choice(1_000_000, 30.0, gamma=8.0) == (0, None)
+    assert autotune.kernel_scale(2.0, 1.0) == 1.0 and autotune.kernel_scale(4.0, 1.0) == 8.0
+    assert autotune.kernel_scale(2.0, 4.0) == 8.0
     assert autotune.fft_length(64, 1) == 128 and autotune.fft_length(341, 3) == 2048
     # radix-3 lengths where 3 * 2^a >= 2M is shorter than the power of two
     assert [autotune.fft_length(n, 3) for n in (64, 128, 256, 300)] == [384, 768, 1536, 2048]

@@ -262,3 +262,93 @@ def test_batch_members_match_oracle_one_step(T, stream):
         B.close()
         for it in items:
             it[-1].close()
+
+
+def test_batch_churn_reuse_and_arena_resets(T, stream):
+    """Members join, leave and re-join over many short calls (the serving
+    pattern), with an arena of the minimum size, so that compositions are
+    built, reused (captured on their second use) and dropped by arena resets;
+    every member stays bit-identical to its plain twin."""
+    import torch
+    with torch.cuda.stream(stream):
+        gs = graphs([0, 1, 2, 4, 7])
+        lays = [pair(T, g, pos, [32, 48, 16, 24, 40][q], 80, {}) for q, (g, pos) in enumerate(gs)]
+        B = T.Batch(3, map_entries=3000)  # room for a few compositions: resets
+        plan = [  # (members in the batch during the call, iterations)
+            ({0, 1}, 4), ({0, 1}, 4), ({0, 1, 2}, 3), ({1, 2}, 5), ({1, 2, 3}, 6), ({1, 2, 3}, 6),
+            ({2, 3, 4}, 7), ({0, 3, 4}, 2), ({0, 3, 4}, 2), ({0, 1, 4}, 9), ({0, 1}, 4), ({0, 1}, 4),
+        ]
+        inside = set()
+        for members, iters in plan:
+            for q in sorted(inside - members):
+                B.remove(lays[q][0])
+            for q in sorted(members - inside):
+                B.add(lays[q][0])
+            inside = set(members)
+            B.step(iters)
+            for q in members:
+                lays[q][1].step(iters)
+        torch.cuda.synchronize()
+        for q, (a, b) in enumerate(lays):
+            assert a.sync_status() == 0
+            assert a.iteration == b.iteration, q
+            assert torch.equal(a.pos, b.pos), q
+        B.close()
+
+
+def test_batch_arena_too_small_is_reported(T, stream):
+    """A composition larger than the whole arena is refused with
+    TFDP_ERR_WORKSPACE (nothing stepped); a larger arena then runs it."""
+    import torch
+    with torch.cuda.stream(stream):
+        lays = []
+        for q, g in enumerate([sg.chung_lu(60_000, 2.5, 10.0, 5), sg.sbm([400, 300], 0.02, 0.002, 6)]):
+            pos = sg.uniform_positions(g.n, 6 + q)
+            lays.append(T.Layout(g.row_ptr, g.col_idx, torch.as_tensor(pos).cuda(),
+                                 T.tfdp_params_default(n_int=[96, 32][q])))
+        B = T.Batch(2, map_entries=0)  # the minimum arena (256 entries)
+        for lay in lays:
+            B.add(lay)
+        with pytest.raises(T.TfdpError) as e:
+            B.step(2)
+        assert e.value.status == -2 and "map entries" in str(e.value)
+        # the same members step in a batch whose arena holds their composition
+        B.close()
+        B2 = T.Batch(2, map_entries=1 << 16)
+        for lay in lays:
+            B2.add(lay)
+        B2.step(2)
+        torch.cuda.synchronize()
+        for lay in lays:
+            assert lay.sync_status() == 0 and lay.iteration == 2
+        B2.close()
+        for lay in lays:
+            lay.close()
+
+
+def test_single_member_batch_equals_plain(T, stream):
+    """A batch of one steps its member by the plain call; joining and
+    leaving members switch between that and the batched launches without
+    changing any result."""
+    import torch
+    with torch.cuda.stream(stream):
+        gs = graphs([3, 5])
+        lays = [pair(T, g, pos, [48, 32][q], 50, {}) for q, (g, pos) in enumerate(gs)]
+        B = T.Batch(2)
+        B.add(lays[0][0])
+        for calls, members in (((7, 5), (0,)), ((9,), (0, 1)), ((6, 3), (0,)), ((20,), (0, 1))):
+            for q in (0, 1):
+                inside = any(m is lays[q][0] for m in B.members)
+                if q in members and not inside:
+                    B.add(lays[q][0])
+                elif q not in members and inside:
+                    B.remove(lays[q][0])
+            for c in calls:
+                B.step(c)
+                for q in members:
+                    lays[q][1].step(c)
+        torch.cuda.synchronize()
+        for a, b in lays:
+            assert a.iteration == b.iteration
+            assert torch.equal(a.pos, b.pos)
+        B.close()

@@ -6,8 +6,11 @@ graphs is served with a tight HBM budget (so that requests queue, graphs are
 evicted and re-uploaded) and chunked batched steps (so that requests join
 and leave a running batch). Each request is then replayed alone: a fresh
 layout handle with the request's parameters and starting positions, stepped
-by tfdp_layout_step for the request's iterations. Tolerance: bit-identical
-positions (the batch runs the plain kernels' code per graph).
+by tfdp_layout_step for the request's iterations, with the same final-stage
+rule (the grid or exact method of the last 5 % chosen from the box 10
+iterations before the switch, for a repulsion error of 1e-3). Tolerance:
+bit-identical positions and the same final-stage choice (the batch runs the
+plain kernels' code per graph).
 """
 import sys
 
@@ -65,16 +68,21 @@ def test_results_same_alone_and_in_the_mix(T):
     s = serve.summarize(recs)
     say(f"served: {s}")
     assert all(r.done > 0 for r in recs)
+    finals = set()
     with torch.cuda.stream(stream):
         for r, req in zip(recs, trace):
             g = pool[req.graph][0] if req.kind == "layout" else pool[trace[req.target].graph][0]
-            lay = T.Layout(g.row_ptr, g.col_idx, r.start_pos.clone(), r.params)
-            lay.step(r.iters)
+            ws = T.TfdpParams(**{**r.params.as_dict(), "n_int": r.ws_n_int, "k_mode": -1})
+            lay = T.Layout(g.row_ptr, g.col_idx, r.start_pos.clone(), r.params, workspace_params=ws)
+            final = serve.run_alone(lay, r.iters, 1e-3, r.ws_n_int)
             torch.cuda.synchronize()
             same = torch.equal(lay.pos, r.final_pos)
-            say(f"request {r.rid} {r.kind} n={r.n} latency {r.latency * 1e3:.1f} ms same={same}")
-            assert same
+            say(f"request {r.rid} {r.kind} n={r.n} latency {r.latency * 1e3:.1f} ms start grid "
+                f"{r.params.k_mode}/{r.params.n_int} last stage {r.final} (alone {final}) same={same}")
+            assert same and tuple(final) == tuple(r.final)
+            finals.add(r.final)
             lay.close()
+    say(f"last stages chosen: {sorted(finals)}")
     # the first re-tune request's first iteration against the FP64 oracle
     # (Sec. 5 global refinement: new weights, unit step cap, the schedule
     # restarted): a replay alone equals the served result bit for bit
