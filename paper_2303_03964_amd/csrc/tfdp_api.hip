@@ -322,12 +322,14 @@ bool use_overlap(tfdp_layout* h) {
     bool ok = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&h->ev_node, hipEventDisableTiming) == hipSuccess;
     if (cur != h->device) (void)hipSetDevice(cur);
     if (!ok) {
         if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
         if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+        if (h->ev_node) (void)hipEventDestroy(h->ev_node);
         if (h->side) (void)hipStreamDestroy(h->side);
-        h->ev_fork = h->ev_join = nullptr;
+        h->ev_fork = h->ev_join = h->ev_node = nullptr;
         h->side = nullptr;
         h->overlap_mode = 0;
         (void)hipGetLastError();
@@ -375,11 +377,58 @@ void drop_graphs(tfdp_layout* h) {
                     }
 }
 
-// One interpolated iteration (k >= 1) from cur to alt; `set` = t & 1 selects
-// the box-extremes slot set read now (set ^ 1 is filled by the update).
-void enqueue_iteration(tfdp_layout* h, int k, int set, const float2* cur, float2* alt, const ModelArgs& a,
-                       hipStream_t s) {
-    enqueue_evaluation(h, k, set, cur, alt, a, nullptr, nullptr, nullptr, s);
+// `iters` consecutive interpolated iterations (k >= 1) from positions A
+// (then alternating between B and A); `parity` = t & 1 of the first selects
+// its box-extremes slot set. Overlapped schedule, pipelined over the run:
+// the attraction pass and the node pass of every iteration follow each other
+// on the second stream, and the grid passes of an iteration (on s) start
+// when the node pass of the previous one is done:
+//   side: attract(t), [wait grid(t)] node(t), attract(t + 1), [wait grid(t + 1)] node(t + 1), ...
+//   s:    grid(t), [wait node(t)] grid(t + 1), [wait node(t + 1)] ...
+// At k = 1 on the 1M-node graph the attraction pass is the longer branch, so
+// its stream runs back to back and only the grid passes wait across
+// streams. s waits for the last node pass, so the run ends ordered on s.
+void enqueue_run(tfdp_layout* h, int k, int parity, float2* A, float2* B, int iters, const ModelArgs& a,
+                 hipStream_t s) {
+    if (!use_overlap(h)) {
+        for (int i = 0; i < iters; ++i) {
+            enqueue_evaluation(h, k, (parity + i) & 1, A, B, a, nullptr, nullptr, nullptr, s);
+            float2* t = A;
+            A = B;
+            B = t;
+        }
+        return;
+    }
+    const Bufs b = bufs_for(h, k);
+    const Geom g = make_geom(h->p.n_int, k);
+    const int ab = h->attract_blocks[k <= 1 ? 0 : 1];
+    (void)hipEventRecord(h->ev_fork, s);
+    (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
+    {
+        PhaseTimer pt(h, PH_ATTRACT, h->side);
+        launch_attract(A, h->lay.slice[0], h->lay.fpart, b, g, a, ab, h->side);
+    }
+    for (int i = 0; i < iters; ++i) {
+        const int set = (parity + i) & 1;
+        enqueue_grid(h, A, b, g, set, s);
+        (void)hipEventRecord(h->ev_join, s);
+        (void)hipStreamWaitEvent(h->side, h->ev_join, 0);
+        {
+            PhaseTimer pt(h, PH_NODE, h->side);
+            launch_node_update(A, B, h->lay.fpart, b, g, a, set ^ 1, nullptr, nullptr, nullptr, h->side);
+        }
+        // the next grid passes wait for this node pass only, not for the
+        // attraction pass queued behind it
+        (void)hipEventRecord(h->ev_node, h->side);
+        (void)hipStreamWaitEvent(s, h->ev_node, 0);
+        if (i + 1 < iters) {
+            PhaseTimer pt(h, PH_ATTRACT, h->side);
+            launch_attract(B, h->lay.slice[0], h->lay.fpart, b, g, a, ab, h->side);
+        }
+        float2* t = A;
+        A = B;
+        B = t;
+    }
 }
 
 // Graph of `iters` (2 or kGraphIters, even) consecutive iterations at k
@@ -399,12 +448,7 @@ hipGraphExec_t group_graph(tfdp_layout* h, int iters, int k, int parity, int ori
         B = t;
     }
     if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
-    for (int i = 0; i < iters; ++i) {
-        enqueue_iteration(h, k, (parity + i) & 1, A, B, a, s);
-        float2* t = A;
-        A = B;
-        B = t;
-    }
+    enqueue_run(h, k, parity, A, B, iters, a, s);
     hipGraph_t graph = nullptr;
     if (hipStreamEndCapture(s, &graph) != hipSuccess || !graph) return nullptr;
     if (hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
@@ -613,7 +657,7 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
     h->uid = next_uid.fetch_add(1);
     h->overlap_mode = -1;
     h->side = nullptr;
-    h->ev_fork = h->ev_join = nullptr;
+    h->ev_fork = h->ev_join = h->ev_node = nullptr;
     h->device = 0;
     int cus = 0;
     st = check_hip(hipGetDevice(&h->device), "hipGetDevice");
@@ -712,7 +756,7 @@ static tfdp_status step_fixed_grid(tfdp_layout* h, int32_t iters, hipStream_t s)
             launch_brute(cur, alt, h->row_ptr, h->col_idx, h->n, h->lay.b.st, a, h->t, nullptr, nullptr,
                          nullptr, s);
         } else {
-            enqueue_iteration(h, k, h->t & 1, cur, alt, a, s);
+            enqueue_run(h, k, h->t & 1, cur, alt, 1, a, s);
         }
         float2* tmp = cur;
         cur = alt;
@@ -848,6 +892,7 @@ void tfdp_layout_destroy(tfdp_layout* h) {
     drop_graphs(h);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->ev_node) (void)hipEventDestroy(h->ev_node);
     if (h->side) (void)hipStreamDestroy(h->side);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     delete h;

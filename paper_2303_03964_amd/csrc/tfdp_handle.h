@@ -100,7 +100,7 @@ struct tfdp_layout {
     int device;             // device current at init (the second stream is created on it)
     int attract_blocks[2];  // blocks of the overlapped attraction pass at k = 1 and at k = 2, 3
     hipStream_t side;       // second stream of the overlapped attraction pass (created on first use)
-    hipEvent_t ev_fork, ev_join;
+    hipEvent_t ev_fork, ev_join, ev_node;  // start of a run, grid passes done, node pass done
     unsigned long long uid; // unique per handle of the process (batch compositions are keyed by it)
 };
 

@@ -37,7 +37,9 @@ holds up the stepping loop; the stepping stream waits for it before the new
 member's first chunk. Members whose iterations are long (an exact stage of a
 large graph, EXPENSIVE_ITERATION) are stepped as a second batch with chunks
 of their own length, so that the others are not held to it. The host keeps
-at most two chunks in flight. Latency of a request = completion - arrival, completion
+at most two chunks in flight. Kernels are launched directly (no stream
+capture) in both legs, since the worker thread's GPU work runs concurrently
+with the stepping thread. Latency of a request = completion - arrival, completion
 being the device time of the event recorded after the chunk (or, plain, the
 call) that finished it, measured from an event recorded at the start of the
 run on the idle stream.
@@ -203,6 +205,13 @@ class Server:
         # long iterations (an exact stage of a large graph) do not hold the
         # others to their chunk length
         self.batches = [] if plain else [T.Batch(slots, map_entries=1 << 22) for _ in range(2)]
+        # no stream capture in the server (batches and served handles launch
+        # directly, in both legs): the worker thread's uploads and handle
+        # set-up run concurrently with the stepping thread, and a capture in
+        # progress on the stepping stream must not meet them (a chunk event
+        # was once recorded inside a capture that way)
+        for b in self.batches:
+            b.set_graphs(False)
 
     # ---------------------------------------------------------------- memory
     def _evict_for(self, need: int) -> bool:
@@ -223,6 +232,7 @@ class Server:
         with torch.cuda.stream(self.admit_stream):
             pos = torch.as_tensor(pos_host).to(self.stream.device)
             lay = T.Layout(g.graph.row_ptr, g.graph.col_idx, pos, params, workspace_params=ws)
+            T.tfdp_layout_set_graphs(lay.handle, 0)
             # the tensors are used on the stepping stream from now on
             for t in (lay.row_ptr, lay.col_idx, lay.pos, lay.workspace):
                 t.record_stream(self.stream)

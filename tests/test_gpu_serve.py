@@ -74,7 +74,7 @@ def test_results_same_alone_and_in_the_mix(T):
             g = pool[req.graph][0] if req.kind == "layout" else pool[trace[req.target].graph][0]
             ws = T.TfdpParams(**{**r.params.as_dict(), "n_int": r.ws_n_int, "k_mode": -1})
             lay = T.Layout(g.row_ptr, g.col_idx, r.start_pos.clone(), r.params, workspace_params=ws)
-            final = serve.run_alone(lay, r.iters, 1e-3, r.ws_n_int)
+            final = serve.run_alone(lay, r.iters, 1e-3, r.ws_n_int)  # captured graphs: the same results
             torch.cuda.synchronize()
             same = torch.equal(lay.pos, r.final_pos)
             say(f"request {r.rid} {r.kind} n={r.n} latency {r.latency * 1e3:.1f} ms start grid "
