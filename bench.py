@@ -193,6 +193,17 @@ def batched_section(T, torch, stream, graphs, iters, accuracy=True, sequential=T
     B = T.Batch(len(lays))
     for lay in lays:
         B.add(lay)
+    # tile schedule of the batched grid passes, chosen by the autotuner for
+    # the FFT lengths of each stage (k = 1 at t = 0, then the k = 2 and k = 3
+    # grids at their switches)
+    t_tune = time.perf_counter()
+    tiles, done = {}, set()
+    for t_at in (0, (9 * iters) // 10, (19 * iters) // 20):
+        want = autotune.batch_lengths(lays, t_at) - done
+        if want:
+            tiles.update(autotune.tune_batch_tiles(B, lays, lengths=want, at_iteration=t_at))
+            done |= want
+    tune_s = time.perf_counter() - t_tune
 
     def reset():
         for lay, p0, p in zip(lays, pos0, p1):
@@ -270,6 +281,9 @@ def batched_section(T, torch, stream, graphs, iters, accuracy=True, sequential=T
         "sequential_ms": t_seq * 1e3,
         "speedup_vs_sequential": t_seq / t_batch,
         "bitwise_equal_to_sequential": same if same is None else bool(same),
+        "tiles": {str(L): {"rows_per_block": r, "column_groups": g, "trial_ms": round(ms, 3)}
+                  for L, (r, g, ms) in sorted(tiles.items())},
+        "tile_tuning_s": tune_s,
         "nonfinite_members": int(sum(1 for v in bad if v != 0)),
         "generation_s": gen_s,
     }

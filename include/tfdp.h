@@ -347,6 +347,20 @@ int32_t tfdp_batch_count(const tfdp_batch* b);
  * arena holds. Asynchronous failures are reported per member by
  * tfdp_layout_sync_status. */
 tfdp_status tfdp_batch_step(tfdp_batch* b, int32_t iters, hipStream_t stream);
+/* Tile schedule of the batched grid passes for one FFT length (64, 128, ...,
+ * 2048): rows per block of the row FFT passes (2, 4 or 8) and column groups
+ * per block of the column pass (1 or 2), selectable for lengths up to 512 (a
+ * fixed tile above); 0 selects the default (8 rows up to length 256, 2
+ * groups at 256). Tiles change only how the work is cut into blocks: every
+ * tile gives bit-identical results. The project's autotuner times the
+ * candidates on a batch and keeps the fastest per length. Changing a tile
+ * synchronises `stream` (the batch's maps are rebuilt).
+ * TFDP_ERR_INVALID_ARG for another length, TFDP_ERR_UNSUPPORTED for a tile
+ * that is not available. */
+tfdp_status tfdp_batch_set_tiles(tfdp_batch* b, int32_t fft_length, int32_t rows_per_block, int32_t column_groups,
+                                 hipStream_t stream);
+tfdp_status tfdp_batch_get_tiles(const tfdp_batch* b, int32_t fft_length, int32_t* rows_per_block,
+                                 int32_t* column_groups);
 /* Capture groups of iterations as HIP graphs (default on; the stream must
  * then not be the legacy default stream). */
 tfdp_status tfdp_batch_set_graphs(tfdp_batch* b, int32_t enable);

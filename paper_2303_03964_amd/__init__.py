@@ -18,6 +18,8 @@ from .tfdp import (  # noqa: F401
     tfdp_batch_destroy,
     tfdp_batch_remove,
     tfdp_batch_set_graphs,
+    tfdp_batch_get_tiles,
+    tfdp_batch_set_tiles,
     tfdp_batch_step,
     tfdp_batch_workspace_size,
     tfdp_last_error,

@@ -227,3 +227,70 @@ def calibrate(T, layouts, n_ints=(16, 24, 32, 48, 64, 96), ks=(1, 2, 3)):
         ok = (e > 0) & np.isfinite(e)
         consts[k] = float(np.exp(np.mean(np.log(e[ok]) - k * np.log(h[ok])))) if ok.any() else DEFAULT_C[k]
     return consts, samples
+
+
+TILE_CANDIDATES = [(r, g) for r in (2, 4, 8) for g in (1, 2)]
+TUNABLE_LENGTHS = (64, 128, 256, 384, 512)
+
+
+def k_of(params, t: int) -> int:
+    """k of iteration t (the schedule of Sec. 3.4 for k_mode -1)."""
+    if params.k_mode >= 0:
+        return params.k_mode
+    T = params.total_iters
+    return 1 if t < (9 * T) // 10 else 2 if t < (19 * T) // 20 else 3
+
+
+def batch_lengths(layouts, at_iteration=None):
+    """Tunable FFT lengths the members use at their current counters (or at
+    counter `at_iteration`)."""
+    out = set()
+    for lay in layouts:
+        k = k_of(lay.params, lay.iteration if at_iteration is None else at_iteration)
+        if k > 0 and fft_length(lay.params.n_int, k) in TUNABLE_LENGTHS:
+            out.add(fft_length(lay.params.n_int, k))
+    return out
+
+
+def tune_batch_tiles(batch, layouts, iters: int = 4, repeats: int = 2, lengths=None, at_iteration=None,
+                     stream=None):
+    """Tile schedule of a batch's grid passes, chosen by measurement: for
+    every tunable FFT length the members use (at their current counters, or
+    with every counter set to `at_iteration` during the trials), time `iters`
+    batched iterations with each candidate tile (rows per block of the row
+    passes, column groups of the column pass; the best of `repeats` runs
+    after a first one that builds the maps) and keep the fastest. Tiles do
+    not change results, and every member's positions and counter are restored
+    afterwards. Returns {length: (rows, groups, ms)}."""
+    import time
+    import torch
+    if lengths is None:
+        lengths = batch_lengths(layouts, at_iteration)
+    saved = [(lay.pos.clone(), lay.iteration) for lay in layouts]
+
+    def restore(trial=True):
+        for lay, (p, t) in zip(layouts, saved):
+            lay.pos.copy_(p)
+            lay.iteration = at_iteration if (trial and at_iteration is not None) else t
+        torch.cuda.synchronize()
+
+    chosen = {}
+    for L in sorted(lengths):
+        best = None
+        for rows, groups in TILE_CANDIDATES:
+            batch.set_tiles(L, rows, groups, stream)
+            times = []
+            for rep in range(repeats + 1):
+                restore()
+                t0 = time.perf_counter()
+                batch.step(iters, stream)
+                torch.cuda.synchronize()
+                if rep > 0:  # the first run builds the maps and launches directly
+                    times.append(time.perf_counter() - t0)
+            ms = 1e3 * min(times)
+            if best is None or ms < best[2]:
+                best = (rows, groups, ms)
+        batch.set_tiles(L, best[0], best[1], stream)
+        chosen[L] = best
+    restore(trial=False)
+    return chosen

@@ -33,11 +33,28 @@ enum BPhase { B_BIN_COUNT, B_BIN_SCAN, B_BIN_SCATTER, B_SPREAD, B_ROWFFT, B_COLC
 
 struct BLaunch {
     int phase;
-    int k, len, nw;  // B_BRUTE: nw = offset of the tick map (one entry per member), k = members
+    int k, len, nw;  // B_BRUTE: nw = offset of the tick map (one entry per member), k = members;
+                     // row passes: nw = rows per block; column pass: nw = column groups per block
     size_t off;       // first map entry (relative to the composition's region)
     int blocks;
     size_t lds;
 };
+
+// Index of an FFT length in the batch's tile table.
+int len_index(int L) {
+    switch (L) {
+        case 64: return 0;
+        case 128: return 1;
+        case 256: return 2;
+        case 384: return 3;
+        case 512: return 4;
+        case 768: return 5;
+        case 1024: return 6;
+        case 1536: return 7;
+        default: return 8;
+    }
+}
+constexpr int kLens[9] = {64, 128, 256, 384, 512, 768, 1024, 1536, 2048};
 
 // One composition: the members (slot, handle, grid) with the k of each, the
 // launches of an iteration and the maps of the call-level launches.
@@ -101,6 +118,7 @@ struct tfdp_batch {
     bool graphs;
     std::vector<Comp> comps;
     unsigned long long clock;
+    int2 tiles[9];  // per FFT length: rows per block of the row passes, column groups of the column pass
 };
 
 namespace {
@@ -116,8 +134,6 @@ Member make_member(const tfdp_layout* h, int slot, int k) {
     m.alt = h->lay.pos_alt;
     m.slot = slot;
     spread_dims(m.b, m.g, &m.nw, &m.nkb);
-    rowfft_dims(m.g, &m.nqb, true);
-    rowifft_dims(m.g, &m.nrb, true);
     m.box_blocks = box_reduce_dims(h->n).grid;
     return m;
 }
@@ -209,19 +225,21 @@ void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<in
         for (int i : order) cls[make_geom(H(i)->p.n_int, ks[i]).L].push_back(i);
         for (int phase : {B_ROWFFT, B_COLCONV, B_ROWIFFT})
             for (auto& kv : cls) {
+                const int2 tile = b->tiles[len_index(kv.first)];
+                const int param = phase == B_COLCONV ? tile.y : tile.x;
                 std::vector<int> blocks;
                 for (int i : kv.second) {
                     const Geom g = make_geom(H(i)->p.n_int, ks[i]);
                     int nb = 0;
                     if (phase == B_ROWFFT)
-                        rowfft_dims(g, &nb, true);
+                        rowfft_dims(g, &nb, tile.x);
                     else if (phase == B_COLCONV)
-                        nb = colconv_dims(g, true).grid;
+                        nb = colconv_dims(g, tile.y).grid;
                     else
-                        rowifft_dims(g, &nb, true);
+                        rowifft_dims(g, &nb, tile.x);
                     blocks.push_back(nb);
                 }
-                emit(phase, 0, kv.first, 0, 0, kv.second, blocks);
+                emit(phase, 0, kv.first, param, 0, kv.second, blocks);
             }
     }
     // edge pass + gather + move: classes by k
@@ -321,9 +339,9 @@ void enqueue_iter(tfdp_batch* b, const Comp& c, int j, hipStream_t s) {
             case B_BIN_SCAN: launch_b_bin_scan(mem, map, L.blocks, b->d_t, j, s); break;
             case B_BIN_SCATTER: launch_b_bin_scatter(mem, map, L.blocks, L.lds, j, s); break;
             case B_SPREAD: launch_b_spread(L.k, L.len, L.nw, mem, map, L.blocks, L.lds, s); break;
-            case B_ROWFFT: launch_b_rowfft(L.len, mem, map, L.blocks, s); break;
-            case B_COLCONV: launch_b_colconv(L.len, mem, map, L.blocks, s); break;
-            case B_ROWIFFT: launch_b_rowifft(L.len, mem, map, L.blocks, s); break;
+            case B_ROWFFT: launch_b_rowfft(L.len, L.nw, mem, map, L.blocks, s); break;
+            case B_COLCONV: launch_b_colconv(L.len, L.nw, mem, map, L.blocks, s); break;
+            case B_ROWIFFT: launch_b_rowifft(L.len, L.nw, mem, map, L.blocks, s); break;
             case B_EDGES: launch_b_edges(L.k, mem, map, L.blocks, b->d_t, j, s); break;
             default: launch_b_brute(mem, map, L.blocks, base + L.nw, L.k, j, s); break;
         }
@@ -389,7 +407,52 @@ tfdp_status tfdp_batch_create(tfdp_batch** out, int32_t capacity, void* d_ws, si
     b->arena_used = 0;
     b->graphs = true;
     b->clock = 0;
+    for (int i = 0; i < 9; ++i) b->tiles[i] = make_int2(batch_rows_default(kLens[i]), batch_groups_default(kLens[i]));
     *out = b;
+    return TFDP_OK;
+}
+
+tfdp_status tfdp_batch_set_tiles(tfdp_batch* b, int32_t fft_length, int32_t rows_per_block, int32_t column_groups,
+                                 hipStream_t stream) {
+    if (!b) {
+        set_msg("invalid batch handle");
+        return TFDP_ERR_INVALID_ARG;
+    }
+    const int li = len_index(fft_length);
+    if (kLens[li] != fft_length) {
+        set_msg("fft_length must be one of 64, 128, 256, 384, 512, 768, 1024, 1536, 2048");
+        return TFDP_ERR_INVALID_ARG;
+    }
+    const int rows = rows_per_block > 0 ? rows_per_block : batch_rows_default(fft_length);
+    const int groups = column_groups > 0 ? column_groups : batch_groups_default(fft_length);
+    if (!batch_tile_valid(fft_length, rows, groups)) {
+        set_msg("tile not available for this FFT length (rows 2, 4, 8 and column groups 1, 2 up to length 512; "
+                "the default tile above)");
+        return TFDP_ERR_UNSUPPORTED;
+    }
+    set_msg("");
+    if (b->tiles[li].x == rows && b->tiles[li].y == groups) return TFDP_OK;
+    // the maps of every composition change: drop them once enqueued work is done
+    tfdp_status st = check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (st != TFDP_OK) return st;
+    drop_comps(b);
+    b->tiles[li] = make_int2(rows, groups);
+    return TFDP_OK;
+}
+
+tfdp_status tfdp_batch_get_tiles(const tfdp_batch* b, int32_t fft_length, int32_t* rows_per_block,
+                                 int32_t* column_groups) {
+    if (!b || !rows_per_block || !column_groups) {
+        set_msg("invalid batch handle or pointer");
+        return TFDP_ERR_INVALID_ARG;
+    }
+    const int li = len_index(fft_length);
+    if (kLens[li] != fft_length) {
+        set_msg("fft_length must be one of 64, 128, 256, 384, 512, 768, 1024, 1536, 2048");
+        return TFDP_ERR_INVALID_ARG;
+    }
+    *rows_per_block = b->tiles[li].x;
+    *column_groups = b->tiles[li].y;
     return TFDP_OK;
 }
 

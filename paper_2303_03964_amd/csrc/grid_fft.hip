@@ -571,29 +571,35 @@ __global__ __launch_bounds__(RowTile<L>::THREADS) void k_rowfft(Bufs b, Geom g, 
     rowfft_body<L, RowTile<L>::RB>(b, g, lb);
 }
 
-template <int L>
+// Batched row passes take RB rows per block from the batch's tile schedule
+// (tfdp_batch_set_tiles, chosen by the autotuner): 2, 4 or 8 at L <= 512,
+// RowTile<L>::RBB above. The transforms, their pairing of rows and every
+// sum do not depend on RB, so all tiles give bit-identical results.
+template <int L, int RB>
 __global__ __launch_bounds__(RowTile<L>::THREADS_B) void kb_rowfft(const Member* __restrict__ mem,
                                                                      const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
-    rowfft_body<L, RowTile<L>::RBB>(m.b, m.g, e.y);
+    rowfft_body<L, RB>(m.b, m.g, e.y);
 }
 
-template <int L, bool BATCHED = false>
-static Dims rowfft_dims_t(const Geom& g, int* nqb) {
+// Blocks, threads and LDS of a row pass of RB rows per block (rows = 0: the
+// plain launch's RowTile<L>::RB and block size; rows > 0: a batched launch).
+template <int L>
+static Dims row_pass_dims_t(const Geom& g, int* nb, int rows) {
     constexpr int F = task_ffts<L>();
     constexpr int TL = F * L;
-    constexpr int RB = BATCHED ? RowTile<L>::RBB : RowTile<L>::RB;
-    constexpr int NQT = (3 * RB / 2 + F - 1) / F;
-    *nqb = (g.m + RB - 1) / RB;
-    constexpr int T = BATCHED ? RowTile<L>::THREADS_B : RowTile<L>::THREADS;
-    return Dims{*nqb, T, (size_t)(NQT * TL + L) * sizeof(float2)};
+    const int RB = rows > 0 ? rows : RowTile<L>::RB;
+    const int NT = (3 * RB / 2 + F - 1) / F;
+    *nb = (g.m + RB - 1) / RB;
+    const int T = rows > 0 ? RowTile<L>::THREADS_B : RowTile<L>::THREADS;
+    return Dims{*nb, T, (size_t)(NT * TL + L) * sizeof(float2)};
 }
 
 template <int L>
 static void launch_rowfft_t(const Bufs& b, const Geom& g, hipStream_t s) {
     int nqb;
-    const Dims d = rowfft_dims_t<L>(g, &nqb);
+    const Dims d = row_pass_dims_t<L>(g, &nqb, 0);
     hipLaunchKernelGGL(k_rowfft<L>, dim3(xcd_pair_grid(nqb)), dim3(d.block), d.lds, s, b, g, nqb);
 }
 
@@ -688,16 +694,19 @@ __global__ __launch_bounds__(512) void k_colconv(Bufs b, Geom g) {
     colconv_body<L, col_groups(L, false)>(b, g, blockIdx.x);
 }
 
-template <int L>
+// Batched column passes take G column groups per block from the batch's
+// tile schedule (1 or 2 at L <= 512; col_groups(L, true) above); each column
+// is transformed alike in either, so the results are bit-identical.
+template <int L, int G>
 __global__ __launch_bounds__(512) void kb_colconv(const Member* __restrict__ mem, const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
-    colconv_body<L, col_groups(L, true)>(m.b, m.g, e.y);
+    colconv_body<L, G>(m.b, m.g, e.y);
 }
 
-Dims colconv_dims(const Geom& g, bool batched) {
+Dims colconv_dims(const Geom& g, int groups) {
     const int F = fft_task_ffts(g.L);
-    const int G = col_groups(g.L, batched);
+    const int G = groups > 0 ? groups : col_groups(g.L, false);
     return Dims{(g.H + G * F - 1) / (G * F), 512, ((size_t)4 * G * F * g.L + g.L) * sizeof(float2)};
 }
 
@@ -775,29 +784,18 @@ __global__ __launch_bounds__(RowTile<L>::THREADS) void k_rowifft(Bufs b, Geom g,
     rowifft_body<L, RowTile<L>::RB>(b, g, lb);
 }
 
-template <int L>
+template <int L, int RB>
 __global__ __launch_bounds__(RowTile<L>::THREADS_B) void kb_rowifft(const Member* __restrict__ mem,
                                                                       const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
-    rowifft_body<L, RowTile<L>::RBB>(m.b, m.g, e.y);
-}
-
-template <int L, bool BATCHED = false>
-static Dims rowifft_dims_t(const Geom& g, int* nrb) {
-    constexpr int F = task_ffts<L>();
-    constexpr int TL = F * L;
-    constexpr int RB = BATCHED ? RowTile<L>::RBB : RowTile<L>::RB;
-    constexpr int NT = (3 * RB / 2 + F - 1) / F;
-    *nrb = (g.m + RB - 1) / RB;
-    constexpr int T = BATCHED ? RowTile<L>::THREADS_B : RowTile<L>::THREADS;
-    return Dims{*nrb, T, (size_t)(NT * TL + L) * sizeof(float2)};
+    rowifft_body<L, RB>(m.b, m.g, e.y);
 }
 
 template <int L>
 static void launch_rowifft_t(const Bufs& b, const Geom& g, hipStream_t s) {
     int nrb;
-    const Dims d = rowifft_dims_t<L>(g, &nrb);
+    const Dims d = row_pass_dims_t<L>(g, &nrb, 0);
     hipLaunchKernelGGL(k_rowifft<L>, dim3(xcd_pair_grid(nrb)), dim3(d.block), d.lds, s, b, g, nrb);
 }
 
@@ -807,47 +805,94 @@ void launch_rowifft(const Bufs& b, const Geom& g, hipStream_t s) {
 #undef TFDP_C
 }
 
-Dims rowfft_dims(const Geom& g, int* nqb, bool batched) {
+Dims rowfft_dims(const Geom& g, int* nqb, int rows) {
     Dims d{};
-#define TFDP_D(LG) d = batched ? rowfft_dims_t<LG, true>(g, nqb) : rowfft_dims_t<LG, false>(g, nqb)
+#define TFDP_D(LG) d = row_pass_dims_t<LG>(g, nqb, rows)
     TFDP_L_SWITCH(g.L, TFDP_D)
 #undef TFDP_D
     return d;
 }
 
-Dims rowifft_dims(const Geom& g, int* nrb, bool batched) {
-    Dims d{};
-#define TFDP_D(LG) d = batched ? rowifft_dims_t<LG, true>(g, nrb) : rowifft_dims_t<LG, false>(g, nrb)
-    TFDP_L_SWITCH(g.L, TFDP_D)
-#undef TFDP_D
-    return d;
+Dims rowifft_dims(const Geom& g, int* nrb, int rows) { return rowfft_dims(g, nrb, rows); }
+
+int batch_rows_default(int L) {
+    int r = 0;
+#define TFDP_R(LG) r = RowTile<LG>::RBB
+    TFDP_L_SWITCH(L, TFDP_R)
+#undef TFDP_R
+    return r;
 }
 
-void launch_b_rowfft(int len, const Member* mem, const int2* map, int blocks, hipStream_t s) {
-    if (blocks <= 0) return;
-    const Geom g{1, 1, len, len / 2 + 1, 1};
+int batch_groups_default(int L) { return col_groups(L, true); }
+
+bool batch_tile_valid(int L, int rows, int groups) {
+    if (L > 512) return rows == batch_rows_default(L) && groups == batch_groups_default(L);
+    return (rows == 2 || rows == 4 || rows == 8) && (groups == 1 || groups == 2);
+}
+
+// Launch of a batched row pass (kernel template K) with `rows` rows per block.
+#define TFDP_ROWPASS_LAUNCH(KERN, LG, rows, d, blocks, s, mem, map)                                             \
+    do {                                                                                                        \
+        if constexpr (LG <= 512) {                                                                              \
+            if ((rows) == 2)                                                                                    \
+                hipLaunchKernelGGL((KERN<LG, 2>), dim3(blocks), dim3((d).block), (d).lds, s, mem, map);        \
+            else if ((rows) == 4)                                                                               \
+                hipLaunchKernelGGL((KERN<LG, 4>), dim3(blocks), dim3((d).block), (d).lds, s, mem, map);        \
+            else                                                                                                \
+                hipLaunchKernelGGL((KERN<LG, 8>), dim3(blocks), dim3((d).block), (d).lds, s, mem, map);        \
+        } else {                                                                                                \
+            hipLaunchKernelGGL((KERN<LG, RowTile<LG>::RBB>), dim3(blocks), dim3((d).block), (d).lds, s, mem,    \
+                               map);                                                                            \
+        }                                                                                                       \
+    } while (0)
+
+template <int L>
+static void launch_b_rowfft_t(int rows, const Member* mem, const int2* map, int blocks, hipStream_t s) {
+    const Geom g{1, 1, L, L / 2 + 1, 1};
     int nqb;
-    const Dims d = rowfft_dims(g, &nqb, true);
-#define TFDP_L(LG) hipLaunchKernelGGL(kb_rowfft<LG>, dim3(blocks), dim3(d.block), d.lds, s, mem, map)
-    TFDP_L_SWITCH(len, TFDP_L)
-#undef TFDP_L
+    const Dims d = row_pass_dims_t<L>(g, &nqb, rows);
+    TFDP_ROWPASS_LAUNCH(kb_rowfft, L, rows, d, blocks, s, mem, map);
 }
 
-void launch_b_colconv(int len, const Member* mem, const int2* map, int blocks, hipStream_t s) {
-    if (blocks <= 0) return;
-    const Geom g{1, 1, len, len / 2 + 1, 1};
-    const Dims d = colconv_dims(g, true);
-#define TFDP_L(LG) hipLaunchKernelGGL(kb_colconv<LG>, dim3(blocks), dim3(d.block), d.lds, s, mem, map)
-    TFDP_L_SWITCH(len, TFDP_L)
-#undef TFDP_L
-}
-
-void launch_b_rowifft(int len, const Member* mem, const int2* map, int blocks, hipStream_t s) {
-    if (blocks <= 0) return;
-    const Geom g{1, 1, len, len / 2 + 1, 1};
+template <int L>
+static void launch_b_rowifft_t(int rows, const Member* mem, const int2* map, int blocks, hipStream_t s) {
+    const Geom g{1, 1, L, L / 2 + 1, 1};
     int nrb;
-    const Dims d = rowifft_dims(g, &nrb, true);
-#define TFDP_L(LG) hipLaunchKernelGGL(kb_rowifft<LG>, dim3(blocks), dim3(d.block), d.lds, s, mem, map)
+    const Dims d = row_pass_dims_t<L>(g, &nrb, rows);
+    TFDP_ROWPASS_LAUNCH(kb_rowifft, L, rows, d, blocks, s, mem, map);
+}
+
+template <int L>
+static void launch_b_colconv_t(int groups, const Member* mem, const int2* map, int blocks, hipStream_t s) {
+    const Geom g{1, 1, L, L / 2 + 1, 1};
+    const Dims d = colconv_dims(g, groups);
+    if constexpr (L <= 512) {
+        if (groups == 2)
+            hipLaunchKernelGGL((kb_colconv<L, 2>), dim3(blocks), dim3(d.block), d.lds, s, mem, map);
+        else
+            hipLaunchKernelGGL((kb_colconv<L, 1>), dim3(blocks), dim3(d.block), d.lds, s, mem, map);
+    } else {
+        hipLaunchKernelGGL((kb_colconv<L, col_groups(L, true)>), dim3(blocks), dim3(d.block), d.lds, s, mem, map);
+    }
+}
+
+void launch_b_rowfft(int len, int rows, const Member* mem, const int2* map, int blocks, hipStream_t s) {
+    if (blocks <= 0) return;
+#define TFDP_L(LG) launch_b_rowfft_t<LG>(rows, mem, map, blocks, s)
+    TFDP_L_SWITCH(len, TFDP_L)
+#undef TFDP_L
+}
+
+void launch_b_colconv(int len, int groups, const Member* mem, const int2* map, int blocks, hipStream_t s) {
+    if (blocks <= 0) return;
+#define TFDP_L(LG) launch_b_colconv_t<LG>(groups, mem, map, blocks, s)
+    TFDP_L_SWITCH(len, TFDP_L)
+#undef TFDP_L
+}
+
+void launch_b_rowifft(int len, int rows, const Member* mem, const int2* map, int blocks, hipStream_t s) {
+    if (blocks <= 0) return;
+#define TFDP_L(LG) launch_b_rowifft_t<LG>(rows, mem, map, blocks, s)
     TFDP_L_SWITCH(len, TFDP_L)
 #undef TFDP_L
 }
@@ -866,9 +911,20 @@ static void allow_big_lds_all_l() {
     allow_big_lds(kb_spread<1, L>);
     allow_big_lds(kb_spread<2, L>);
     allow_big_lds(kb_spread<3, L>);
-    allow_big_lds(kb_rowfft<L>);
-    allow_big_lds(kb_colconv<L>);
-    allow_big_lds(kb_rowifft<L>);
+    if constexpr (L <= 512) {
+        allow_big_lds(kb_rowfft<L, 2>);
+        allow_big_lds(kb_rowfft<L, 4>);
+        allow_big_lds(kb_rowfft<L, 8>);
+        allow_big_lds(kb_rowifft<L, 2>);
+        allow_big_lds(kb_rowifft<L, 4>);
+        allow_big_lds(kb_rowifft<L, 8>);
+        allow_big_lds(kb_colconv<L, 1>);
+        allow_big_lds(kb_colconv<L, 2>);
+    } else {
+        allow_big_lds(kb_rowfft<L, RowTile<L>::RBB>);
+        allow_big_lds(kb_rowifft<L, RowTile<L>::RBB>);
+        allow_big_lds(kb_colconv<L, col_groups(L, true)>);
+    }
 }
 
 void init_kernel_attributes() {

@@ -107,7 +107,7 @@ struct Member {
     float2* alt;        // second buffer (current at odd iterations)
     int slot;           // index of the graph's iteration counter at the start of the call
     int nw;             // waves per block of the spreading pass
-    int nkb, nqb, nrb;  // logical blocks of the kernel-row, row-FFT and inverse-row passes
+    int nkb;            // logical kernel-row blocks of the spreading pass
     int box_blocks;     // blocks of the box reduction
 };
 
@@ -189,10 +189,16 @@ Dims bin_scan_dims(const Bufs& b);
 Dims bin_scatter_dims(const Bufs& b);
 // spreading: grid = chunk blocks + logical kernel-row blocks (nkb); nw waves
 Dims spread_dims(const Bufs& b, const Geom& g, int* nw, int* nkb);
-// batched: the row tiles of the batched kernels (more rows per block)
-Dims rowfft_dims(const Geom& g, int* nqb, bool batched = false);
-Dims colconv_dims(const Geom& g, bool batched = false);
-Dims rowifft_dims(const Geom& g, int* nrb, bool batched = false);
+// rows / groups: 0 for the plain launches, else the batched launch's rows
+// per block (row passes) or column groups per block (column pass)
+Dims rowfft_dims(const Geom& g, int* nqb, int rows = 0);
+Dims colconv_dims(const Geom& g, int groups = 0);
+Dims rowifft_dims(const Geom& g, int* nrb, int rows = 0);
+// Tile schedule of the batched grid passes per FFT length: the defaults, and
+// whether (rows, groups) is one of the instantiated tiles for length L.
+int batch_rows_default(int L);
+int batch_groups_default(int L);
+bool batch_tile_valid(int L, int rows, int groups);
 
 // ---- batched launchers: one launch for every map entry {member, block} ----
 // tcall: per-slot iteration counters at the start of the call; j: iteration
@@ -206,9 +212,9 @@ void launch_b_bin_scan(const Member* mem, const int2* map, int blocks, const int
 void launch_b_bin_scatter(const Member* mem, const int2* map, int blocks, size_t lds, int j, hipStream_t s);
 void launch_b_spread(int k, int len, int nw, const Member* mem, const int2* map, int blocks, size_t lds,
                      hipStream_t s);
-void launch_b_rowfft(int len, const Member* mem, const int2* map, int blocks, hipStream_t s);
-void launch_b_colconv(int len, const Member* mem, const int2* map, int blocks, hipStream_t s);
-void launch_b_rowifft(int len, const Member* mem, const int2* map, int blocks, hipStream_t s);
+void launch_b_rowfft(int len, int rows, const Member* mem, const int2* map, int blocks, hipStream_t s);
+void launch_b_colconv(int len, int groups, const Member* mem, const int2* map, int blocks, hipStream_t s);
+void launch_b_rowifft(int len, int rows, const Member* mem, const int2* map, int blocks, hipStream_t s);
 void launch_b_edges(int k, const Member* mem, const int2* map, int blocks, const int* tcall, int j,
                     hipStream_t s);
 void launch_b_copy(const Member* mem, const int2* map, int blocks, hipStream_t s);

@@ -90,6 +90,8 @@ _SIGS = {
     "tfdp_batch_count": (c_int32, [c_void_p]),
     "tfdp_batch_step": (c_int32, [c_void_p, c_int32, c_void_p]),
     "tfdp_batch_set_graphs": (c_int32, [c_void_p, c_int32]),
+    "tfdp_batch_set_tiles": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p]),
+    "tfdp_batch_get_tiles": (c_int32, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32)]),
     "tfdp_batch_destroy": (None, [c_void_p]),
 }
 
@@ -328,6 +330,17 @@ def tfdp_batch_set_graphs(b, enable):
     return _check(load_library().tfdp_batch_set_graphs(b, int(bool(enable))))
 
 
+def tfdp_batch_set_tiles(b, fft_length, rows_per_block, column_groups, stream=None):
+    return _check(load_library().tfdp_batch_set_tiles(b, fft_length, rows_per_block, column_groups,
+                                                      _stream(stream)))
+
+
+def tfdp_batch_get_tiles(b, fft_length):
+    r, g = c_int32(), c_int32()
+    _check(load_library().tfdp_batch_get_tiles(b, fft_length, ctypes.byref(r), ctypes.byref(g)))
+    return r.value, g.value
+
+
 def tfdp_batch_destroy(b):
     load_library().tfdp_batch_destroy(b)
 
@@ -456,6 +469,12 @@ class Batch:
 
     def set_graphs(self, enable):
         tfdp_batch_set_graphs(self.handle, enable)
+
+    def set_tiles(self, fft_length, rows_per_block, column_groups, stream=None):
+        tfdp_batch_set_tiles(self.handle, fft_length, rows_per_block, column_groups, stream)
+
+    def tiles(self, fft_length):
+        return tfdp_batch_get_tiles(self.handle, fft_length)
 
     def close(self):
         if getattr(self, "handle", None) is not None:

@@ -169,6 +169,15 @@ def test_batch_host_bookkeeping():
     assert lib.tfdp_batch_step(b, -1, None) == INVALID
     assert lib.tfdp_batch_step(None, 1, None) == INVALID
     assert lib.tfdp_batch_set_graphs(b, 0) == OK and lib.tfdp_batch_set_graphs(None, 1) == INVALID
+    # tile schedule: defaults, validation (no device work when nothing changes)
+    assert T.tfdp_batch_get_tiles(b, 256) == (8, 2) and T.tfdp_batch_get_tiles(b, 512) == (2, 1)
+    assert T.tfdp_batch_get_tiles(b, 768) == (4, 1)
+    assert lib.tfdp_batch_set_tiles(b, 256, 8, 2, None) == OK and lib.tfdp_batch_set_tiles(b, 256, 0, 0, None) == OK
+    assert lib.tfdp_batch_set_tiles(None, 256, 8, 2, None) == INVALID
+    assert lib.tfdp_batch_set_tiles(b, 300, 8, 2, None) == INVALID
+    assert lib.tfdp_batch_set_tiles(b, 256, 3, 1, None) == UNSUPPORTED
+    assert lib.tfdp_batch_set_tiles(b, 256, 4, 3, None) == UNSUPPORTED
+    assert lib.tfdp_batch_set_tiles(b, 1024, 8, 1, None) == UNSUPPORTED
     lib.tfdp_batch_destroy(b)
     lib.tfdp_batch_destroy(None)
 

@@ -352,3 +352,51 @@ def test_single_member_batch_equals_plain(T, stream):
             assert a.iteration == b.iteration
             assert torch.equal(a.pos, b.pos)
         B.close()
+
+
+@pytest.mark.parametrize("rows,groups", [(2, 1), (4, 2), (8, 1)])
+def test_batch_tiles_bitwise(T, stream, rows, groups):
+    """Every tile of the batched grid passes gives the plain results bit for
+    bit (members at FFT lengths 128, 256, 384 and 512 across the k switches)."""
+    import torch
+    members = [(0, 32, {}), (1, 64, {}), (3, 96, {}), (7, 40, {}), (5, 48, {"k_mode": 2})]
+    with torch.cuda.stream(stream):
+        gs = graphs([m[0] for m in members])
+        lays = [pair(T, g, pos, n_int, 40, extra) for (idx, n_int, extra), (g, pos) in zip(members, gs)]
+        B = T.Batch(len(lays))
+        for L in (64, 128, 256, 384, 512):
+            B.set_tiles(L, rows, groups)
+            assert B.tiles(L) == (rows, groups)
+        for a, _ in lays:
+            B.add(a)
+        for c in (9, 20, 11):
+            B.step(c)
+            for _, b in lays:
+                b.step(c)
+        torch.cuda.synchronize()
+        for a, b in lays:
+            assert a.iteration == b.iteration == 40
+            assert torch.equal(a.pos, b.pos)
+        B.close()
+
+
+def test_tile_autotuner_restores_state(T, stream):
+    import torch
+    from paper_2303_03964_amd import autotune
+    with torch.cuda.stream(stream):
+        gs = graphs([0, 1, 3, 4])
+        lays = [pair(T, g, pos, autotune.n_int_for_size(g.n), 60, {})[0] for g, pos in gs]
+        B = T.Batch(len(lays))
+        for lay in lays:
+            B.add(lay)
+        B.step(3)
+        torch.cuda.synchronize()
+        before = [(lay.pos.clone(), lay.iteration) for lay in lays]
+        chosen = autotune.tune_batch_tiles(B, lays, iters=2, repeats=1)
+        say(f"tiles chosen: {chosen}")
+        assert chosen and all(L in autotune.TUNABLE_LENGTHS for L in chosen)
+        for L, (r, g, ms) in chosen.items():
+            assert B.tiles(L) == (r, g) and ms > 0
+        for lay, (p, t) in zip(lays, before):
+            assert lay.iteration == t and torch.equal(lay.pos, p)
+        B.close()
