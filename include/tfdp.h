@@ -79,7 +79,10 @@ typedef struct tfdp_params {
                             max(50, ceil(W)) for the box side W of the current layout, the rule the
                             paper cites for t-SNE (Sec. 3.4, "Choices of k"), capped at 1024 / k_max;
                             the workspace is then sized for the cap */
-    int32_t k_mode;      /* 0: exact O(n^2) repulsion; 1, 2, 3: fixed k; -1: k schedule */
+    int32_t k_mode;      /* 0: exact O(n^2) repulsion; 1, 2, 3: fixed k; -1: k schedule.
+                            The exact method takes each unordered pair once from 4096
+                            nodes on (sums in 64-bit fixed point, order-independent);
+                            below, one kernel sums every row over all nodes. */
     int32_t total_iters; /* T of the k schedule and the cooling, >= 1 */
     float t0;            /* initial step cap; <= 0 selects max(1, sqrt(n)/10) */
     float tau;           /* length scale of both t-forces, > 0, default 1: (1 + tau d^2) in
@@ -342,7 +345,10 @@ tfdp_status tfdp_batch_remove(tfdp_batch* b, tfdp_layout* h);
 int32_t tfdp_batch_count(const tfdp_batch* b);
 /* Advance every member by `iters` iterations (asynchronous, on `stream`),
  * each from its own counter t with its own k schedule and parameters
- * (k_mode 0 members run the exact method by their plain kernel).
+ * (k_mode 0 members run the exact method by the kernels of their plain
+ * steps: the one-launch kernel below 4096 nodes, else the pair-symmetric
+ * passes, whose map needs one entry per tile pair of 256 nodes, about
+ * (n / 256)^2 / 2, beyond the bound given above).
  * TFDP_ERR_WORKSPACE if one composition needs more map entries than the
  * arena holds. Asynchronous failures are reported per member by
  * tfdp_layout_sync_status. */

@@ -56,7 +56,9 @@ def build_library(verbose: bool = True) -> str:
             if res.returncode != 0:
                 raise subprocess.CalledProcessError(res.returncode, res.args, res.stdout, res.stderr)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    # every symbol resolved at link time: a missing definition fails the build,
+    # not the first call
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

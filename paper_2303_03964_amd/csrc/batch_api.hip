@@ -29,12 +29,15 @@ using namespace tfdp;
 
 namespace {
 
-enum BPhase { B_BIN_COUNT, B_BIN_SCAN, B_BIN_SCATTER, B_SPREAD, B_ROWFFT, B_COLCONV, B_ROWIFFT, B_EDGES, B_BRUTE };
+enum BPhase {
+    B_BIN_COUNT, B_BIN_SCAN, B_BIN_SCATTER, B_SPREAD, B_ROWFFT, B_COLCONV, B_ROWIFFT, B_EDGES,
+    B_BRUTE, B_SYM_PAIRS, B_SYM_NODE, B_TICK
+};
 
 struct BLaunch {
     int phase;
-    int k, len, nw;  // B_BRUTE: nw = offset of the tick map (one entry per member), k = members;
-                     // row passes: nw = rows per block; column pass: nw = column groups per block
+    int k, len, nw;  // row passes: nw = rows per block; column pass: nw = column groups per block
+                     // (B_TICK: blocks = members, one map entry each)
     size_t off;       // first map entry (relative to the composition's region)
     int blocks;
     size_t lds;
@@ -252,13 +255,27 @@ void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<in
             emit(B_EDGES, kv.first, 0, 0, 0, kv.second, blocks);
         }
     }
-    // exact method: one launch for all such members, then their counters
+    // exact method: the one-launch kernel for the small members, the
+    // pair-symmetric passes for the others, then every such member's counter
     if (!brute.empty()) {
-        std::vector<int> blocks;
-        for (int i : brute) blocks.push_back((H(i)->n + kBruteRows - 1) / kBruteRows);
-        const size_t tick = map.size();
+        std::vector<int> small, big, bs, bp, bn;
+        for (int i : brute) {
+            if (use_sym(H(i)->n)) {
+                big.push_back(i);
+                bp.push_back((int)sym_pair_blocks(H(i)->n));
+                bn.push_back(sym_node_blocks(H(i)->n));
+            } else {
+                small.push_back(i);
+                bs.push_back((H(i)->n + kBruteRows - 1) / kBruteRows);
+            }
+        }
+        emit(B_BRUTE, 0, 0, 0, 0, small, bs);
+        emit(B_SYM_PAIRS, 0, 0, 0, 0, big, bp);
+        emit(B_SYM_NODE, 0, 0, 0, 0, big, bn);
+        BLaunch L{B_TICK, 0, 0, 0, map.size(), 0, 0};
         for (int i : brute) map.push_back(make_int2(entry_of(act[i], 1), 0));
-        emit(B_BRUTE, (int)brute.size(), 0, (int)tick, 0, brute, blocks);
+        L.blocks = (int)brute.size();
+        c.launches.push_back(L);
     }
     // call-level maps: a box-begin block per member, box-reduce blocks, copy blocks
     c.box_begin = (int)map.size();
@@ -343,7 +360,10 @@ void enqueue_iter(tfdp_batch* b, const Comp& c, int j, hipStream_t s) {
             case B_COLCONV: launch_b_colconv(L.len, L.nw, mem, map, L.blocks, s); break;
             case B_ROWIFFT: launch_b_rowifft(L.len, L.nw, mem, map, L.blocks, s); break;
             case B_EDGES: launch_b_edges(L.k, mem, map, L.blocks, b->d_t, j, s); break;
-            default: launch_b_brute(mem, map, L.blocks, base + L.nw, L.k, j, s); break;
+            case B_BRUTE: launch_b_brute(mem, map, L.blocks, j, s); break;
+            case B_SYM_PAIRS: launch_b_sym_pairs(mem, map, L.blocks, j, s); break;
+            case B_SYM_NODE: launch_b_sym_node(mem, map, L.blocks, j, s); break;
+            default: launch_b_tick(mem, map, L.blocks, s); break;
         }
     }
 }

@@ -554,11 +554,12 @@ __global__ void kb_tick(const Member* __restrict__ mem, const int2* __restrict__
     if (i < count) mem[map[i].x].b.st->t += 1;
 }
 
-void launch_b_brute(const Member* mem, const int2* map, int blocks, const int2* tick_map, int members, int j,
-                    hipStream_t s) {
-    if (blocks <= 0) return;
-    hipLaunchKernelGGL(kb_brute, dim3(blocks), dim3(kThreads), 0, s, mem, map, j);
-    hipLaunchKernelGGL(kb_tick, dim3((members + 255) / 256), dim3(256), 0, s, mem, tick_map, members);
+void launch_b_brute(const Member* mem, const int2* map, int blocks, int j, hipStream_t s) {
+    if (blocks > 0) hipLaunchKernelGGL(kb_brute, dim3(blocks), dim3(kThreads), 0, s, mem, map, j);
+}
+
+void launch_b_tick(const Member* mem, const int2* tick_map, int members, hipStream_t s) {
+    if (members > 0) hipLaunchKernelGGL(kb_tick, dim3((members + 255) / 256), dim3(256), 0, s, mem, tick_map, members);
 }
 
 void launch_brute(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx, int n,
@@ -567,6 +568,234 @@ void launch_brute(const float2* pos, float2* pos_out, const int* row_ptr, const 
     const int blocks = (n + kBruteRows - 1) / kBruteRows;
     hipLaunchKernelGGL(k_brute, dim3(blocks), dim3(kThreads), 0, s, pos, n, pos_out, row_ptr, col_idx,
                        st, a, t, f_rep, f_att, f_tot);
+}
+
+// ----------------------------------------------------------------- exact method, pair-symmetric form
+//
+// For larger graphs the exact repulsion takes every unordered pair once
+// (Newton's third law: the term of (j, i) is minus that of (i, j)). Blocks
+// take tile pairs (I, J), I <= J, of kSymTile nodes. In an off-diagonal block
+// lane l of wave w holds row i = I kSymTile + 64 w + l and, at step s, meets
+// column q 64 + ((l + s) mod 64) of each quarter q of tile J; the column's
+// running sum of minus the row terms travels with it, one lane down per
+// step, so that after 64 steps lane l holds the sums of columns q 64 + l.
+// A diagonal block sums both orders of its pairs into the rows only. Each
+// block adds its row and column sums to per-node 64-bit fixed-point
+// accumulators with integer atomics, which are exact, so the totals do not
+// depend on the order of the blocks; the node pass reads and clears them.
+
+// Scale of the fixed-point sums: a pair term is below tmax = max over d of
+// d (1 + tau d^2)^-gamma in magnitude (reached at d^2 = 1 / (tau (2 gamma -
+// 1))), so n terms stay below 2^61 with the scale 2^(61 - e), n tmax < 2^e.
+__device__ __forceinline__ double sym_scale(int n, float gamma, float tau) {
+    const double g = gamma, tt = tau;
+    const double d2 = 1.0 / (tt * (2.0 * g - 1.0));
+    const double tmax = sqrt(d2) * pow(1.0 + tt * d2, -g);
+    int e;
+    (void)frexp((double)n * tmax, &e);
+    return ldexp(1.0, 61 - e);
+}
+
+// Tile pair p (0 <= p < nt (nt + 1) / 2) in row order: row I starts at
+// I nt - I (I - 1) / 2.
+__device__ __forceinline__ void sym_tile_pair(int p, int nt, int& I, int& J) {
+    const double b = (double)nt + 0.5;
+    int r = (int)(b - sqrt(b * b - 2.0 * (double)p));
+    if (r < 0) r = 0;
+    if (r > nt - 1) r = nt - 1;
+    auto start = [nt](int x) { return (long long)x * nt - (long long)x * (x - 1) / 2; };
+    while (r > 0 && start(r) > p) --r;
+    while (r < nt - 1 && start(r + 1) <= p) ++r;
+    I = r;
+    J = r + (int)(p - start(r));
+}
+
+// Repulsion term factor K(d) = (1 + tau d^2)^-gamma of one pair.
+template <bool G2>
+__device__ __forceinline__ float sym_kernel(float dx, float dy, float tau, float gamma) {
+    const float u = 1.f + tau * (dx * dx + dy * dy);
+    if constexpr (G2) {
+        const float r = __builtin_amdgcn_rcpf(u);
+        return r * r;
+    } else {
+        return powf(u, -gamma);
+    }
+}
+
+// Lane l receives the value of lane (l + 1) mod 64 (DPP wavefront rotate).
+__device__ __forceinline__ float lane_next(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ void sym_add(unsigned long long* acc, int node, float fx, float fy, double scale) {
+    atomicAdd(acc + 2 * (size_t)node, (unsigned long long)__double2ll_rn((double)fx * scale));
+    atomicAdd(acc + 2 * (size_t)node + 1, (unsigned long long)__double2ll_rn((double)fy * scale));
+}
+
+template <bool G2>
+__device__ __forceinline__ void sym_pairs_t(const float2* __restrict__ pos, int n, unsigned long long* __restrict__ acc,
+                                            float gamma, float tau, int p) {
+    __shared__ float2 cols[kSymTile];
+    __shared__ float2 gpart[kSymTile / 64][kSymTile];
+    const int nt = (n + kSymTile - 1) / kSymTile;
+    int I, J;
+    sym_tile_pair(p, nt, I, J);
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int i = I * kSymTile + threadIdx.x;
+    const int jt = J * kSymTile + threadIdx.x;
+    cols[threadIdx.x] = jt < n ? pos[jt] : make_float2(0.f, 0.f);
+    const float2 pi = i < n ? pos[i] : make_float2(0.f, 0.f);
+    const double scale = sym_scale(n, gamma, tau);
+    const int cnt = min(kSymTile, n - J * kSymTile);  // columns of tile J inside the graph
+    __syncthreads();
+    float fx[4] = {0.f, 0.f, 0.f, 0.f}, fy[4] = {0.f, 0.f, 0.f, 0.f};
+    if (I == J) {
+        // both orders of every pair of the tile, into the rows (the term of
+        // a node with itself is zero)
+        for (int c0 = 0; c0 < cnt; c0 += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u;
+                if (c < cnt) {
+                    const float2 q = cols[c];
+                    const float dx = pi.x - q.x, dy = pi.y - q.y;
+                    const float kk = sym_kernel<G2>(dx, dy, tau, gamma);
+                    fx[u] += kk * dx;
+                    fy[u] += kk * dy;
+                }
+            }
+        }
+    } else {
+        float gx[4] = {0.f, 0.f, 0.f, 0.f}, gy[4] = {0.f, 0.f, 0.f, 0.f};
+        const bool full = cnt == kSymTile;
+        for (int s = 0; s < 64; ++s) {
+            const int cl = (lane + s) & 63;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = q * 64 + cl;
+                const float2 v = cols[c];
+                const float dx = pi.x - v.x, dy = pi.y - v.y;
+                float kk = sym_kernel<G2>(dx, dy, tau, gamma);
+                if (!full && c >= cnt) kk = 0.f;
+                fx[q] += kk * dx;
+                fy[q] += kk * dy;
+                gx[q] -= kk * dx;
+                gy[q] -= kk * dy;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                gx[q] = lane_next(gx[q]);
+                gy[q] = lane_next(gy[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gpart[w][q * 64 + lane] = make_float2(gx[q], gy[q]);
+    }
+    if (i < n) sym_add(acc, i, (fx[0] + fx[1]) + (fx[2] + fx[3]), (fy[0] + fy[1]) + (fy[2] + fy[3]), scale);
+    if (I != J) {
+        __syncthreads();
+        const float2 a0 = gpart[0][threadIdx.x], a1 = gpart[1][threadIdx.x];
+        const float2 a2 = gpart[2][threadIdx.x], a3 = gpart[3][threadIdx.x];
+        if (jt < n) sym_add(acc, jt, (a0.x + a1.x) + (a2.x + a3.x), (a0.y + a1.y) + (a2.y + a3.y), scale);
+    }
+}
+
+__device__ __forceinline__ void sym_pairs_body(const float2* __restrict__ pos, int n,
+                                               unsigned long long* __restrict__ acc, const ModelArgs& a, int p) {
+    if (a.gamma == 2.0f)
+        sym_pairs_t<true>(pos, n, acc, a.gamma, a.tau, p);
+    else
+        sym_pairs_t<false>(pos, n, acc, a.gamma, a.tau, p);
+}
+
+// Node pass of the pair-symmetric exact method: repulsion from the
+// accumulators (cleared for the next pass), attraction along the row,
+// displacement and move (or the force outputs); one node per thread.
+__device__ __forceinline__ void sym_node_body(const float2* __restrict__ pos, int n, float2* __restrict__ pos_out,
+                                              const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
+                                              unsigned long long* __restrict__ acc, DevState* st,
+                                              const ModelArgs& a, int t, float2* f_rep, float2* f_att,
+                                              float2* f_tot, int bid) {
+    const int i = bid * kThreads + threadIdx.x;
+    if (i < n) {
+        float xmin = INFINITY, ymin = INFINITY, xmax = -INFINITY, ymax = -INFINITY;
+        const double inv = 1.0 / sym_scale(n, a.gamma, a.tau);
+        const unsigned long long ux = acc[2 * (size_t)i], uy = acc[2 * (size_t)i + 1];
+        acc[2 * (size_t)i] = 0ull;
+        acc[2 * (size_t)i + 1] = 0ull;
+        const float frx = (float)((double)(long long)ux * inv);
+        const float fry = (float)((double)(long long)uy * inv);
+        const float2 p = pos[i];
+        float sax = 0.f, say = 0.f;
+        const int e1 = row_ptr[i + 1];
+        const float* __restrict__ aw = a.att_w;
+        for (int e = row_ptr[i]; e < e1; ++e) {
+            const int j = col_idx[e] & 0x3ffffff;
+            float ax, ay;
+            edge_term(p.x, p.y, pos[j], a.beta, a.tau, ax, ay);
+            const float wgt = aw ? 0.5f * (aw[i] + aw[j]) : 1.f;
+            sax += wgt * ax;
+            say += wgt * ay;
+        }
+        node_output(i, p, frx, fry, sax, say, a, t, st, pos_out, f_rep, f_att, f_tot, xmin, ymin, xmax, ymax);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sym_pairs(const float2* __restrict__ pos, int n,
+                                                        unsigned long long* __restrict__ acc, ModelArgs a) {
+    sym_pairs_body(pos, n, acc, a, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_sym_node(const float2* __restrict__ pos, int n,
+                                                       float2* __restrict__ pos_out, const int* __restrict__ row_ptr,
+                                                       const int* __restrict__ col_idx,
+                                                       unsigned long long* __restrict__ acc, DevState* st, ModelArgs a,
+                                                       int t, float2* f_rep, float2* f_att, float2* f_tot) {
+    sym_node_body(pos, n, pos_out, row_ptr, col_idx, acc, st, a, t, f_rep, f_att, f_tot, blockIdx.x);
+}
+
+long long sym_pair_blocks(int n) {
+    const long long nt = (n + kSymTile - 1) / kSymTile;
+    return nt * (nt + 1) / 2;
+}
+
+int sym_node_blocks(int n) { return (n + kThreads - 1) / kThreads; }
+
+void launch_sym(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx, int n,
+                unsigned long long* acc, DevState* st, const ModelArgs& a, int t, float2* f_rep, float2* f_att,
+                float2* f_tot, hipStream_t s) {
+    hipLaunchKernelGGL(k_sym_pairs, dim3((unsigned)sym_pair_blocks(n)), dim3(kThreads), 0, s, pos, n, acc, a);
+    hipLaunchKernelGGL(k_sym_node, dim3(sym_node_blocks(n)), dim3(kThreads), 0, s, pos, n, pos_out, row_ptr, col_idx,
+                       acc, st, a, t, f_rep, f_att, f_tot);
+}
+
+// Batched pair-symmetric exact method: map entries {member, tile pair} for
+// the pair pass and {member, node block} for the node pass, iteration j of
+// the call by its parity (like kb_brute; kb_tick advances the counters).
+__global__ __launch_bounds__(kThreads) void kb_sym_pairs(const Member* __restrict__ mem, const int2* __restrict__ map,
+                                                         int j) {
+    const int2 e = map[blockIdx.x];
+    const Member& m = mem[e.x];
+    sym_pairs_body((j & 1) ? m.alt : m.pos, m.b.n, m.b.sym_acc, m.a, e.y);
+}
+
+__global__ __launch_bounds__(kThreads) void kb_sym_node(const Member* __restrict__ mem, const int2* __restrict__ map,
+                                                        int j) {
+    const int2 e = map[blockIdx.x];
+    const Member& m = mem[e.x];
+    const float2* cur = (j & 1) ? m.alt : m.pos;
+    float2* nxt = (j & 1) ? m.pos : m.alt;
+    sym_node_body(cur, m.b.n, nxt, m.es.rp, m.es.col, m.b.sym_acc, m.b.st, m.a, m.b.st->t + 1, nullptr, nullptr,
+                  nullptr, e.y);
+}
+
+void launch_b_sym_pairs(const Member* mem, const int2* map, int blocks, int j, hipStream_t s) {
+    if (blocks > 0) hipLaunchKernelGGL(kb_sym_pairs, dim3(blocks), dim3(kThreads), 0, s, mem, map, j);
+}
+
+void launch_b_sym_node(const Member* mem, const int2* map, int blocks, int j, hipStream_t s) {
+    if (blocks > 0) hipLaunchKernelGGL(kb_sym_node, dim3(blocks), dim3(kThreads), 0, s, mem, map, j);
 }
 
 // CSR sanity check: row_ptr[0] = 0, monotone, row_ptr[n] = nnz, columns in

@@ -34,6 +34,15 @@ void enqueue_twiddles(tfdp_layout* h, hipStream_t s) {
     h->tw_pending = false;
 }
 
+int sym_min_nodes() {
+    const char* e = std::getenv("TFDP_SYM_MIN_NODES");
+    if (e) {
+        const long long v = std::atoll(e);
+        if (v >= 1 && v <= 0x7fffffffLL) return (int)v;
+    }
+    return kSymMinNodes;
+}
+
 }  // namespace tfdp
 
 namespace {
@@ -114,6 +123,7 @@ Layout carve(void* base, int n, long long nnz, const tfdp_params* p, long long s
     l.nslices = edge_slices(n, sn);
     l.slice_col = c.take<int>((size_t)nnz);
     l.fpart = c.take<float2>((size_t)n);  // attraction sums (earlier slices, or the overlapped pass)
+    l.b.sym_acc = c.take<unsigned long long>((size_t)2 * n);  // exact-method sums (kept zero between passes)
     if (l.nslices > 1) l.slice_rp = c.take<int>((size_t)l.nslices * ((size_t)n + 1));
     l.sched = c.take<int2>((size_t)4 * edge_blocks_bound(n, nnz, sn));
     l.b.blkcnt = c.take<int>((size_t)p->n_int * l.b.nblk);
@@ -213,6 +223,16 @@ struct PhaseTimer {
 // One evaluation of the interpolated repulsion up to the grid potentials;
 // the box comes from extremes slot set `set`, set ^ 1 is reset for the
 // update that follows.
+// Exact method at pos (k = 0): the one-launch kernel for small graphs, the
+// pair-symmetric passes from sym_min_nodes() nodes on.
+void enqueue_exact(tfdp_layout* h, const float2* pos, float2* pos_out, const ModelArgs& a, float2* fr, float2* fa,
+                   float2* ft, hipStream_t s) {
+    if (use_sym(h->n))
+        launch_sym(pos, pos_out, h->row_ptr, h->col_idx, h->n, h->lay.b.sym_acc, h->lay.b.st, a, h->t, fr, fa, ft, s);
+    else
+        launch_brute(pos, pos_out, h->row_ptr, h->col_idx, h->n, h->lay.b.st, a, h->t, fr, fa, ft, s);
+}
+
 void enqueue_grid(tfdp_layout* h, const float2* pos, const Bufs& b, const Geom& g, int set, hipStream_t s) {
     { PhaseTimer pt(h, PH_BIN_COUNT, s); launch_bin_count(pos, b, set, s); }
     { PhaseTimer pt(h, PH_BIN_SCAN, s); launch_bin_scan(b, set ^ 1, s); }
@@ -675,6 +695,9 @@ tfdp_status tfdp_layout_init(tfdp_layout** out, int32_t n, int64_t nnz, const in
     static const bool attrs = (init_kernel_attributes(), true);
     (void)attrs;
     st = check_hip(hipMemsetAsync(dst, 0, sizeof(DevState), stream), "hipMemsetAsync");
+    if (st == TFDP_OK)
+        st = check_hip(hipMemsetAsync(h->lay.b.sym_acc, 0, (size_t)2 * n * sizeof(unsigned long long), stream),
+                       "hipMemsetAsync");
     if (st == TFDP_OK) {
         if (nnz > 0 || n > 0) launch_csr_check(d_row_ptr, d_col_idx, n, nnz, dst, stream);
         h->tw_pending = true;
@@ -753,8 +776,7 @@ static tfdp_status step_fixed_grid(tfdp_layout* h, int32_t iters, hipStream_t s)
         }
         if (k == 0) {
             PhaseTimer pt(h, PH_BRUTE, s);
-            launch_brute(cur, alt, h->row_ptr, h->col_idx, h->n, h->lay.b.st, a, h->t, nullptr, nullptr,
-                         nullptr, s);
+            enqueue_exact(h, cur, alt, a, nullptr, nullptr, nullptr, s);
         } else {
             enqueue_run(h, k, h->t & 1, cur, alt, 1, a, s);
         }
@@ -791,7 +813,7 @@ tfdp_status tfdp_layout_forces(tfdp_layout* h, const float* d_pos_in, int32_t k,
     float2* ft = reinterpret_cast<float2*>(d_f_tot);
     if (k == 0) {
         PhaseTimer pt(h, PH_BRUTE, s);
-        launch_brute(pos, nullptr, h->row_ptr, h->col_idx, h->n, h->lay.b.st, a, h->t, fr, fa, ft, s);
+        enqueue_exact(h, pos, nullptr, a, fr, fa, ft, s);
     } else {
         enqueue_box(h, pos, 0, s);
         enqueue_evaluation(h, k, 0, pos, nullptr, a, fr, fa, ft, s);

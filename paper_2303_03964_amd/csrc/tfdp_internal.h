@@ -19,6 +19,8 @@ constexpr int kMaxSlices = 64;
 constexpr int kGraphIters = 8;             // iterations per captured graph (even; pairs for the rest)
 constexpr int kGroupRows = 64;       // rows of one wave group of the edge pass
 constexpr int kBruteRows = 64;       // rows per block of the exact repulsion (one per lane)
+constexpr int kSymTile = 256;        // nodes per tile of the pair-symmetric exact method
+constexpr int kSymMinNodes = 4096;   // graphs from this size on use it (the one-launch kernel below)
 constexpr int kAutoGridMin = 50;     // automatic grid: at least this many intervals per side
 constexpr int kAutoGridChunk = 10;   // automatic grid: iterations between grid choices
 
@@ -68,6 +70,7 @@ struct Bufs {
     int* chunk_start;    // [n_int + 1] first spreading chunk of each interval row
     int* chunk_row;      // [max_chunks] interval row of each spreading chunk
     unsigned long long* spart;  // [max_chunks][k][M][3] partial grid rows of each chunk (fixed point)
+    unsigned long long* sym_acc;  // [n][2] fixed-point repulsion sums of the pair-symmetric exact method (zero between passes)
     float2* qcol;        // [3][H][M] charge row spectra, column-major
     float2* kcol;        // [H][L] kernel row spectra (K^, H_x^/i), column-major
     float2* pcol;        // [3][H][M] potential row spectra after the column pass
@@ -174,6 +177,18 @@ inline long long edge_blocks_bound(long long n, long long nnz, long long slice_n
 void launch_brute(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx,
                   int n, DevState* st, const ModelArgs& a, int t,
                   float2* f_rep, float2* f_att, float2* f_tot, hipStream_t s);
+// Pair-symmetric exact method (graphs of at least kSymMinNodes nodes): the
+// pair pass over tile pairs, then the node pass, which clears acc.
+void launch_sym(const float2* pos, float2* pos_out, const int* row_ptr, const int* col_idx, int n,
+                unsigned long long* acc, DevState* st, const ModelArgs& a, int t, float2* f_rep, float2* f_att,
+                float2* f_tot, hipStream_t s);
+long long sym_pair_blocks(int n);
+int sym_node_blocks(int n);
+// Smallest graph on the pair-symmetric exact method: kSymMinNodes, or the
+// environment variable TFDP_SYM_MIN_NODES (>= 1) read at each call; graphs
+// whose tile pairs would not fit one launch keep the one-launch kernel.
+int sym_min_nodes();
+inline bool use_sym(int n) { return n >= sym_min_nodes() && sym_pair_blocks(n) <= 0x7fffffffLL; }
 void launch_csr_check(const int* row_ptr, const int* col_idx, int n, long long nnz,
                       DevState* st, hipStream_t s);
 
@@ -219,10 +234,13 @@ void launch_b_edges(int k, const Member* mem, const int2* map, int blocks, const
                     hipStream_t s);
 void launch_b_copy(const Member* mem, const int2* map, int blocks, hipStream_t s);
 void launch_b_advance(int* tcall, int slots, int iters, hipStream_t s);
-// exact method of the k = 0 members, then their counters advance (tick_map:
-// one entry per member)
-void launch_b_brute(const Member* mem, const int2* map, int blocks, const int2* tick_map, int members, int j,
-                    hipStream_t s);
+// exact method of the k = 0 members: one-launch kernel (map {member, row
+// block}), pair-symmetric passes (maps {member, tile pair} and {member, node
+// block}); then their counters advance (tick_map: one entry per member)
+void launch_b_brute(const Member* mem, const int2* map, int blocks, int j, hipStream_t s);
+void launch_b_sym_pairs(const Member* mem, const int2* map, int blocks, int j, hipStream_t s);
+void launch_b_sym_node(const Member* mem, const int2* map, int blocks, int j, hipStream_t s);
+void launch_b_tick(const Member* mem, const int2* tick_map, int members, hipStream_t s);
 
 // ---- layout quality (metrics.hip) ----
 size_t stress_workspace_bytes(int n, int nsrc);

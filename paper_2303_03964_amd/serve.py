@@ -66,10 +66,10 @@ EXPENSIVE_ITERATION = 2.5e-4  # members with longer iterations are stepped as a 
 
 def iteration_seconds(n: int, nnz: int, exact: bool) -> float:
     """Rough device time of one iteration of a graph on MI355X (for chunk
-    sizing only): the exact method at about 4.6e12 pair terms per second,
+    sizing only): the exact method at about 5e12 pair terms per second,
     else a launch floor plus the per-node and per-entry passes."""
     if exact:
-        return n * n / 4.6e12
+        return n * n / 5.0e12
     return 25e-6 + 6e-11 * n + 7e-12 * nnz
 
 

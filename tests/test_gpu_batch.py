@@ -111,6 +111,13 @@ def test_batch_matches_plain_bitwise(T, stream):
     run_case(T, stream, [7, 20, 13], exact_n=300)
 
 
+def test_batch_exact_symmetric_member_bitwise(T, stream):
+    # an exact member of 5,000 nodes takes the pair-symmetric passes (tile
+    # pairs and node pass in the batched launches), beside a small exact one
+    run_case(T, stream, [3, 4], members=MEMBERS[:2], exact_n=5000)
+    run_case(T, stream, [2, 5], members=MEMBERS[:1], exact_n=300)
+
+
 def test_batch_direct_launches(T, stream):
     run_case(T, stream, [5, 6], graphs_on=False)
 
