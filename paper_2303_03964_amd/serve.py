@@ -35,9 +35,13 @@ Admission work (uploads, handle creation) runs on a worker thread and a
 stream of its own, so that it waits neither for the chunk on the device nor
 holds up the stepping loop; the stepping stream waits for it before the new
 member's first chunk. Members whose iterations are long (an exact stage of a
-large graph, EXPENSIVE_ITERATION) are stepped as a second batch with chunks
-of their own length, so that the others are not held to it. The host keeps
-at most two chunks in flight. Kernels are launched directly (no stream
+large graph, EXPENSIVE_ITERATION) are stepped as a second batch on a second
+stream, with chunks of their own length: its compute-bound exact passes run
+beside the other class's latency-bound grid passes, and neither class waits
+for the other's chunks. Each class keeps at most two chunks in flight; a
+graph that changes class, or is re-tuned, evicted or copied after a chunk
+on the other stream, is ordered after that chunk by its event. Kernels are
+launched directly (no stream
 capture) in both legs, since the worker thread's GPU work runs concurrently
 with the stepping thread. Latency of a request = completion - arrival, completion
 being the device time of the event recorded after the chunk (or, plain, the
@@ -82,6 +86,8 @@ class _Graph:
     bytes: int = 0
     busy: bool = False
     ws_n_int: int = 0     # largest grid the workspace holds
+    last_ev: object = None      # event after the graph's latest chunk
+    last_stream: object = None  # the stream it was recorded on
 
 
 @dataclass
@@ -188,6 +194,13 @@ class Server:
         self.tol = tol
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.admit_stream = torch.cuda.Stream(device=self.stream.device)
+        # one stream per cost class (default priority): the long chunks of
+        # the expensive class run beside the short ones of the other
+        self.streams = [self.stream] if plain else [self.stream, torch.cuda.Stream(device=self.stream.device)]
+        # chunks in flight per class (one for the expensive class: p99 at
+        # 0.8x load within run-to-run spread, at 1.2x load 595 ms against
+        # 285 ms with two)
+        self.max_inflight = [2, 2]
         # handles are created on a worker thread (uploads, the CSR check and
         # the host-side edge schedule of tfdp_layout_init take milliseconds
         # for large graphs; the stepping loop keeps the GPU busy meanwhile)
@@ -220,6 +233,8 @@ class Server:
             if victim is None:
                 return False
             with self.torch.cuda.stream(self.stream):
+                if victim.last_ev is not None and victim.last_stream is not self.stream:
+                    self.stream.wait_event(victim.last_ev)
                 victim.host_pos = victim.lay.pos.cpu().numpy()
             victim.lay.close()
             victim.lay = None
@@ -233,9 +248,10 @@ class Server:
             pos = torch.as_tensor(pos_host).to(self.stream.device)
             lay = T.Layout(g.graph.row_ptr, g.graph.col_idx, pos, params, workspace_params=ws)
             T.tfdp_layout_set_graphs(lay.handle, 0)
-            # the tensors are used on the stepping stream from now on
+            # the tensors are used on the stepping streams from now on
             for t in (lay.row_ptr, lay.col_idx, lay.pos, lay.workspace):
-                t.record_stream(self.stream)
+                for st in self.streams:
+                    t.record_stream(st)
         return lay
 
     def _reserve(self, g: _Graph, params):
@@ -291,19 +307,23 @@ class Server:
         rec.n = g.graph.n
         rec.params = g.lay.params
         rec.ws_n_int = g.ws_n_int
-        self.stream.wait_stream(self.admit_stream)
+        for st in self.streams:
+            st.wait_stream(self.admit_stream)
+            if g.last_ev is not None and g.last_stream is not st:
+                st.wait_event(g.last_ev)  # a re-tune after a chunk on the other stream
         if self.record_inputs:
             rec.start_pos = g.lay.pos.clone()
         run = _Run(g, rec, req.iters)
         run.group = -1
         active[req.rid] = run
 
-    def _retire(self, run: _Run, event):
+    def _retire(self, run: _Run, event, stream):
         rec = run.rec
         rec.done_event = event
         rec.final = (run.g.lay.params.k_mode, run.g.lay.params.n_int)
         if self.record_outputs:
-            rec.final_pos = run.g.lay.pos.clone()
+            with self.torch.cuda.stream(stream):
+                rec.final_pos = run.g.lay.pos.clone()
         if not self.plain and run.group >= 0:
             self.batches[run.group].remove(run.g.lay)
         run.g.busy = False
@@ -318,45 +338,64 @@ class Server:
             if run.tuned:
                 continue
             if run.done == run.t_read and run.ext is None:
-                ext = box_extremes(run.g.lay.pos)
-                run.ext = torch.empty(4, dtype=ext.dtype, pin_memory=True)
-                run.ext.copy_(ext, non_blocking=True)
-                run.ext_ev = torch.cuda.Event()
-                run.ext_ev.record(self.stream)
+                st = run.g.last_stream if run.g.last_stream is not None else self.stream
+                with torch.cuda.stream(st):
+                    ext = box_extremes(run.g.lay.pos)
+                    run.ext = torch.empty(4, dtype=ext.dtype, pin_memory=True)
+                    run.ext.copy_(ext, non_blocking=True)
+                    run.ext_ev = torch.cuda.Event()
+                    run.ext_ev.record(st)
             if run.done == run.t_switch:
                 run.ext_ev.synchronize()
                 run.g.lay.set_params(final_params(run.g.lay, run.ext.numpy(), self.tol, run.g.ws_n_int))
                 run.tuned = True
 
-    def _step_batched(self, active):
-        """One chunk of every active run, per cost class; returns the runs that
-        finished and the event after the chunk."""
+    def _issue(self, active, inflight):
+        """A chunk of the active runs of every cost class whose stream has
+        fewer than two chunks in flight; returns the finished runs (with the
+        event and stream of their last chunk) and whether anything was
+        issued."""
         torch = self.torch
+        for q in inflight:
+            while q and q[0].query():
+                q.popleft()
         self._final_stage_events(active)
         groups = ([], [])
         for run in active.values():
             cost = iteration_seconds(run.g.graph.n, run.g.graph.nnz, run.g.lay.params.k_mode == 0)
-            grp = 1 if cost > EXPENSIVE_ITERATION else 0
-            if grp != run.group:
-                if run.group >= 0:
-                    self.batches[run.group].remove(run.g.lay)
-                self.batches[grp].add(run.g.lay)
-                run.group = grp
-            groups[grp].append((run, cost))
+            groups[1 if cost > EXPENSIVE_ITERATION else 0].append((run, cost))
+        finished, issued = [], False
         for grp, members in enumerate(groups):
-            if not members:
+            if not members or len(inflight[grp]) >= self.max_inflight[grp]:
                 continue
+            stream = self.streams[grp]
+            for run, _ in members:
+                if run.group != grp:
+                    if run.group >= 0:
+                        self.batches[run.group].remove(run.g.lay)
+                    self.batches[grp].add(run.g.lay)
+                    run.group = grp
+                g = run.g
+                # a graph last stepped on the other stream (class change,
+                # or a re-tune after a request of the other class)
+                if g.last_ev is not None and g.last_stream is not stream:
+                    stream.wait_event(g.last_ev)
             # at most `chunk` iterations, fewer when the members' iterations
             # are long, so that a chunk takes about CHUNK_SECONDS
             per_iter = sum(c for _, c in members)
             cap_iters = max(1, min(self.chunk, int(CHUNK_SECONDS / max(per_iter, 1e-9))))
             step = min(cap_iters, min(r.next_stop() for r, _ in members))
-            self.batches[grp].step(step)
+            self.batches[grp].step(step, stream)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(stream)
+            inflight[grp].append(ev)
+            issued = True
             for r, _ in members:
                 r.done += step
-        ev = torch.cuda.Event(enable_timing=True)
-        ev.record(self.stream)
-        return [rid for rid, r in active.items() if r.done == r.iters], ev
+                r.g.last_ev, r.g.last_stream = ev, stream
+                if r.done == r.iters:
+                    finished.append((r, ev, stream))
+        return finished, issued
 
     def run(self, trace):
         """Serve the trace; returns the list of Records in request order."""
@@ -366,7 +405,7 @@ class Server:
         waiting = []
         active = {}      # rid -> _Run
         preparing = {}   # rid -> (request, graph, future or None)
-        inflight = deque()
+        inflight = [deque() for _ in self.streams]
         i = 0
         with torch.cuda.stream(self.stream):
             torch.cuda.synchronize()
@@ -405,14 +444,25 @@ class Server:
                     ev = torch.cuda.Event(enable_timing=True)
                     ev.record(self.stream)
                     run.done = run.iters
-                    self._retire(run, ev)
-                else:
-                    finished, ev = self._step_batched(active)
-                    for rid in finished:
-                        self._retire(active.pop(rid), ev)
-                inflight.append(ev)
-                while len(inflight) > 2:
-                    inflight.popleft().synchronize()
+                    run.g.last_ev, run.g.last_stream = ev, self.stream
+                    self._retire(run, ev, self.stream)
+                    inflight[0].append(ev)
+                    while len(inflight[0]) > 2:
+                        inflight[0].popleft().synchronize()
+                    continue
+                finished, issued = self._issue(active, inflight)
+                for run, ev, st in finished:
+                    self._retire(active.pop(run.rec.rid), ev, st)
+                for q in inflight:
+                    while q and q[0].query():
+                        q.popleft()
+                if not issued:
+                    # the classes with members had two chunks in flight: wait
+                    # until one of those still in flight ends (none left, if
+                    # they all ended since the check)
+                    blocked = [q for g, q in enumerate(inflight) if q and len(q) >= self.max_inflight[g]]
+                    while blocked and not any(q[0].query() for q in blocked):
+                        time.sleep(5e-5)
             torch.cuda.synchronize()
             for r in recs.values():
                 r.done = ev0.elapsed_time(r.done_event) * 1e-3
