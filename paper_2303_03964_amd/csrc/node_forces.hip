@@ -443,11 +443,20 @@ void launch_edges(const float2* pos, float2* pos_out, const EdgeSlice& es, int m
 // adds the four sums in a fixed order, then finishes its rows.
 // Columns are read through the 26-bit column mask, so the packed edge-pass
 // entries (column | row-in-group << 26) serve as well as a plain CSR.
-template <bool G2>
+// 1 + tau d^2; for tau = 1 two fused multiply-adds.
+template <bool T1>
+__device__ __forceinline__ float one_plus_tau_d2(float dx, float dy, float tau) {
+    if constexpr (T1)
+        return __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, 1.f));
+    else
+        return 1.f + tau * (dx * dx + dy * dy);
+}
+
+template <bool G2, bool T1>
 __device__ __forceinline__ void brute_term(float2 p, float2 q, float tau, float gamma, float& frx, float& fry) {
     const float dx = p.x - q.x;
     const float dy = p.y - q.y;
-    const float u = 1.f + tau * (dx * dx + dy * dy);
+    const float u = one_plus_tau_d2<T1>(dx, dy, tau);
     float kk;
     if constexpr (G2) {
         const float r = __builtin_amdgcn_rcpf(u);  // u >= 1: hardware reciprocal, <= 1 ulp
@@ -459,7 +468,7 @@ __device__ __forceinline__ void brute_term(float2 p, float2 q, float tau, float 
     fry += kk * dy;
 }
 
-template <bool G2>
+template <bool G2, bool T1>
 __device__ __forceinline__ void brute_tile(const float2* tile, int j0, int j1, float2 p, float tau, float gamma,
                                            float& frx, float& fry) {
     // four independent partial sums (positions jj + u, u mod 4) shorten the
@@ -471,9 +480,9 @@ __device__ __forceinline__ void brute_tile(const float2* tile, int j0, int j1, f
 #pragma unroll
         for (int u = 0; u < 8; ++u) q[u] = tile[jj + u];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) brute_term<G2>(p, q[u], tau, gamma, sx[u & 3], sy[u & 3]);
+        for (int u = 0; u < 8; ++u) brute_term<G2, T1>(p, q[u], tau, gamma, sx[u & 3], sy[u & 3]);
     }
-    for (; jj < j1; ++jj) brute_term<G2>(p, tile[jj], tau, gamma, sx[0], sy[0]);
+    for (; jj < j1; ++jj) brute_term<G2, T1>(p, tile[jj], tau, gamma, sx[0], sy[0]);
     frx += (sx[0] + sx[1]) + (sx[2] + sx[3]);
     fry += (sy[0] + sy[1]) + (sy[2] + sy[3]);
 }
@@ -500,9 +509,10 @@ __device__ __forceinline__ void brute_body(const float2* __restrict__ pos, int n
         const int j0 = w * 64;
         const int j1 = min(j0 + 64, cnt);
         if (g2)
-            brute_tile<true>(tile, j0, j1, p, tau, a.gamma, frx, fry);
+            tau == 1.f ? brute_tile<true, true>(tile, j0, j1, p, tau, a.gamma, frx, fry)
+                       : brute_tile<true, false>(tile, j0, j1, p, tau, a.gamma, frx, fry);
         else
-            brute_tile<false>(tile, j0, j1, p, tau, a.gamma, frx, fry);
+            brute_tile<false, false>(tile, j0, j1, p, tau, a.gamma, frx, fry);
         __syncthreads();
     }
     if (w > 0) part[w - 1][lane] = make_float2(frx, fry);
@@ -611,9 +621,9 @@ __device__ __forceinline__ void sym_tile_pair(int p, int nt, int& I, int& J) {
 }
 
 // Repulsion term factor K(d) = (1 + tau d^2)^-gamma of one pair.
-template <bool G2>
+template <bool G2, bool T1>
 __device__ __forceinline__ float sym_kernel(float dx, float dy, float tau, float gamma) {
-    const float u = 1.f + tau * (dx * dx + dy * dy);
+    const float u = one_plus_tau_d2<T1>(dx, dy, tau);
     if constexpr (G2) {
         const float r = __builtin_amdgcn_rcpf(u);
         return r * r;
@@ -632,7 +642,7 @@ __device__ __forceinline__ void sym_add(unsigned long long* acc, int node, float
     atomicAdd(acc + 2 * (size_t)node + 1, (unsigned long long)__double2ll_rn((double)fy * scale));
 }
 
-template <bool G2>
+template <bool G2, bool T1>
 __device__ __forceinline__ void sym_pairs_t(const float2* __restrict__ pos, int n, unsigned long long* __restrict__ acc,
                                             float gamma, float tau, int p) {
     __shared__ float2 cols[kSymTile];
@@ -660,7 +670,7 @@ __device__ __forceinline__ void sym_pairs_t(const float2* __restrict__ pos, int 
                 if (c < cnt) {
                     const float2 q = cols[c];
                     const float dx = pi.x - q.x, dy = pi.y - q.y;
-                    const float kk = sym_kernel<G2>(dx, dy, tau, gamma);
+                    const float kk = sym_kernel<G2, T1>(dx, dy, tau, gamma);
                     fx[u] += kk * dx;
                     fy[u] += kk * dy;
                 }
@@ -676,7 +686,7 @@ __device__ __forceinline__ void sym_pairs_t(const float2* __restrict__ pos, int 
                 const int c = q * 64 + cl;
                 const float2 v = cols[c];
                 const float dx = pi.x - v.x, dy = pi.y - v.y;
-                float kk = sym_kernel<G2>(dx, dy, tau, gamma);
+                float kk = sym_kernel<G2, T1>(dx, dy, tau, gamma);
                 if (!full && c >= cnt) kk = 0.f;
                 fx[q] += kk * dx;
                 fy[q] += kk * dy;
@@ -703,10 +713,12 @@ __device__ __forceinline__ void sym_pairs_t(const float2* __restrict__ pos, int 
 
 __device__ __forceinline__ void sym_pairs_body(const float2* __restrict__ pos, int n,
                                                unsigned long long* __restrict__ acc, const ModelArgs& a, int p) {
-    if (a.gamma == 2.0f)
-        sym_pairs_t<true>(pos, n, acc, a.gamma, a.tau, p);
+    if (a.gamma == 2.0f && a.tau == 1.0f)
+        sym_pairs_t<true, true>(pos, n, acc, a.gamma, a.tau, p);
+    else if (a.gamma == 2.0f)
+        sym_pairs_t<true, false>(pos, n, acc, a.gamma, a.tau, p);
     else
-        sym_pairs_t<false>(pos, n, acc, a.gamma, a.tau, p);
+        sym_pairs_t<false, false>(pos, n, acc, a.gamma, a.tau, p);
 }
 
 // Node pass of the pair-symmetric exact method: repulsion from the
