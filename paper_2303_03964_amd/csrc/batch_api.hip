@@ -41,6 +41,7 @@ struct BLaunch {
     size_t off;       // first map entry (relative to the composition's region)
     int blocks;
     size_t lds;
+    int lane = 0;     // 1: a grid pass of a class other than the largest (second stream)
 };
 
 // Index of an FFT length in the batch's tile table.
@@ -122,6 +123,10 @@ struct tfdp_batch {
     std::vector<Comp> comps;
     unsigned long long clock;
     int2 tiles[9];  // per FFT length: rows per block of the row passes, column groups of the column pass
+    int device;                    // device current at creation
+    hipStream_t side;              // second stream of the grid passes (created on first use)
+    hipEvent_t ev_fork, ev_join;
+    bool side_failed;
 };
 
 namespace {
@@ -245,6 +250,29 @@ void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<in
                 emit(phase, 0, kv.first, param, 0, kv.second, blocks);
             }
     }
+    // The grid passes of different FFT lengths are independent chains: all
+    // but the length with the most blocks run on the second stream, between
+    // the binning and the edge pass. (The exact-method launches stay on the
+    // first stream after the edge pass: beside the FFT passes their
+    // arithmetic-bound blocks slowed those latency-bound ones more than they
+    // gained, size-rule grids 3.17e9 -> 2.76e9 node-it/s.)
+    {
+        std::map<int, long long> work;
+        for (const BLaunch& L : c.launches)
+            if (L.phase == B_SPREAD || L.phase == B_ROWFFT || L.phase == B_COLCONV || L.phase == B_ROWIFFT)
+                work[L.len] += L.blocks;
+        int main_len = 0;
+        long long most = -1;
+        for (auto& kv : work)
+            if (kv.second > most) {
+                most = kv.second;
+                main_len = kv.first;
+            }
+        for (BLaunch& L : c.launches)
+            if ((L.phase == B_SPREAD || L.phase == B_ROWFFT || L.phase == B_COLCONV || L.phase == B_ROWIFFT) &&
+                L.len != main_len)
+                L.lane = 1;
+    }
     // edge pass + gather + move: classes by k
     {
         std::map<int, std::vector<int>> cls;
@@ -346,25 +374,72 @@ int get_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<int>&
 
 // Iteration j of the call (the kernels read each member's counter at the
 // start of the call from the device and add j).
+// Second stream of the batch and its two events, created on first use on
+// the batch's device; false (one stream) if they cannot be created.
+bool use_side(tfdp_batch* b) {
+    if (b->side) return true;
+    if (b->side_failed) return false;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+    if (cur != b->device) (void)hipSetDevice(b->device);
+    bool ok = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) == hipSuccess;
+    if (cur >= 0 && cur != b->device) (void)hipSetDevice(cur);
+    if (!ok) {
+        if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+        if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+        if (b->side) (void)hipStreamDestroy(b->side);
+        b->side = nullptr;
+        b->ev_fork = b->ev_join = nullptr;
+        b->side_failed = true;
+        (void)hipGetLastError();
+    }
+    return ok;
+}
+
 void enqueue_iter(tfdp_batch* b, const Comp& c, int j, hipStream_t s) {
     const Member* mem = b->d_mem;
     const int2* base = b->d_arena + c.off;
+    // the second stream starts after the binning (the grid passes of the
+    // other lengths need it) and joins before the edge pass
+    bool side = false;
+    for (const BLaunch& L : c.launches) side = side || L.lane == 1;
+    side = side && use_side(b);
+    bool forked = false;
     for (const BLaunch& L : c.launches) {
         const int2* map = base + L.off;
-        switch (L.phase) {
-            case B_BIN_COUNT: launch_b_bin_count(mem, map, L.blocks, L.lds, b->d_t, j, s); break;
-            case B_BIN_SCAN: launch_b_bin_scan(mem, map, L.blocks, b->d_t, j, s); break;
-            case B_BIN_SCATTER: launch_b_bin_scatter(mem, map, L.blocks, L.lds, j, s); break;
-            case B_SPREAD: launch_b_spread(L.k, L.len, L.nw, mem, map, L.blocks, L.lds, s); break;
-            case B_ROWFFT: launch_b_rowfft(L.len, L.nw, mem, map, L.blocks, s); break;
-            case B_COLCONV: launch_b_colconv(L.len, L.nw, mem, map, L.blocks, s); break;
-            case B_ROWIFFT: launch_b_rowifft(L.len, L.nw, mem, map, L.blocks, s); break;
-            case B_EDGES: launch_b_edges(L.k, mem, map, L.blocks, b->d_t, j, s); break;
-            case B_BRUTE: launch_b_brute(mem, map, L.blocks, j, s); break;
-            case B_SYM_PAIRS: launch_b_sym_pairs(mem, map, L.blocks, j, s); break;
-            case B_SYM_NODE: launch_b_sym_node(mem, map, L.blocks, j, s); break;
-            default: launch_b_tick(mem, map, L.blocks, s); break;
+        const bool bin = L.phase == B_BIN_COUNT || L.phase == B_BIN_SCAN || L.phase == B_BIN_SCATTER;
+        if (side && !forked && !bin && L.phase != B_EDGES) {
+            (void)hipEventRecord(b->ev_fork, s);
+            (void)hipStreamWaitEvent(b->side, b->ev_fork, 0);
+            forked = true;
         }
+        if (forked && L.phase == B_EDGES) {  // the edge pass needs every grid
+            (void)hipEventRecord(b->ev_join, b->side);
+            (void)hipStreamWaitEvent(s, b->ev_join, 0);
+            forked = false;
+            side = false;
+        }
+        const hipStream_t ls = (forked && L.lane == 1) ? b->side : s;
+        switch (L.phase) {
+            case B_BIN_COUNT: launch_b_bin_count(mem, map, L.blocks, L.lds, b->d_t, j, ls); break;
+            case B_BIN_SCAN: launch_b_bin_scan(mem, map, L.blocks, b->d_t, j, ls); break;
+            case B_BIN_SCATTER: launch_b_bin_scatter(mem, map, L.blocks, L.lds, j, ls); break;
+            case B_SPREAD: launch_b_spread(L.k, L.len, L.nw, mem, map, L.blocks, L.lds, ls); break;
+            case B_ROWFFT: launch_b_rowfft(L.len, L.nw, mem, map, L.blocks, ls); break;
+            case B_COLCONV: launch_b_colconv(L.len, L.nw, mem, map, L.blocks, ls); break;
+            case B_ROWIFFT: launch_b_rowifft(L.len, L.nw, mem, map, L.blocks, ls); break;
+            case B_EDGES: launch_b_edges(L.k, mem, map, L.blocks, b->d_t, j, ls); break;
+            case B_BRUTE: launch_b_brute(mem, map, L.blocks, j, ls); break;
+            case B_SYM_PAIRS: launch_b_sym_pairs(mem, map, L.blocks, j, ls); break;
+            case B_SYM_NODE: launch_b_sym_node(mem, map, L.blocks, j, ls); break;
+            default: launch_b_tick(mem, map, L.blocks, ls); break;
+        }
+    }
+    if (forked) {
+        (void)hipEventRecord(b->ev_join, b->side);
+        (void)hipStreamWaitEvent(s, b->ev_join, 0);
     }
 }
 
@@ -427,6 +502,10 @@ tfdp_status tfdp_batch_create(tfdp_batch** out, int32_t capacity, void* d_ws, si
     b->arena_used = 0;
     b->graphs = true;
     b->clock = 0;
+    if (hipGetDevice(&b->device) != hipSuccess) b->device = 0;
+    b->side = nullptr;
+    b->ev_fork = b->ev_join = nullptr;
+    b->side_failed = false;
     for (int i = 0; i < 9; ++i) b->tiles[i] = make_int2(batch_rows_default(kLens[i]), batch_groups_default(kLens[i]));
     *out = b;
     return TFDP_OK;
@@ -632,6 +711,9 @@ tfdp_status tfdp_batch_step(tfdp_batch* b, int32_t iters, hipStream_t s) {
 void tfdp_batch_destroy(tfdp_batch* b) {
     if (!b) return;
     drop_comps(b);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->side) (void)hipStreamDestroy(b->side);
     delete b;
 }
 
