@@ -316,6 +316,11 @@ tfdp_status tfdp_quality_sampled_noalloc(int32_t n, int64_t nnz, const int32_t* 
  * when the arena is full it is reset after one synchronisation of the
  * stream. A composition needs at most about n/60 + nnz/200 + 4,300 map
  * entries per member (8 bytes each; the constant covers the largest grid).
+ * At its first step the batch creates a second stream and two events on the
+ * device that was current at tfdp_batch_create (no device memory): the grid
+ * passes of all but the largest FFT length run there, between the binning
+ * and the edge pass of each iteration; the call is still ordered on
+ * `stream` as a whole. tfdp_batch_destroy releases them.
  * Adding, removing or re-tuning members costs no synchronisation: the new
  * kernel arguments and counters are written by small kernels on the stream
  * at the next step. Groups of eight (else two) iterations of a composition
