@@ -88,9 +88,6 @@ int attract_blocks_per_cu(int k) {
     return k <= 1 ? 3 : 2;
 }
 
-
-
-
 // Column-slice width of the edge pass: kSliceNodesDefault, or the value of
 // the environment variable TFDP_EDGE_SLICE_NODES (>= 1024) read at each call.
 // One slice is fastest on MI355X up to millions of nodes (measured); the
