@@ -134,7 +134,7 @@ namespace {
 Member make_member(const tfdp_layout* h, int slot, int k) {
     Member m;
     std::memset(&m, 0, sizeof(m));
-    m.b = bufs_for(h, k);
+    m.b = bufs_for(h, k, true);
     m.g = make_geom(h->p.n_int, k);
     m.a = model_args(h);
     m.es = h->lay.slice[0];
@@ -193,7 +193,7 @@ void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<in
         std::vector<int> bc, bs, bsc;
         size_t lds_c = 0, lds_s = 0;
         for (int i : order) {
-            const Bufs bb = bufs_for(H(i), ks[i]);
+            const Bufs bb = bufs_for(H(i), ks[i], true);
             const Dims dc = bin_count_dims(bb), ds = bin_scan_dims(bb), dsc = bin_scatter_dims(bb);
             bc.push_back(dc.grid);
             bs.push_back(ds.grid);
@@ -211,7 +211,7 @@ void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<in
         for (int i : order) {
             const Geom g = make_geom(H(i)->p.n_int, ks[i]);
             int nw, nkb;
-            spread_dims(bufs_for(H(i), ks[i]), g, &nw, &nkb);
+            spread_dims(bufs_for(H(i), ks[i], true), g, &nw, &nkb);
             cls[std::make_tuple(ks[i], g.L, nw)].push_back(i);
         }
         for (auto& kv : cls) {
@@ -219,7 +219,7 @@ void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<in
             size_t lds = 0;
             for (int i : kv.second) {
                 int nw, nkb;
-                const Dims d = spread_dims(bufs_for(H(i), ks[i]), make_geom(H(i)->p.n_int, ks[i]), &nw, &nkb);
+                const Dims d = spread_dims(bufs_for(H(i), ks[i], true), make_geom(H(i)->p.n_int, ks[i]), &nw, &nkb);
                 blocks.push_back(d.grid);
                 lds = std::max(lds, d.lds);
             }

@@ -204,31 +204,96 @@ __device__ __forceinline__ void bin_scatter_body(const float2* __restrict__ pos,
     int* base = sm;                  // [n_int] global slot of this block's first node per row
     int* run = base + n_int;         // [n_int] nodes of this block already placed per row
     int* scan_lds = run + n_int;     // [kThreads/64 + 1]
-    // bucket starts: exclusive scan over rows (n_int <= 1024, four per thread)
+    int* gflag = scan_lds + kThreads / 64 + 1;  // [groups] (block 0) the row group is one chunk
+    int* bsl = gflag + n_int;                   // [n_int + 1] (block 0) bucket starts
+    const int rg = b.rgroup;
+    const int ngroups = (n_int + rg - 1) / rg;
+    if (bid == 0 && rg > 1) {
+        // a group of rg consecutive rows holding at most 2 kSpreadChunk nodes
+        // together is spread by one block
+        for (int gi = threadIdx.x; gi < ngroups; gi += blockDim.x) {
+            const int r0 = gi * rg, r1 = min(r0 + rg, n_int);
+            int tot = 0;
+            for (int c = r0; c < r1; ++c) tot += b.bucket_cnt[c];
+            gflag[gi] = (r1 - r0 >= 2 && tot <= 2 * kSpreadChunk) ? 1 : 0;
+        }
+        __syncthreads();
+    }
+    // bucket starts: exclusive scan over rows (n_int <= 1024, four per
+    // thread); block 0 also numbers the partial rows of the spreading pass:
+    // one per row of a grouped row, else one per kSpreadChunk nodes (at
+    // least one), consecutive for each row
     int carry = 0;
     int chunk_carry = 0;
     for (int c0 = 0; c0 < n_int; c0 += blockDim.x) {
         const int c = c0 + threadIdx.x;
         const int cnt = c < n_int ? b.bucket_cnt[c] : 0;
-        const int chunks = c < n_int ? max(1, (cnt + kSpreadChunk - 1) / kSpreadChunk) : 0;
+        int parts = 0;
+        if (bid == 0 && c < n_int)
+            parts = (rg > 1 && gflag[c / rg]) ? 1 : max(1, (cnt + kSpreadChunk - 1) / kSpreadChunk);
         int tot, tot2;
         const int ex = block_exclusive_scan(cnt, scan_lds, tot);
-        const int ex2 = block_exclusive_scan(chunks, scan_lds, tot2);
+        const int ex2 = block_exclusive_scan(parts, scan_lds, tot2);
         if (c < n_int) {
             base[c] = carry + ex + b.blkcnt[(size_t)c * b.nblk + bid];
             run[c] = 0;
             if (bid == 0) {
                 b.bucket_start[c] = carry + ex;
                 b.chunk_start[c] = chunk_carry + ex2;
-                for (int k = 0; k < chunks; ++k) b.chunk_row[chunk_carry + ex2 + k] = c;
+                bsl[c] = carry + ex;
+                if (rg == 1)  // one block per row share: work chunks = partial rows
+                    for (int u = 0; u < parts; ++u)
+                        b.wchunk[chunk_carry + ex2 + u] = make_int4(
+                            c, 1, carry + ex + u * kSpreadChunk, min(carry + ex + (u + 1) * kSpreadChunk, carry + ex + cnt));
             }
         }
         carry += tot;
         chunk_carry += tot2;
     }
-    if (bid == 0 && threadIdx.x == 0) {
+    if (bid == 0 && rg == 1 && threadIdx.x == 0) {
         b.bucket_start[n_int] = carry;
         b.chunk_start[n_int] = chunk_carry;
+        b.wchunk[b.max_chunks] = make_int4(chunk_carry, 0, 0, 0);
+    }
+    if (bid == 0 && rg > 1) {
+        if (threadIdx.x == 0) {
+            b.bucket_start[n_int] = carry;
+            b.chunk_start[n_int] = chunk_carry;
+            bsl[n_int] = carry;
+        }
+        __syncthreads();
+        // work chunks of the spreading pass, {first row, rows, first node,
+        // end}: a grouped row group, or a row's share of kSpreadChunk nodes
+        int wcarry = 0;
+        for (int g0 = 0; g0 < ngroups; g0 += blockDim.x) {
+            const int gi = g0 + threadIdx.x;
+            int nw = 0;
+            const int r0 = gi * rg, r1 = min(r0 + rg, n_int);
+            if (gi < ngroups) {
+                if (gflag[gi]) {
+                    nw = 1;
+                } else {
+                    for (int c = r0; c < r1; ++c) nw += max(1, (bsl[c + 1] - bsl[c] + kSpreadChunk - 1) / kSpreadChunk);
+                }
+            }
+            int tot;
+            const int ex = block_exclusive_scan(nw, scan_lds, tot);
+            if (gi < ngroups) {
+                int k = wcarry + ex;
+                if (gflag[gi]) {
+                    b.wchunk[k] = make_int4(r0, r1 - r0, bsl[r0], bsl[r1]);
+                } else {
+                    for (int c = r0; c < r1; ++c) {
+                        const int q = max(1, (bsl[c + 1] - bsl[c] + kSpreadChunk - 1) / kSpreadChunk);
+                        for (int u = 0; u < q; ++u)
+                            b.wchunk[k++] = make_int4(c, 1, bsl[c] + u * kSpreadChunk,
+                                                      min(bsl[c] + (u + 1) * kSpreadChunk, bsl[c + 1]));
+                    }
+                }
+            }
+            wcarry += tot;
+        }
+        if (threadIdx.x == 0) b.wchunk[b.max_chunks] = make_int4(wcarry, 0, 0, 0);
     }
     __syncthreads();
     // slots inside the block's range of each row by LDS atomics: the order
@@ -262,7 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const float2* __restri
 Dims bin_count_dims(const Bufs& b) { return Dims{b.nblk, kThreads, (size_t)b.n_int * sizeof(int)}; }
 Dims bin_scan_dims(const Bufs& b) { return Dims{b.nblk <= kSerialScanBlocks ? 1 : b.n_int, kThreads, 0}; }
 Dims bin_scatter_dims(const Bufs& b) {
-    return Dims{b.nblk, kThreads, (size_t)(2 * b.n_int + kThreads / 64 + 1) * sizeof(int)};
+    return Dims{b.nblk, kThreads, (size_t)(4 * b.n_int + kThreads / 64 + 2) * sizeof(int)};
 }
 
 void launch_bin_count(const float2* pos, const Bufs& b, int set, hipStream_t s) {

@@ -311,16 +311,21 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
         // the adds, and they run several times faster than float LDS
         // atomics. A chunk holds at most kSpreadChunk nodes with Lagrange
         // weights of magnitude < 2, far from the 2^63 limit.
-        unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem4);  // [K][M][3]
+        unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem4);  // [rows][K][M][3]
+        __shared__ int slot[kSpreadGroupRows];
         const int per = K * M * 3;
         const int blk = bid;
         const int n_int = b.n_int;
-        const int nchunks = b.chunk_start[n_int];
-        const int cy = b.chunk_row[blk];
-        if (blk >= nchunks) return;
-        const int beg = b.bucket_start[cy] + (blk - b.chunk_start[cy]) * kSpreadChunk;
-        const int end = min(beg + kSpreadChunk, b.bucket_start[cy + 1]);
-        for (int i = threadIdx.x; i < per; i += blockDim.x) acc[i] = 0ull;
+        const int nwork = b.wchunk[b.max_chunks].x;
+        if (blk >= nwork) return;
+        const int4 wc = b.wchunk[blk];
+        const int row0 = wc.x, nrows = wc.y, beg = wc.z, end = wc.w;
+        // partial row of each covered row: one per row of a group, else this
+        // chunk's place among its row's chunks
+        if (threadIdx.x < nrows)
+            slot[threadIdx.x] = nrows > 1 ? b.chunk_start[row0 + threadIdx.x]
+                                          : b.chunk_start[row0] + (beg - b.bucket_start[row0]) / kSpreadChunk;
+        for (int i = threadIdx.x; i < nrows * per; i += blockDim.x) acc[i] = 0ull;
         __syncthreads();
         const Box bx = b.st->box;
         constexpr double kFix = 4294967296.0;  // 2^32
@@ -337,6 +342,9 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
                 double tx, ty;
                 bin_axis(p.x, bx.lo_x, bx.h, n_int, cx, tx);
                 bin_axis(p.y, bx.lo_y, bx.h, n_int, cyy, ty);
+                // the node's row inside the chunk (the binning pass put it in
+                // row cyy by the same computation)
+                unsigned long long* racc = acc + (size_t)min(max(cyy - row0, 0), nrows - 1) * per;
                 double wx[K], wy[K], ux[K], uy[K];
                 lagrange<K>(tx, wx);
                 lagrange<K>(ty, wy);
@@ -351,7 +359,7 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
 #pragma clang fp contract(off)
                             wt = wx[a] * wy[bb];
                         }
-                        unsigned long long* cell = acc + ((bb * M) + cx * K + a) * 3;
+                        unsigned long long* cell = racc + ((bb * M) + cx * K + a) * 3;
                         atomicAdd(cell + 0, (unsigned long long)__double2ll_rn(wt * kFix));
                         atomicAdd(cell + 1, (unsigned long long)__double2ll_rn(wt * ux[a] * kFix));
                         atomicAdd(cell + 2, (unsigned long long)__double2ll_rn(wt * uy[bb] * kFix));
@@ -362,8 +370,10 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
         __syncthreads();
         // partial rows stay in fixed point: the row pass sums the chunks of a
         // row exactly, so no result depends on how a row is cut into chunks
-        unsigned long long* out = b.spart + (size_t)blk * per;
-        for (int i = threadIdx.x; i < per; i += blockDim.x) out[i] = acc[i];
+        for (int i = threadIdx.x; i < nrows * per; i += blockDim.x) {
+            const int q = i / per;
+            b.spart[(size_t)slot[q] * per + (i - q * per)] = acc[i];
+        }
         return;
     }
     constexpr int F = task_ffts<L>();
@@ -430,7 +440,8 @@ __global__ __launch_bounds__(512) void kb_spread(const Member* __restrict__ mem,
 }
 
 Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
-    const size_t per = (size_t)g.k * g.m * 3 * sizeof(unsigned long long);  // <= 74 KB (M <= 1023)
+    // rgroup row copies (rgroup x per <= 48 KB, or one row of <= 74 KB at M <= 1023)
+    const size_t per = (size_t)b.rgroup * g.k * g.m * 3 * sizeof(unsigned long long);
     // waves per block: graphs of a few ten thousand nodes have rows of tens
     // to hundreds of nodes, which four waves spread as fast as eight, and
     // half the threads leave room for more blocks (batched 512-graph

@@ -127,7 +127,7 @@ Layout carve(void* base, int n, long long nnz, const tfdp_params* p, long long s
     l.b.bucket_cnt = c.take<int>((size_t)p->n_int);
     l.b.bucket_start = c.take<int>((size_t)p->n_int + 1);
     l.b.chunk_start = c.take<int>((size_t)p->n_int + 1);
-    l.b.chunk_row = c.take<int>((size_t)l.b.max_chunks);
+    l.b.wchunk = c.take<int4>((size_t)l.b.max_chunks + 1);
     l.b.spart = c.take<unsigned long long>((size_t)l.b.max_chunks * kw * gw.m * 3);
     l.b.qcol = c.take<float2>((size_t)3 * gw.H * gw.m);
     l.b.kcol = c.take<float2>((size_t)gw.H * gw.L);

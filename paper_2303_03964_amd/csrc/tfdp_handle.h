@@ -124,9 +124,14 @@ inline ModelArgs model_args(const tfdp_layout* h) {
     return a;
 }
 
-inline Bufs bufs_for(const tfdp_layout* h, int k) {
+inline Bufs bufs_for(const tfdp_layout* h, int k, bool batched = false) {
     Bufs b = h->lay.b;
     b.tw = h->lay.tw[k];
+    // sparse rows grouped per spreading block in batched launches only:
+    // there the blocks of many graphs fill the chip, while the plain pass of
+    // one graph needs a block per row for its parallelism (the grouping does
+    // not change the exact sums)
+    b.rgroup = batched ? spread_row_group(k, b.n_int) : 1;
     return b;
 }
 

@@ -4,12 +4,14 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <cstdlib>
 
 namespace tfdp {
 
 constexpr int kThreads = 256;        // threads per block of the node and FFT kernels
 constexpr int kBinChunk = 2048;      // nodes per block of the binning passes
-constexpr int kSpreadChunk = 4096;   // sorted nodes per block of the spreading pass
+constexpr int kSpreadChunk = 4096;   // sorted nodes per block of the spreading pass (one row's share)
+constexpr int kSpreadGroupRows = 8;  // sparse interval rows one spreading block may take together
 constexpr int kBoxSlots = 64;        // slots of the box extremes (one 128-byte line each)
 constexpr int kMaxL = 2048;          // largest FFT length per side
 constexpr int kMaxNInt = 1024;       // largest number of intervals per side
@@ -67,9 +69,11 @@ struct Bufs {
     int* blkcnt;         // [n_int][nblk] counts, then exclusive offsets
     int* bucket_cnt;     // [n_int]
     int* bucket_start;   // [n_int + 1]
-    int* chunk_start;    // [n_int + 1] first spreading chunk of each interval row
-    int* chunk_row;      // [max_chunks] interval row of each spreading chunk
-    unsigned long long* spart;  // [max_chunks][k][M][3] partial grid rows of each chunk (fixed point)
+    int* chunk_start;    // [n_int + 1] first partial row of each interval row (spreading pass)
+    int4* wchunk;        // [max_chunks + 1] spreading blocks {first row, rows, first node, end};
+                         // entry max_chunks: {number of blocks, 0, 0, 0}
+    int rgroup;          // interval rows one spreading block may take (this k's row size)
+    unsigned long long* spart;  // [max_chunks][k][M][3] partial grid rows (fixed point)
     unsigned long long* sym_acc;  // [n][2] fixed-point repulsion sums of the pair-symmetric exact method (zero between passes)
     float2* qcol;        // [3][H][M] charge row spectra, column-major
     float2* kcol;        // [H][L] kernel row spectra (K^, H_x^/i), column-major
@@ -113,6 +117,19 @@ struct Member {
     int nkb;            // logical kernel-row blocks of the spreading pass
     int box_blocks;     // blocks of the box reduction
 };
+
+// Interval rows one spreading block may hold in LDS at once for k and
+// n_int: up to kSpreadGroupRows row copies of K x M x 3 64-bit sums in 48 KB.
+inline int spread_row_group(int k, int n_int) {
+    const long long per = (long long)k * n_int * k * 3 * 8;
+    long long cap = kSpreadGroupRows;
+    if (const char* e = std::getenv("TFDP_SPREAD_GROUP_ROWS")) {  // 1 .. kSpreadGroupRows
+        const long long v = std::atoll(e);
+        if (v >= 1 && v <= kSpreadGroupRows) cap = v;
+    }
+    const long long g = per > 0 ? 49152 / per : 1;
+    return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
 
 // Slot-set parity and position buffers of iteration j of a batched call for
 // a graph whose counter was t0 at the start of the call.
