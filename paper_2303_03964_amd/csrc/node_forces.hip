@@ -584,15 +584,17 @@ void launch_brute(const float2* pos, float2* pos_out, const int* row_ptr, const 
 //
 // For larger graphs the exact repulsion takes every unordered pair once
 // (Newton's third law: the term of (j, i) is minus that of (i, j)). Blocks
-// take tile pairs (I, J), I <= J, of kSymTile nodes. In an off-diagonal block
-// lane l of wave w holds row i = I kSymTile + 64 w + l and, at step s, meets
-// column q 64 + ((l + s) mod 64) of each quarter q of tile J; the column's
-// running sum of minus the row terms travels with it, one lane down per
-// step, so that after 64 steps lane l holds the sums of columns q 64 + l.
-// A diagonal block sums both orders of its pairs into the rows only. Each
-// block adds its row and column sums to per-node 64-bit fixed-point
-// accumulators with integer atomics, which are exact, so the totals do not
-// depend on the order of the blocks; the node pass reads and clears them.
+// take tile pairs (I, J), I <= J, of kSymTile nodes. Every wave holds the
+// whole row tile, lane l the rows I kSymTile + 64 r + l (r < 4), and takes
+// one quarter of tile J's columns: at step s lane l meets column
+// 64 w + ((l + s) mod 64) with its four rows; the column's running sum of
+// minus the row terms travels with it, one lane down per step, so that after
+// 64 steps lane l holds the sum of column 64 w + l over the row tile. The
+// waves' row sums are combined in LDS in a fixed order. A diagonal block
+// sums both orders of its pairs into the rows only. Each block adds its row
+// and column sums to per-node 64-bit fixed-point accumulators with integer
+// atomics, which are exact, so the totals do not depend on the order of the
+// blocks; the node pass reads and clears them.
 
 // Scale of the fixed-point sums: a pair term is below tmax = max over d of
 // d (1 + tau d^2)^-gamma in magnitude (reached at d^2 = 1 / (tau (2 gamma -
@@ -645,70 +647,73 @@ __device__ __forceinline__ void sym_add(unsigned long long* acc, int node, float
 template <bool G2, bool T1>
 __device__ __forceinline__ void sym_pairs_t(const float2* __restrict__ pos, int n, unsigned long long* __restrict__ acc,
                                             float gamma, float tau, int p) {
+    constexpr int R = kSymTile / 64;  // rows per lane: every wave holds the whole row tile
     __shared__ float2 cols[kSymTile];
-    __shared__ float2 gpart[kSymTile / 64][kSymTile];
+    __shared__ float2 rpart[kSymTile / 64][kSymTile];  // each wave's row sums over its column quarter
     const int nt = (n + kSymTile - 1) / kSymTile;
     int I, J;
     sym_tile_pair(p, nt, I, J);
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int i = I * kSymTile + threadIdx.x;
     const int jt = J * kSymTile + threadIdx.x;
     cols[threadIdx.x] = jt < n ? pos[jt] : make_float2(0.f, 0.f);
-    const float2 pi = i < n ? pos[i] : make_float2(0.f, 0.f);
+    float2 pi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = I * kSymTile + r * 64 + lane;
+        pi[r] = i < n ? pos[i] : make_float2(0.f, 0.f);
+    }
     const double scale = sym_scale(n, gamma, tau);
     const int cnt = min(kSymTile, n - J * kSymTile);  // columns of tile J inside the graph
+    const int cbase = w * 64;                         // this wave's quarter of the columns
     __syncthreads();
-    float fx[4] = {0.f, 0.f, 0.f, 0.f}, fy[4] = {0.f, 0.f, 0.f, 0.f};
+    float fx[R], fy[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) fx[r] = fy[r] = 0.f;
     if (I == J) {
         // both orders of every pair of the tile, into the rows (the term of
         // a node with itself is zero)
-        for (int c0 = 0; c0 < cnt; c0 += 4) {
+        const int c1 = min(cbase + 64, cnt);
+        for (int c = cbase; c < c1; ++c) {
+            const float2 v = cols[c];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = c0 + u;
-                if (c < cnt) {
-                    const float2 q = cols[c];
-                    const float dx = pi.x - q.x, dy = pi.y - q.y;
-                    const float kk = sym_kernel<G2, T1>(dx, dy, tau, gamma);
-                    fx[u] += kk * dx;
-                    fy[u] += kk * dy;
-                }
+            for (int r = 0; r < R; ++r) {
+                const float dx = pi[r].x - v.x, dy = pi[r].y - v.y;
+                const float kk = sym_kernel<G2, T1>(dx, dy, tau, gamma);
+                fx[r] += kk * dx;
+                fy[r] += kk * dy;
             }
         }
     } else {
-        float gx[4] = {0.f, 0.f, 0.f, 0.f}, gy[4] = {0.f, 0.f, 0.f, 0.f};
+        float gx = 0.f, gy = 0.f;
         const bool full = cnt == kSymTile;
         for (int s = 0; s < 64; ++s) {
-            const int cl = (lane + s) & 63;
+            const int c = cbase + ((lane + s) & 63);
+            const float2 v = cols[c];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int c = q * 64 + cl;
-                const float2 v = cols[c];
-                const float dx = pi.x - v.x, dy = pi.y - v.y;
+            for (int r = 0; r < R; ++r) {
+                const float dx = pi[r].x - v.x, dy = pi[r].y - v.y;
                 float kk = sym_kernel<G2, T1>(dx, dy, tau, gamma);
                 if (!full && c >= cnt) kk = 0.f;
-                fx[q] += kk * dx;
-                fy[q] += kk * dy;
-                gx[q] -= kk * dx;
-                gy[q] -= kk * dy;
+                fx[r] += kk * dx;
+                fy[r] += kk * dy;
+                gx -= kk * dx;
+                gy -= kk * dy;
             }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                gx[q] = lane_next(gx[q]);
-                gy[q] = lane_next(gy[q]);
-            }
+            gx = lane_next(gx);
+            gy = lane_next(gy);
         }
+        // lane l now holds column cbase + l, summed over the whole row tile
+        const int j = J * kSymTile + cbase + lane;
+        if (j < n) sym_add(acc, j, gx, gy, scale);
+    }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) gpart[w][q * 64 + lane] = make_float2(gx[q], gy[q]);
-    }
-    if (i < n) sym_add(acc, i, (fx[0] + fx[1]) + (fx[2] + fx[3]), (fy[0] + fy[1]) + (fy[2] + fy[3]), scale);
-    if (I != J) {
-        __syncthreads();
-        const float2 a0 = gpart[0][threadIdx.x], a1 = gpart[1][threadIdx.x];
-        const float2 a2 = gpart[2][threadIdx.x], a3 = gpart[3][threadIdx.x];
-        if (jt < n) sym_add(acc, jt, (a0.x + a1.x) + (a2.x + a3.x), (a0.y + a1.y) + (a2.y + a3.y), scale);
-    }
+    for (int r = 0; r < R; ++r) rpart[w][r * 64 + lane] = make_float2(fx[r], fy[r]);
+    __syncthreads();
+    const float2 a0 = rpart[0][threadIdx.x], a1 = rpart[1][threadIdx.x];
+    const float2 a2 = rpart[2][threadIdx.x], a3 = rpart[3][threadIdx.x];
+    const int i = I * kSymTile + threadIdx.x;
+    if (i < n) sym_add(acc, i, (a0.x + a1.x) + (a2.x + a3.x), (a0.y + a1.y) + (a2.y + a3.y), scale);
 }
 
 __device__ __forceinline__ void sym_pairs_body(const float2* __restrict__ pos, int n,
