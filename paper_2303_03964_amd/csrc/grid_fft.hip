@@ -301,14 +301,16 @@ static void allow_big_lds(Kern k) {
 
 // ----------------------------------------------------------------- spread + kernel rows
 
-// Blocks [0, max_chunks): one chunk of <= kSpreadChunk sorted nodes of one
-// interval row each, accumulated into the row's K grid rows in LDS (exact
-// fixed-point sums, hence reproducible) and written as one contiguous
-// partial row set.
-// Blocks past max_chunks: RBK kernel rows each, FFT over a of
+// Blocks [0, chunk_blocks): the work chunks the binning pass listed, block
+// bid taking chunks bid, bid + chunk_blocks, ...: up to kSpreadChunk sorted
+// nodes of one interval row, or a group of sparse consecutive rows (batched
+// launches), accumulated into the rows' K grid rows in LDS (exact
+// fixed-point sums, hence reproducible) and written as one partial row set
+// per row.
+// Blocks past chunk_blocks: RBK kernel rows each, FFT over a of
 // K(a, b) + i H_x(a, b); the result is real, its even part the row spectrum of
 // K, minus its odd part the row spectrum of H_x divided by i.
-// bid < max_chunks: chunk block; otherwise lb = logical kernel-row block.
+// bid < chunk_blocks: chunk block; otherwise lb = logical kernel-row block.
 template <int K, int L>
 __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float gamma, float tau, int nw, int bid,
                                             int lb) {
@@ -316,7 +318,7 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
     const int M = g.m;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    if (bid < b.max_chunks) {
+    if (bid < b.chunk_blocks) {
         // One block-wide copy of the interval row's K grid rows in 64-bit
         // fixed point (units of 2^-32; offsets in interval units): integer
         // LDS atomics are exact, so the sums do not depend on the order of
@@ -326,10 +328,10 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
         unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem4);  // [rows][K][M][3]
         __shared__ int slot[kSpreadGroupRows];
         const int per = K * M * 3;
-        const int blk = bid;
         const int n_int = b.n_int;
         const int nwork = b.wchunk[b.max_chunks].x;
-        if (blk >= nwork) return;
+        // work chunks bid, bid + chunk_blocks, ... (block-uniform loop)
+        for (int blk = bid; blk < nwork; blk += b.chunk_blocks) {
         const int4 wc = b.wchunk[blk];
         const int row0 = wc.x, nrows = wc.y, beg = wc.z, end = wc.w;
         // partial row of each covered row: one per row of a group, else this
@@ -386,6 +388,8 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
             const int q = i / per;
             b.spart[(size_t)slot[q] * per + (i - q * per)] = acc[i];
         }
+        __syncthreads();  // acc and slot are reused by the next work chunk
+        }
         return;
     }
     constexpr int F = task_ffts<L>();
@@ -434,20 +438,20 @@ __global__ __launch_bounds__(512) void k_spread(Bufs b, Geom g, float gamma, flo
     grid_pass_priority();
     const int bid = blockIdx.x;
     int lb = -1;
-    if (bid >= b.max_chunks) {
-        lb = xcd_pair_block(bid - b.max_chunks, nkb);
+    if (bid >= b.chunk_blocks) {
+        lb = xcd_pair_block(bid - b.chunk_blocks, nkb);
         if (lb < 0) return;
     }
     spread_body<K, L>(b, g, gamma, tau, nw, bid, lb);
 }
 
-// Batched: map entry {member, block}; blocks past the member's max_chunks
+// Batched: map entry {member, block}; blocks past the member's chunk_blocks
 // are its logical kernel-row blocks.
 template <int K, int L>
 __global__ __launch_bounds__(512) void kb_spread(const Member* __restrict__ mem, const int2* __restrict__ map) {
     const int2 e = map[blockIdx.x];
     const Member& m = mem[e.x];
-    spread_body<K, L>(m.b, m.g, m.a.gamma, m.a.tau, m.nw, e.y, e.y - m.b.max_chunks);
+    spread_body<K, L>(m.b, m.g, m.a.gamma, m.a.tau, m.nw, e.y, e.y - m.b.chunk_blocks);
 }
 
 Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
@@ -465,7 +469,7 @@ Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
     const int nkb = (g.L / 2 + 1 + RBK - 1) / RBK;  // rows 0 .. L/2
     *nw_out = nw;
     *nkb_out = nkb;
-    return Dims{b.max_chunks + nkb, nw * 64, lds};
+    return Dims{b.chunk_blocks + nkb, nw * 64, lds};
 }
 
 template <int K, int L>
@@ -473,7 +477,7 @@ static void launch_spread_t(const Bufs& b, const Geom& g, float gamma, float tau
     static_assert(RowTile<L>::RBK == 8, "spread_dims assumes 8 kernel rows per block");
     int nw, nkb;
     const Dims d = spread_dims(b, g, &nw, &nkb);
-    hipLaunchKernelGGL((k_spread<K, L>), dim3(b.max_chunks + xcd_pair_grid(nkb)), dim3(d.block), d.lds, s, b, g,
+    hipLaunchKernelGGL((k_spread<K, L>), dim3(b.chunk_blocks + xcd_pair_grid(nkb)), dim3(d.block), d.lds, s, b, g,
                        gamma, tau, nw, nkb);
 }
 

@@ -132,6 +132,10 @@ inline Bufs bufs_for(const tfdp_layout* h, int k, bool batched = false) {
     // one graph needs a block per row for its parallelism (the grouping does
     // not change the exact sums)
     b.rgroup = batched ? spread_row_group(k, b.n_int) : 1;
+    // grouped rows leave about max_chunks / rgroup work chunks: launch that
+    // many blocks (each loops over the chunks it is given) rather than one
+    // block per possible chunk
+    b.chunk_blocks = (b.max_chunks + b.rgroup - 1) / b.rgroup;
     return b;
 }
 

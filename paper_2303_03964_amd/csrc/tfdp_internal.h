@@ -73,6 +73,8 @@ struct Bufs {
     int4* wchunk;        // [max_chunks + 1] spreading blocks {first row, rows, first node, end};
                          // entry max_chunks: {number of blocks, 0, 0, 0}
     int rgroup;          // interval rows one spreading block may take (this k's row size)
+    int chunk_blocks;    // spreading blocks launched for the work chunks (each takes every
+                         // chunk_blocks-th one); then the kernel-row blocks
     unsigned long long* spart;  // [max_chunks][k][M][3] partial grid rows (fixed point)
     unsigned long long* sym_acc;  // [n][2] fixed-point repulsion sums of the pair-symmetric exact method (zero between passes)
     float2* qcol;        // [3][H][M] charge row spectra, column-major
