@@ -316,11 +316,13 @@ tfdp_status tfdp_quality_sampled_noalloc(int32_t n, int64_t nnz, const int32_t* 
  * when the arena is full it is reset after one synchronisation of the
  * stream. A composition needs at most about n/60 + nnz/200 + 4,300 map
  * entries per member (8 bytes each; the constant covers the largest grid).
- * At its first step the batch creates a second stream and two events on the
- * device that was current at tfdp_batch_create (no device memory): the grid
- * passes of all but the largest FFT length run there, between the binning
- * and the edge pass of each iteration; the call is still ordered on
- * `stream` as a whole. tfdp_batch_destroy releases them.
+ * While graphs are enabled (tfdp_batch_set_graphs), at its first step the
+ * batch creates a second stream and two events on the device that was
+ * current at tfdp_batch_create (no device memory): the grid passes of all
+ * but the largest FFT length run there, between the binning and the edge
+ * pass of each iteration; the call is still ordered on `stream` as a whole.
+ * With graphs disabled every launch stays on `stream`. tfdp_batch_destroy
+ * releases them.
  * Adding, removing or re-tuning members costs no synchronisation: the new
  * kernel arguments and counters are written by small kernels on the stream
  * at the next step. Groups of eight (else two) iterations of a composition
@@ -373,7 +375,8 @@ tfdp_status tfdp_batch_set_tiles(tfdp_batch* b, int32_t fft_length, int32_t rows
 tfdp_status tfdp_batch_get_tiles(const tfdp_batch* b, int32_t fft_length, int32_t* rows_per_block,
                                  int32_t* column_groups);
 /* Capture groups of iterations as HIP graphs (default on; the stream must
- * then not be the legacy default stream). */
+ * then not be the legacy default stream). Off: every kernel is launched
+ * directly on the step's stream (no second stream either). */
 tfdp_status tfdp_batch_set_graphs(tfdp_batch* b, int32_t enable);
 /* Free the batch (host memory and captured graphs; the members and the
  * workspace stay valid). */

@@ -402,10 +402,14 @@ void enqueue_iter(tfdp_batch* b, const Comp& c, int j, hipStream_t s) {
     const Member* mem = b->d_mem;
     const int2* base = b->d_arena + c.off;
     // the second stream starts after the binning (the grid passes of the
-    // other lengths need it) and joins before the edge pass
+    // other lengths need it) and joins before the edge pass; only in batches
+    // that capture their iterations: launched directly, every iteration pays
+    // the fork and join as API calls and waits between hardware queues
+    // (serving loop, where other streams also step batches: p50 / p99 at
+    // 0.8x load 30 / 223 ms with one stream against 67 / 323 ms with two)
     bool side = false;
     for (const BLaunch& L : c.launches) side = side || L.lane == 1;
-    side = side && use_side(b);
+    side = side && b->graphs && use_side(b);
     bool forked = false;
     for (const BLaunch& L : c.launches) {
         const int2* map = base + L.off;

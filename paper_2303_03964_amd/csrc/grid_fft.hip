@@ -267,6 +267,13 @@ __device__ __forceinline__ int signed_offset(int r, int M, int L) {
 // RBK kernel rows make RBK transforms. Column tiles of RB (RBK) consecutive
 // rows are stored with one RB * 8-byte write per column; pairs of logical
 // blocks share an XCD so that a line is filled from fewer L2s.
+// Kernel rows per block of the spreading launch: eight, four from L = 768 on,
+// where eight rows' transforms (98 KB of LDS at L = 1536) left room for one
+// or two blocks per CU and so held back the spreading blocks of the same
+// launch, which need a fraction of that. Each row is transformed alike in
+// either tile.
+__host__ __device__ constexpr int kernel_row_tile(int L) { return L >= 768 ? 4 : 8; }
+
 template <int L>
 struct RowTile {
     // few rows per block at small L so that a 256 x 256 grid still makes
@@ -277,7 +284,7 @@ struct RowTile {
     // rows per block at short lengths (512-graph workload: 2.49e9 ->
     // 2.73e9 node-it/s with 8 rows at L <= 256; 4 and 16 rows were slower)
     static constexpr int RBB = L <= 256 ? 8 : RB;
-    static constexpr int RBK = 8;
+    static constexpr int RBK = kernel_row_tile(L);
     // a single grid at L = 512 has only M / 2 = 128 row blocks: eight waves
     // halve each thread's partial-row loads and column stores (the k = 1
     // forward row pass at N_int 256: 8.0 -> 5.7 us against four waves)
@@ -463,7 +470,7 @@ Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
     // workload: 2.29e9 -> 2.50e9 node-it/s; two waves the same, one slower)
     const int nw = b.n <= 32768 ? 4 : 8;
     const int F = fft_task_ffts(g.L);
-    const int RBK = 8;
+    const int RBK = kernel_row_tile(g.L);
     const size_t kern = ((size_t)zp_len(g.L, (RBK + F - 1) / F * F * g.L) + g.L) * sizeof(float2);  // + twiddles
     const size_t lds = per > kern ? per : kern;
     const int nkb = (g.L / 2 + 1 + RBK - 1) / RBK;  // rows 0 .. L/2
@@ -474,7 +481,6 @@ Dims spread_dims(const Bufs& b, const Geom& g, int* nw_out, int* nkb_out) {
 
 template <int K, int L>
 static void launch_spread_t(const Bufs& b, const Geom& g, float gamma, float tau, hipStream_t s) {
-    static_assert(RowTile<L>::RBK == 8, "spread_dims assumes 8 kernel rows per block");
     int nw, nkb;
     const Dims d = spread_dims(b, g, &nw, &nkb);
     hipLaunchKernelGGL((k_spread<K, L>), dim3(b.chunk_blocks + xcd_pair_grid(nkb)), dim3(d.block), d.lds, s, b, g,

@@ -131,7 +131,7 @@ inline Bufs bufs_for(const tfdp_layout* h, int k, bool batched = false) {
     // there the blocks of many graphs fill the chip, while the plain pass of
     // one graph needs a block per row for its parallelism (the grouping does
     // not change the exact sums)
-    b.rgroup = batched ? spread_row_group(k, b.n_int) : 1;
+    b.rgroup = batched ? spread_row_group(k, b.n_int, b.n) : 1;
     // grouped rows leave about max_chunks / rgroup work chunks: launch that
     // many blocks (each loops over the chunks it is given) rather than one
     // block per possible chunk

@@ -12,6 +12,7 @@ constexpr int kThreads = 256;        // threads per block of the node and FFT ke
 constexpr int kBinChunk = 2048;      // nodes per block of the binning passes
 constexpr int kSpreadChunk = 4096;   // sorted nodes per block of the spreading pass (one row's share)
 constexpr int kSpreadGroupRows = 8;  // sparse interval rows one spreading block may take together
+constexpr long long kSpreadGroupNodes = 1024;  // nodes of an average row group
 constexpr int kBoxSlots = 64;        // slots of the box extremes (one 128-byte line each)
 constexpr int kMaxL = 2048;          // largest FFT length per side
 constexpr int kMaxNInt = 1024;       // largest number of intervals per side
@@ -121,16 +122,23 @@ struct Member {
 };
 
 // Interval rows one spreading block may hold in LDS at once for k and
-// n_int: up to kSpreadGroupRows row copies of K x M x 3 64-bit sums in 48 KB.
-inline int spread_row_group(int k, int n_int) {
+// n_int: up to kSpreadGroupRows row copies of K x M x 3 64-bit sums in 48 KB,
+// and about kSpreadGroupNodes nodes for the graph's average row (n / n_int):
+// rows of a few tens to hundreds of nodes leave a block per row mostly idle,
+// while grouping rows of thousands would only take blocks from a graph that
+// has few companions in the launch.
+inline int spread_row_group(int k, int n_int, long long n) {
     const long long per = (long long)k * n_int * k * 3 * 8;
     long long cap = kSpreadGroupRows;
     if (const char* e = std::getenv("TFDP_SPREAD_GROUP_ROWS")) {  // 1 .. kSpreadGroupRows
         const long long v = std::atoll(e);
         if (v >= 1 && v <= kSpreadGroupRows) cap = v;
     }
+    const long long avg = n_int > 0 ? n / n_int : n;
+    const long long by_nodes = kSpreadGroupNodes / (avg > 1 ? avg : 1);
+    if (by_nodes < cap) cap = by_nodes;
     const long long g = per > 0 ? 49152 / per : 1;
-    return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+    return (int)(g < 1 || cap < 1 ? 1 : (g > cap ? cap : g));
 }
 
 // Slot-set parity and position buffers of iteration j of a batched call for

@@ -31,16 +31,20 @@ others are on the device join the running batch at the next chunk.
 * admission by HBM footprint: CSR + positions + workspace bytes
   (tfdp_workspace_size) must fit the budget left by the resident graphs.
 
-Admission work (uploads, handle creation) runs on a worker thread and a
-stream of its own, so that it waits neither for the chunk on the device nor
-holds up the stepping loop; the stepping stream waits for it before the new
-member's first chunk. Members whose iterations are long (an exact stage of a
-large graph, EXPENSIVE_ITERATION) are stepped as a second batch on a second
-stream, with chunks of their own length: its compute-bound exact passes run
-beside the other class's latency-bound grid passes, and neither class waits
-for the other's chunks. Each class keeps at most two chunks in flight; a
-graph that changes class, or is re-tuned, evicted or copied after a chunk
-on the other stream, is ordered after that chunk by its event. Kernels are
+Admission work (uploads, handle creation) runs on BUILD_WORKERS worker
+threads and a stream of its own, so that it waits neither for the chunk on
+the device nor holds up the stepping loop, and a large graph's handle
+(tens of milliseconds of host work) does not hold up the smaller ones behind
+it; the stepping stream waits for it before the new member's first chunk. Members are stepped in three cost classes, each a
+batch on a stream of its own with chunks of its own length: light members
+(iterations below LIGHT_ITERATION: grids of graphs up to about 1e5 nodes,
+exact stages up to about 1.4e4), the rest, and members whose iterations are
+long (an exact stage of a large graph, EXPENSIVE_ITERATION). The
+compute-bound exact passes then run beside the latency-bound grid passes,
+and a small request advances at the pace of the light class instead of that
+of every graph on the device. Each class keeps at most two chunks in flight;
+a graph that changes class, or is re-tuned, evicted or copied after a chunk
+on another stream, is ordered after that chunk by its event. Kernels are
 launched directly (no stream
 capture) in both legs, since the worker thread's GPU work runs concurrently
 with the stepping thread. Latency of a request = completion - arrival, completion
@@ -66,6 +70,8 @@ from . import tfdp as T
 BOX_LEAD = 10  # iterations between reading the box and the switch to k = 3
 CHUNK_SECONDS = 2e-3  # target device time of one chunk (admission points this far apart)
 EXPENSIVE_ITERATION = 2.5e-4  # members with longer iterations are stepped as a batch of their own
+LIGHT_ITERATION = 4.0e-5  # members with shorter ones form a class of their own (None: two classes)
+BUILD_WORKERS = 4  # worker threads creating handles (uploads, CSR check, edge schedule)
 
 
 def iteration_seconds(n: int, nnz: int, exact: bool) -> float:
@@ -183,7 +189,8 @@ class _Run:
 
 class Server:
     def __init__(self, pool, budget_bytes: int, slots: int = 256, chunk: int = 10, tol: float = 1e-3,
-                 stream=None, record_inputs: bool = False, record_outputs: bool = False, plain: bool = False):
+                 stream=None, record_inputs: bool = False, record_outputs: bool = False, plain: bool = False,
+                 workers: int = BUILD_WORKERS, light_iteration: float | None = LIGHT_ITERATION):
         import torch
         from concurrent.futures import ThreadPoolExecutor
         self.torch = torch
@@ -196,15 +203,26 @@ class Server:
         self.admit_stream = torch.cuda.Stream(device=self.stream.device)
         # one stream per cost class (default priority): the long chunks of
         # the expensive class run beside the short ones of the other
-        self.streams = [self.stream] if plain else [self.stream, torch.cuda.Stream(device=self.stream.device)]
+        # cost classes: light members (short iterations; None: no such
+        # class), the rest, and members whose iterations are long. Five runs
+        # of each load, median p50 / p99 (ms) with and without the light
+        # class: 0.8x 36 / 218 against 55 / 263, 1.2x 67 / 253 against
+        # 80 / 294 (a threshold of 3e-5 s, which moves graphs of 4e4 - 1e5
+        # nodes out of the light class, measured worse than two classes)
+        self.light_iteration = light_iteration
+        ncls = 1 if plain else (3 if light_iteration is not None else 2)
+        self.streams = [self.stream] + [torch.cuda.Stream(device=self.stream.device) for _ in range(ncls - 1)]
         # chunks in flight per class (one for the expensive class: p99 at
         # 0.8x load within run-to-run spread, at 1.2x load 595 ms against
         # 285 ms with two)
-        self.max_inflight = [2, 2]
-        # handles are created on a worker thread (uploads, the CSR check and
-        # the host-side edge schedule of tfdp_layout_init take milliseconds
-        # for large graphs; the stepping loop keeps the GPU busy meanwhile)
-        self.worker = ThreadPoolExecutor(max_workers=1)
+        self.max_inflight = [2] * ncls
+        # handles are created on worker threads (uploads, the CSR check and
+        # the host-side edge schedule of tfdp_layout_init take up to about
+        # 100 ms for the largest graphs; the stepping loop keeps the GPU busy
+        # meanwhile). With one worker, admissions under load queued behind
+        # those builds (p50 / p99 at 0.8x load 38-56 / 229-353 ms against
+        # 27-34 / 221-229 ms with four)
+        self.worker = ThreadPoolExecutor(max_workers=1 if plain else workers)
         self.graphs = OrderedDict()         # key -> _Graph (LRU order of idle use)
         self.used = 0
         self.record_inputs = record_inputs
@@ -217,7 +235,7 @@ class Server:
         # two cost classes stepped as separate batches, so that members with
         # long iterations (an exact stage of a large graph) do not hold the
         # others to their chunk length
-        self.batches = [] if plain else [T.Batch(slots, map_entries=1 << 22) for _ in range(2)]
+        self.batches = [] if plain else [T.Batch(slots, map_entries=1 << 22) for _ in range(ncls)]
         # no stream capture in the server (batches and served handles launch
         # directly, in both legs): the worker thread's uploads and handle
         # set-up run concurrently with the stepping thread, and a capture in
@@ -350,6 +368,13 @@ class Server:
                 run.g.lay.set_params(final_params(run.g.lay, run.ext.numpy(), self.tol, run.g.ws_n_int))
                 run.tuned = True
 
+    def _cost_class(self, cost: float) -> int:
+        if cost > EXPENSIVE_ITERATION:
+            return len(self.streams) - 1
+        if self.light_iteration is not None and cost > self.light_iteration:
+            return 1
+        return 0
+
     def _issue(self, active, inflight):
         """A chunk of the active runs of every cost class whose stream has
         fewer than two chunks in flight; returns the finished runs (with the
@@ -360,10 +385,10 @@ class Server:
             while q and q[0].query():
                 q.popleft()
         self._final_stage_events(active)
-        groups = ([], [])
+        groups = tuple([] for _ in self.streams)
         for run in active.values():
             cost = iteration_seconds(run.g.graph.n, run.g.graph.nnz, run.g.lay.params.k_mode == 0)
-            groups[1 if cost > EXPENSIVE_ITERATION else 0].append((run, cost))
+            groups[self._cost_class(cost)].append((run, cost))
         finished, issued = [], False
         for grp, members in enumerate(groups):
             if not members or len(inflight[grp]) >= self.max_inflight[grp]:
