@@ -267,12 +267,11 @@ __device__ __forceinline__ int signed_offset(int r, int M, int L) {
 // RBK kernel rows make RBK transforms. Column tiles of RB (RBK) consecutive
 // rows are stored with one RB * 8-byte write per column; pairs of logical
 // blocks share an XCD so that a line is filled from fewer L2s.
-// Kernel rows per block of the spreading launch: eight, four from L = 768 on,
-// where eight rows' transforms (98 KB of LDS at L = 1536) left room for one
-// or two blocks per CU and so held back the spreading blocks of the same
-// launch, which need a fraction of that. Each row is transformed alike in
-// either tile.
-__host__ __device__ constexpr int kernel_row_tile(int L) { return L >= 768 ? 4 : 8; }
+// Kernel rows per block of the spreading launch. Four rows from L = 768 on
+// (less LDS per block, so more spreading blocks per CU) measured: 1M nodes
+// k = 3 spread 54.5 -> 52.8 us, the 512-graph batch's k = 3 spread at
+// L = 768 1014 -> 1094 us (twice the kernel-row blocks); kept at eight.
+__host__ __device__ constexpr int kernel_row_tile(int) { return 8; }
 
 template <int L>
 struct RowTile {
