@@ -426,16 +426,16 @@ __device__ __forceinline__ void spread_body(const Bufs& b, const Geom& g, float 
     for (int tk = w; tk < NKT; tk += nw) wave_fft<L, false>(z + zp<L>(tk * TL), tws, lane);
     __syncthreads();
     // K and H_x are even in the row offset, so rows r and L - r of the
-    // table are equal: rows 0 .. L/2 are transformed and written to both
+    // table are equal: rows 0 .. L/2 are transformed and stored once (the
+    // column pass reads row L - r for r > L/2)
+    constexpr int KH = L / 2 + 1;
     for (int i = threadIdx.x; i < H * RBK; i += blockDim.x) {
         const int f = i % RBK, u = i / RBK;
         const int r = r0 + f;
         if (r > L / 2) continue;
         const float a = z[zp<L>(f * L + u)].x;
         const float c = z[zp<L>(f * L + (u == 0 ? 0 : L - u))].x;
-        const float2 v = make_float2(0.5f * (a + c), -0.5f * (a - c));
-        b.kcol[(size_t)u * L + r] = v;
-        if (r > 0 && r < L / 2) b.kcol[(size_t)u * L + (L - r)] = v;
+        b.kcol[(size_t)u * KH + r] = make_float2(0.5f * (a + c), -0.5f * (a - c));
     }
 }
 
@@ -678,7 +678,7 @@ __device__ __forceinline__ void colconv_body(const Bufs& b, const Geom& g, int b
         const int u = u0 + gi * F + f;
         const int a = gi * GT;
         float2 kr = make_float2(0.f, 0.f);
-        if (u < H) kr = b.kcol[(size_t)u * L + r];
+        if (u < H) kr = b.kcol[(size_t)u * (L / 2 + 1) + (r <= L / 2 ? r : L - r)];
         const int bt = signed_offset(r, M, L);
         const float e = bt != INT_MIN ? s * (float)bt * kr.x : 0.f;
         sm2[zp<L>(a + j)] = make_float2(kr.x + e, kr.y);

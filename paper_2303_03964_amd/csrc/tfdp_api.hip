@@ -130,7 +130,7 @@ Layout carve(void* base, int n, long long nnz, const tfdp_params* p, long long s
     l.b.wchunk = c.take<int4>((size_t)l.b.max_chunks + 1);
     l.b.spart = c.take<unsigned long long>((size_t)l.b.max_chunks * kw * gw.m * 3);
     l.b.qcol = c.take<float2>((size_t)3 * gw.H * gw.m);
-    l.b.kcol = c.take<float2>((size_t)gw.H * gw.L);
+    l.b.kcol = c.take<float2>((size_t)gw.H * (gw.L / 2 + 1));
     l.b.pcol = c.take<float2>((size_t)3 * gw.H * gw.m);
     l.b.pot = c.take<float4>((size_t)gw.m * gw.m);
     for (int k = 1; k <= kw; ++k) l.tw[k] = c.take<float2>((size_t)make_geom(p->n_int, k).L);

@@ -79,7 +79,7 @@ struct Bufs {
     unsigned long long* spart;  // [max_chunks][k][M][3] partial grid rows (fixed point)
     unsigned long long* sym_acc;  // [n][2] fixed-point repulsion sums of the pair-symmetric exact method (zero between passes)
     float2* qcol;        // [3][H][M] charge row spectra, column-major
-    float2* kcol;        // [H][L] kernel row spectra (K^, H_x^/i), column-major
+    float2* kcol;        // [H][L/2+1] kernel row spectra (K^, H_x^/i) of rows 0 .. L/2, column-major
     float2* pcol;        // [3][H][M] potential row spectra after the column pass
     float4* pot;         // [M][M] (phi_1, G_x, G_y, 0)
     const float2* tw;    // twiddles for this L: exp(-2 pi i j / L), j < L
