@@ -38,6 +38,30 @@ def test_box_side():
     assert autotune.box_side(p) == pytest.approx(3.0)
 
 
+def test_box_sides_equal_box_side_per_layout():
+    # the one-reduction widths of many layouts equal box_side of each: rows
+    # with a non-finite coordinate left out, a layout without a finite row
+    # 1.0, a single row (zero extent) 1e-6
+    import torch
+    rng = np.random.default_rng(3)
+    parts = []
+    for i in range(40):
+        n = int(rng.integers(1, 60))
+        p = (rng.standard_normal((n, 2)) * rng.uniform(0.01, 500)).astype(np.float32)
+        if i % 7 == 3:
+            p[rng.integers(0, n)] = (np.nan, 1.0)
+        if i % 11 == 5:
+            p[rng.integers(0, n), 1] = np.inf
+        if i == 20:
+            p[:] = np.nan
+        parts.append(torch.from_numpy(p))
+    parts.append(torch.zeros((1, 2)))
+    got = autotune.box_sides(parts)
+    want = [autotune.box_side(p) for p in parts]
+    assert got.tolist() == want
+    assert got[20] == 1.0 and got[-1] == 1e-6
+
+
 @pytest.mark.parametrize("index,gamma", [(1, 2.0), (11, 2.0), (13, 2.0), (1, 4.0), (1, 1.5)])
 def test_error_model_against_oracle(index, gamma):
     """Lay out a batch-workload graph with the oracle (gamma = 2), pick the
