@@ -258,14 +258,16 @@ tfdp_status build_slices(tfdp_layout* h, hipStream_t stream) {
     const int n = h->n;
     const long long nnz = h->nnz;
     Layout& l = h->lay;
+    // copies ordered on the caller's stream
     std::vector<int> rp((size_t)n + 1);
-    tfdp_status st = check_hip(hipMemcpy(rp.data(), h->row_ptr, rp.size() * sizeof(int), hipMemcpyDeviceToHost),
-                               "hipMemcpy");
+    tfdp_status st = check_hip(hipMemcpyAsync(rp.data(), h->row_ptr, rp.size() * sizeof(int),
+                                              hipMemcpyDeviceToHost, stream), "hipMemcpyAsync");
     if (st != TFDP_OK) return st;
     std::vector<int> ci((size_t)nnz);
     if (nnz > 0)
-        st = check_hip(hipMemcpy(ci.data(), h->col_idx, ci.size() * sizeof(int), hipMemcpyDeviceToHost),
-                       "hipMemcpy");
+        st = check_hip(hipMemcpyAsync(ci.data(), h->col_idx, ci.size() * sizeof(int), hipMemcpyDeviceToHost,
+                                      stream), "hipMemcpyAsync");
+    if (st == TFDP_OK) st = check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
     if (st != TFDP_OK) return st;
     const int S = l.nslices;
     const long long W = ((long long)n + S - 1) / S;
@@ -895,11 +897,14 @@ tfdp_status tfdp_layout_sync_status(tfdp_layout* h, hipStream_t s) {
     if (st != TFDP_OK) return st;
     int flag = 0;
     DevState* dst = h->lay.b.st;
-    st = check_hip(hipMemcpy(&flag, &dst->nonfinite, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy");
+    st = check_hip(hipMemcpyAsync(&flag, &dst->nonfinite, sizeof(int), hipMemcpyDeviceToHost, s),
+                   "hipMemcpyAsync");
+    if (st == TFDP_OK) st = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (st != TFDP_OK) return st;
     if (flag) {
         int zero = 0;
-        (void)hipMemcpy(&dst->nonfinite, &zero, sizeof(int), hipMemcpyHostToDevice);
+        (void)hipMemcpyAsync(&dst->nonfinite, &zero, sizeof(int), hipMemcpyHostToDevice, s);
+        (void)hipStreamSynchronize(s);
         set_msg("a position became NaN or infinite");
         return TFDP_ERR_NONFINITE;
     }

@@ -328,9 +328,12 @@ class Server:
         for st in self.streams:
             st.wait_stream(self.admit_stream)
             if g.last_ev is not None and g.last_stream is not st:
-                st.wait_event(g.last_ev)  # a re-tune after a chunk on the other stream
+                st.wait_event(g.last_ev)  # a re-tune after a chunk on another stream
         if self.record_inputs:
-            rec.start_pos = g.lay.pos.clone()
+            rec.start_pos = g.lay.pos.clone()  # on self.stream
+            copied = torch.cuda.Event()
+            copied.record(self.stream)
+            g.last_ev, g.last_stream = copied, self.stream  # the first chunk waits for the copy
         run = _Run(g, rec, req.iters)
         run.group = -1
         active[req.rid] = run
@@ -342,6 +345,13 @@ class Server:
         if self.record_outputs:
             with self.torch.cuda.stream(stream):
                 rec.final_pos = run.g.lay.pos.clone()
+                # the graph's next run (a re-tune, possibly on another
+                # stream) waits for this copy, not only for the chunk
+                # before it: otherwise its first chunk could move the
+                # positions while they are being copied
+                copied = self.torch.cuda.Event()
+                copied.record(stream)
+            run.g.last_ev, run.g.last_stream = copied, stream
         if not self.plain and run.group >= 0:
             self.batches[run.group].remove(run.g.lay)
         run.g.busy = False
@@ -389,17 +399,23 @@ class Server:
         for run in active.values():
             cost = iteration_seconds(run.g.graph.n, run.g.graph.nnz, run.g.lay.params.k_mode == 0)
             groups[self._cost_class(cost)].append((run, cost))
-        finished, issued = [], False
+        # every member into the batch of its class first: a batch steps all
+        # its slots, so a graph whose class changed (its last stage chosen)
+        # must have left its old batch before that batch steps again, or it
+        # would be stepped twice in one round
         for grp, members in enumerate(groups):
-            if not members or len(inflight[grp]) >= self.max_inflight[grp]:
-                continue
-            stream = self.streams[grp]
             for run, _ in members:
                 if run.group != grp:
                     if run.group >= 0:
                         self.batches[run.group].remove(run.g.lay)
                     self.batches[grp].add(run.g.lay)
                     run.group = grp
+        finished, issued = [], False
+        for grp, members in enumerate(groups):
+            if not members or len(inflight[grp]) >= self.max_inflight[grp]:
+                continue
+            stream = self.streams[grp]
+            for run, _ in members:
                 g = run.g
                 # a graph last stepped on the other stream (class change,
                 # or a re-tune after a request of the other class)
