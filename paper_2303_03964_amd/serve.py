@@ -35,8 +35,9 @@ Admission work (uploads, handle creation) runs on BUILD_WORKERS worker
 threads and a stream of its own, so that it waits neither for the chunk on
 the device nor holds up the stepping loop, and a large graph's handle
 (tens of milliseconds of host work) does not hold up the smaller ones behind
-it; the stepping stream waits for it before the new member's first chunk. Members are stepped in three cost classes, each a
-batch on a stream of its own with chunks of its own length: light members
+it; the stepping stream waits for it before the new member's first chunk.
+Members are stepped in three cost classes, each a batch on a stream of its
+own with chunks of its own length: light members
 (iterations below LIGHT_ITERATION: grids of graphs up to about 1e5 nodes,
 exact stages up to about 1.4e4), the rest, and members whose iterations are
 long (an exact stage of a large graph, EXPENSIVE_ITERATION). The
@@ -201,9 +202,9 @@ class Server:
         self.tol = tol
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.admit_stream = torch.cuda.Stream(device=self.stream.device)
-        # one stream per cost class (default priority): the long chunks of
-        # the expensive class run beside the short ones of the other
-        # cost classes: light members (short iterations; None: no such
+        # one stream per cost class (default priority), so that the long
+        # chunks of one class run beside the short ones of another. Classes:
+        # light members (short iterations; None: no such
         # class), the rest, and members whose iterations are long. Five runs
         # of each load, median p50 / p99 (ms) with and without the light
         # class: 0.8x 36 / 218 against 55 / 263, 1.2x 67 / 253 against
@@ -232,9 +233,9 @@ class Server:
         self.plain = plain
         if plain:
             self.slots = 1
-        # two cost classes stepped as separate batches, so that members with
-        # long iterations (an exact stage of a large graph) do not hold the
-        # others to their chunk length
+        # the cost classes are stepped as separate batches, so that members
+        # with long iterations (an exact stage of a large graph) do not hold
+        # the others to their chunk length
         self.batches = [] if plain else [T.Batch(slots, map_entries=1 << 22) for _ in range(ncls)]
         # no stream capture in the server (batches and served handles launch
         # directly, in both legs): the worker thread's uploads and handle
