@@ -362,9 +362,9 @@ int32_t tfdp_batch_count(const tfdp_batch* b);
 tfdp_status tfdp_batch_step(tfdp_batch* b, int32_t iters, hipStream_t stream);
 /* Tile schedule of the batched grid passes for one FFT length (64, 128, ...,
  * 2048): rows per block of the row FFT passes (2, 4 or 8) and column groups
- * per block of the column pass (1 or 2), selectable for lengths up to 512 (a
+ * per block of the column pass (1 or 2), selectable for lengths up to 768 (a
  * fixed tile above); 0 selects the default (8 rows up to length 256, 2
- * groups at 256). Tiles change only how the work is cut into blocks: every
+ * groups at 256, 4 rows and 1 group at 768). Tiles change only how the work is cut into blocks: every
  * tile gives bit-identical results. The project's autotuner times the
  * candidates on a batch and keeps the fastest per length. Changing a tile
  * synchronises `stream` (the batch's maps are rebuilt).

@@ -255,7 +255,7 @@ def calibrate(T, layouts, n_ints=(16, 24, 32, 48, 64, 96), ks=(1, 2, 3)):
 
 
 TILE_CANDIDATES = [(r, g) for r in (2, 4, 8) for g in (1, 2)]
-TUNABLE_LENGTHS = (64, 128, 256, 384, 512)
+TUNABLE_LENGTHS = (64, 128, 256, 384, 512, 768)
 
 
 def k_of(params, t: int) -> int:

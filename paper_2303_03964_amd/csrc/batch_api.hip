@@ -529,7 +529,7 @@ tfdp_status tfdp_batch_set_tiles(tfdp_batch* b, int32_t fft_length, int32_t rows
     const int rows = rows_per_block > 0 ? rows_per_block : batch_rows_default(fft_length);
     const int groups = column_groups > 0 ? column_groups : batch_groups_default(fft_length);
     if (!batch_tile_valid(fft_length, rows, groups)) {
-        set_msg("tile not available for this FFT length (rows 2, 4, 8 and column groups 1, 2 up to length 512; "
+        set_msg("tile not available for this FFT length (rows 2, 4, 8 and column groups 1, 2 up to length 768; "
                 "the default tile above)");
         return TFDP_ERR_UNSUPPORTED;
     }

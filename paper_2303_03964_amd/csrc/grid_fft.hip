@@ -267,6 +267,11 @@ __device__ __forceinline__ int signed_offset(int r, int M, int L) {
 // RBK kernel rows make RBK transforms. Column tiles of RB (RBK) consecutive
 // rows are stored with one RB * 8-byte write per column; pairs of logical
 // blocks share an XCD so that a line is filled from fewer L2s.
+// Longest FFT length whose batched tiles the autotuner may choose (rows per
+// block 2, 4, 8; column groups 1, 2); longer lengths keep RowTile<L>::RBB
+// and col_groups(L, true).
+constexpr int kMaxTunedL = 768;
+
 // Kernel rows per block of the spreading launch. Four rows from L = 768 on
 // (less LDS per block, so more spreading blocks per CU) measured: 1M nodes
 // k = 3 spread 54.5 -> 52.8 us, the 512-graph batch's k = 3 spread at
@@ -603,7 +608,7 @@ __global__ __launch_bounds__(RowTile<L>::THREADS) void k_rowfft(Bufs b, Geom g, 
 }
 
 // Batched row passes take RB rows per block from the batch's tile schedule
-// (tfdp_batch_set_tiles, chosen by the autotuner): 2, 4 or 8 at L <= 512,
+// (tfdp_batch_set_tiles, chosen by the autotuner): 2, 4 or 8 at L <= 768,
 // RowTile<L>::RBB above. The transforms, their pairing of rows and every
 // sum do not depend on RB, so all tiles give bit-identical results.
 template <int L, int RB>
@@ -727,7 +732,7 @@ __global__ __launch_bounds__(512) void k_colconv(Bufs b, Geom g) {
 }
 
 // Batched column passes take G column groups per block from the batch's
-// tile schedule (1 or 2 at L <= 512; col_groups(L, true) above); each column
+// tile schedule (1 or 2 at L <= 768; col_groups(L, true) above); each column
 // is transformed alike in either, so the results are bit-identical.
 template <int L, int G>
 __global__ __launch_bounds__(512) void kb_colconv(const Member* __restrict__ mem, const int2* __restrict__ map) {
@@ -858,14 +863,14 @@ int batch_rows_default(int L) {
 int batch_groups_default(int L) { return col_groups(L, true); }
 
 bool batch_tile_valid(int L, int rows, int groups) {
-    if (L > 512) return rows == batch_rows_default(L) && groups == batch_groups_default(L);
+    if (L > kMaxTunedL) return rows == batch_rows_default(L) && groups == batch_groups_default(L);
     return (rows == 2 || rows == 4 || rows == 8) && (groups == 1 || groups == 2);
 }
 
 // Launch of a batched row pass (kernel template K) with `rows` rows per block.
 #define TFDP_ROWPASS_LAUNCH(KERN, LG, rows, d, blocks, s, mem, map)                                             \
     do {                                                                                                        \
-        if constexpr (LG <= 512) {                                                                              \
+        if constexpr (LG <= kMaxTunedL) {                                                                       \
             if ((rows) == 2)                                                                                    \
                 hipLaunchKernelGGL((KERN<LG, 2>), dim3(blocks), dim3((d).block), (d).lds, s, mem, map);        \
             else if ((rows) == 4)                                                                               \
@@ -898,7 +903,7 @@ template <int L>
 static void launch_b_colconv_t(int groups, const Member* mem, const int2* map, int blocks, hipStream_t s) {
     const Geom g{1, 1, L, L / 2 + 1, 1};
     const Dims d = colconv_dims(g, groups);
-    if constexpr (L <= 512) {
+    if constexpr (L <= kMaxTunedL) {
         if (groups == 2)
             hipLaunchKernelGGL((kb_colconv<L, 2>), dim3(blocks), dim3(d.block), d.lds, s, mem, map);
         else
@@ -943,7 +948,7 @@ static void allow_big_lds_all_l() {
     allow_big_lds(kb_spread<1, L>);
     allow_big_lds(kb_spread<2, L>);
     allow_big_lds(kb_spread<3, L>);
-    if constexpr (L <= 512) {
+    if constexpr (L <= kMaxTunedL) {
         allow_big_lds(kb_rowfft<L, 2>);
         allow_big_lds(kb_rowfft<L, 4>);
         allow_big_lds(kb_rowfft<L, 8>);
