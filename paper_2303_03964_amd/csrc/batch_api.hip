@@ -252,10 +252,12 @@ void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<in
     }
     // The grid passes of different FFT lengths are independent chains: all
     // but the length with the most blocks run on the second stream, between
-    // the binning and the edge pass. (The exact-method launches stay on the
-    // first stream after the edge pass: beside the FFT passes their
+    // the binning and the edge pass. (The pair-symmetric exact launches stay
+    // on the first stream after the edge pass: beside the FFT passes their
     // arithmetic-bound blocks slowed those latency-bound ones more than they
-    // gained, size-rule grids 3.17e9 -> 2.76e9 node-it/s.)
+    // gained, size-rule grids 3.17e9 -> 2.76e9 node-it/s. The small exact
+    // members' one launch, about 27 us at k = 1, does go to the second
+    // stream below: 3.68e9 -> 3.77e9.)
     {
         std::map<int, long long> work;
         for (const BLaunch& L : c.launches)
@@ -273,6 +275,29 @@ void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<in
                 L.len != main_len)
                 L.lane = 1;
     }
+    // exact method, split by size: the one-launch kernel for the small
+    // members, the pair-symmetric passes for the others
+    std::vector<int> small, big, bs, bp, bn;
+    for (int i : brute) {
+        if (use_sym(H(i)->n)) {
+            big.push_back(i);
+            bp.push_back((int)sym_pair_blocks(H(i)->n));
+            bn.push_back(sym_node_blocks(H(i)->n));
+        } else {
+            small.push_back(i);
+            bs.push_back((H(i)->n + kBruteRows - 1) / kBruteRows);
+        }
+    }
+    // the small exact members need no grid: with a second stream in use
+    // their launch runs there, after the shorter grid chains and before the
+    // join, instead of on the longer chain's stream
+    {
+        bool side = false;
+        for (const BLaunch& L : c.launches) side = side || L.lane == 1;
+        const size_t at = c.launches.size();
+        emit(B_BRUTE, 0, 0, 0, 0, small, bs);
+        if (side && c.launches.size() > at) c.launches.back().lane = 1;
+    }
     // edge pass + gather + move: classes by k
     {
         std::map<int, std::vector<int>> cls;
@@ -283,21 +308,8 @@ void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<in
             emit(B_EDGES, kv.first, 0, 0, 0, kv.second, blocks);
         }
     }
-    // exact method: the one-launch kernel for the small members, the
-    // pair-symmetric passes for the others, then every such member's counter
+    // the pair-symmetric passes, then every exact member's counter
     if (!brute.empty()) {
-        std::vector<int> small, big, bs, bp, bn;
-        for (int i : brute) {
-            if (use_sym(H(i)->n)) {
-                big.push_back(i);
-                bp.push_back((int)sym_pair_blocks(H(i)->n));
-                bn.push_back(sym_node_blocks(H(i)->n));
-            } else {
-                small.push_back(i);
-                bs.push_back((H(i)->n + kBruteRows - 1) / kBruteRows);
-            }
-        }
-        emit(B_BRUTE, 0, 0, 0, 0, small, bs);
         emit(B_SYM_PAIRS, 0, 0, 0, 0, big, bp);
         emit(B_SYM_NODE, 0, 0, 0, 0, big, bn);
         BLaunch L{B_TICK, 0, 0, 0, map.size(), 0, 0};
