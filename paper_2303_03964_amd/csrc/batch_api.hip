@@ -291,12 +291,22 @@ void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<in
     // the small exact members need no grid: with a second stream in use
     // their launch runs there, after the shorter grid chains and before the
     // join, instead of on the longer chain's stream
+    // (with their counters' advance behind them on the same stream)
+    auto emit_tick = [&](const std::vector<int>& who, int lane) {
+        if (who.empty()) return;
+        BLaunch L{B_TICK, 0, 0, 0, map.size(), 0, 0};
+        for (int i : who) map.push_back(make_int2(entry_of(act[i], 1), 0));
+        L.blocks = (int)who.size();
+        L.lane = lane;
+        c.launches.push_back(L);
+    };
     {
         bool side = false;
         for (const BLaunch& L : c.launches) side = side || L.lane == 1;
         const size_t at = c.launches.size();
         emit(B_BRUTE, 0, 0, 0, 0, small, bs);
         if (side && c.launches.size() > at) c.launches.back().lane = 1;
+        emit_tick(small, side ? 1 : 0);
     }
     // edge pass + gather + move: classes by k
     {
@@ -308,14 +318,11 @@ void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<in
             emit(B_EDGES, kv.first, 0, 0, 0, kv.second, blocks);
         }
     }
-    // the pair-symmetric passes, then every exact member's counter
-    if (!brute.empty()) {
+    // the pair-symmetric passes, then their members' counters
+    if (!big.empty()) {
         emit(B_SYM_PAIRS, 0, 0, 0, 0, big, bp);
         emit(B_SYM_NODE, 0, 0, 0, 0, big, bn);
-        BLaunch L{B_TICK, 0, 0, 0, map.size(), 0, 0};
-        for (int i : brute) map.push_back(make_int2(entry_of(act[i], 1), 0));
-        L.blocks = (int)brute.size();
-        c.launches.push_back(L);
+        emit_tick(big, 0);
     }
     // call-level maps: a box-begin block per member, box-reduce blocks, copy blocks
     c.box_begin = (int)map.size();
