@@ -258,12 +258,12 @@ void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<in
     // gained, size-rule grids 3.17e9 -> 2.76e9 node-it/s. The small exact
     // members' one launch, about 27 us at k = 1, does go to the second
     // stream below: 3.68e9 -> 3.77e9.)
+    int main_len = 0;
     {
         std::map<int, long long> work;
         for (const BLaunch& L : c.launches)
             if (L.phase == B_SPREAD || L.phase == B_ROWFFT || L.phase == B_COLCONV || L.phase == B_ROWIFFT)
                 work[L.len] += L.blocks;
-        int main_len = 0;
         long long most = -1;
         for (auto& kv : work)
             if (kv.second > most) {
@@ -308,14 +308,23 @@ void build_comp(tfdp_batch* b, const std::vector<int>& act, const std::vector<in
         if (side && c.launches.size() > at) c.launches.back().lane = 1;
         emit_tick(small, side ? 1 : 0);
     }
-    // edge pass + gather + move: classes by k
+    // edge pass + gather + move: classes by k, and by stream: the members of
+    // the second stream's grid chains take theirs there too, before the
+    // join, so that only the longer chain's members are left after it
     {
-        std::map<int, std::vector<int>> cls;
-        for (int i : order) cls[ks[i]].push_back(i);
+        bool side = false;
+        for (const BLaunch& L : c.launches) side = side || L.lane == 1;
+        std::map<std::pair<int, int>, std::vector<int>> cls;  // (lane, k): lane 1 first
+        for (int i : order) {
+            const int lane = side && make_geom(H(i)->p.n_int, ks[i]).L != main_len ? 1 : 0;
+            cls[std::make_pair(-lane, ks[i])].push_back(i);
+        }
         for (auto& kv : cls) {
             std::vector<int> blocks;
             for (int i : kv.second) blocks.push_back(H(i)->lay.slice[0].blocks);
-            emit(B_EDGES, kv.first, 0, 0, 0, kv.second, blocks);
+            const size_t at = c.launches.size();
+            emit(B_EDGES, kv.first.second, 0, 0, 0, kv.second, blocks);
+            if (c.launches.size() > at) c.launches.back().lane = -kv.first.first;
         }
     }
     // the pair-symmetric passes, then their members' counters
@@ -433,12 +442,12 @@ void enqueue_iter(tfdp_batch* b, const Comp& c, int j, hipStream_t s) {
     for (const BLaunch& L : c.launches) {
         const int2* map = base + L.off;
         const bool bin = L.phase == B_BIN_COUNT || L.phase == B_BIN_SCAN || L.phase == B_BIN_SCATTER;
-        if (side && !forked && !bin && L.phase != B_EDGES) {
+        if (side && !forked && !bin && !(L.phase == B_EDGES && L.lane == 0)) {
             (void)hipEventRecord(b->ev_fork, s);
             (void)hipStreamWaitEvent(b->side, b->ev_fork, 0);
             forked = true;
         }
-        if (forked && L.phase == B_EDGES) {  // the edge pass needs every grid
+        if (forked && L.phase == B_EDGES && L.lane == 0) {  // the edge pass needs every grid
             (void)hipEventRecord(b->ev_join, b->side);
             (void)hipStreamWaitEvent(s, b->ev_join, 0);
             forked = false;
