@@ -318,9 +318,11 @@ tfdp_status tfdp_quality_sampled_noalloc(int32_t n, int64_t nnz, const int32_t* 
  * entries per member (8 bytes each; the constant covers the largest grid).
  * While graphs are enabled (tfdp_batch_set_graphs), at its first step the
  * batch creates a second stream and two events on the device that was
- * current at tfdp_batch_create (no device memory): the grid passes of all
- * but the largest FFT length run there, between the binning and the edge
- * pass of each iteration; the call is still ordered on `stream` as a whole.
+ * current at tfdp_batch_create (no device memory): the grid passes and the
+ * edge pass of the members of all but the FFT length with the most blocks,
+ * and the one-launch exact kernel of the small exact members, run there,
+ * between the binning and the edge pass of the other members in each
+ * iteration; the call is still ordered on `stream` as a whole.
  * With graphs disabled every launch stays on `stream`. tfdp_batch_destroy
  * releases them.
  * Adding, removing or re-tuning members costs no synchronisation: the new
