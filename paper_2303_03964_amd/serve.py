@@ -403,7 +403,7 @@ class Server:
         # every member into the batch of its class first: a batch steps all
         # its slots, so a graph whose class changed (its last stage chosen)
         # must have left its old batch before that batch steps again, or it
-        # would be stepped twice in one round
+        # would be stepped twice in one pass of the loop
         for grp, members in enumerate(groups):
             for run, _ in members:
                 if run.group != grp:

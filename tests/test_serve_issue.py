@@ -1,7 +1,7 @@
 """Host logic of the serving loop's chunk issue (no GPU): a batch steps every
 graph in its slots, so a graph whose cost class changed (its last stage was
 just chosen) must leave its old batch before that batch steps again;
-otherwise it is stepped twice in one round and its layout depends on when
+otherwise it is stepped twice in one pass of the loop and its layout depends on when
 the other class had room for a chunk."""
 from collections import deque
 from types import SimpleNamespace
